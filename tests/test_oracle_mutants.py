@@ -1,0 +1,56 @@
+"""Plants plausible mistakes in a copy of the oracle source (on the CPU) and checks that the
+oracle pins catch every one: a dropped or doubled term, a wrong sign, a wrong tensor index,
+a wrong ghost source, a missing direction.  Each mutant is compiled with gcc into a temporary
+directory and the pin module is run against it in a child process."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = [
+    ("0.5 * C * (ER - EL);", "0.5 * C * (EL - ER);"),
+    ("0.5 * C * (ER - EL);", "1.0 * C * (ER - EL);"),
+    ("phi[0] = 0.5 * (x[1 + d][L] + x[1 + d][R])", "phi[0] = 0.5 * (x[1 + (d + 1) % 3][L] + x[1 + d][R])"),
+    ("(fdj[L] * EL + fdj[R] * ER)", "(fdj[L] * EL + fdj[L] * ER)"),
+    ("0.5 * c2 * (fdj[L]", "0.5 * g->c * (fdj[L]"),
+    ("- 0.5 * C * (x[1 + j][R] - x[1 + j][L]);", "- 0.5 * C * (x[1 + d][R] - x[1 + d][L]);"),
+    ("if (a == 0 && b == 2) return 4;", "if (a == 0 && b == 2) return 5;"),
+    ("return q * q / (2.0 * fdd);", "return q * q / fdd;"),
+    ("double fc = fL > fR ? fL : fR;", "double fc = fL < fR ? fL : fR;"),
+    ("double tau = 0.5 * (cell_tau(g, sigL, fL) + cell_tau(g, sigR, fR));", "double tau = cell_tau(g, sigL, fL);"),
+    ("corr = sqrt(-expm1(-tau) / tau);", "corr = -expm1(-tau) / tau;"),
+    ("double diag = (q == 0) ? dE[c] : 1.0 + sR;", "double diag = (q == 0) ? dE[c] : 1.0;"),
+    ("R[0][c] += -En[c] - sP * g->aR * T4;", "R[0][c] += -En[c] + sP * g->aR * T4;"),
+    ("+ sP * (g->aR * T4 - E[c]);", "+ sP * (g->aR * T4 - 0.5 * E[c]);"),
+    ("- 3.0 * (1.0 - eta) * sP * g->aR * Ts4;", "- 2.0 * (1.0 - eta) * sP * g->aR * Ts4;"),
+    ("o.dE[c] = 1.0 + sP * (1.0 - eta);", "o.dE[c] = 1.0 + sP;"),
+    ("double gv = alpha * (T - Tn) + sP * (aR * T3 * T - E);", "double gv = alpha * (T - Tn) + sP * (aR * T3 - E);"),
+    ("src[d] = side ? 0 : n[d] - 1;", "src[d] = side ? 1 : n[d] - 1;"),
+    ("src[d] = side ? n[d] - 1 : 0;", "src[d] = side ? n[d] - 2 : 0;"),
+    ("return g->c * g->dt * sigma_R(cf, i); }", "return g->dt * sigma_R(cf, i); }"),
+    ("return cf->rho[i] * g->cv; }", "return g->cv; }"),
+    ("double q = 10.0 * g->h * sigR;", "double q = 10.0 * sigR;"),
+    ("for (int d = 0; d < 3; ++d) div +=", "for (int d = 0; d < 2; ++d) div +="),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", range(len(MUTANTS)))
+def test_pins_catch_planted_mistake(k, tmp_path):
+    before, after = MUTANTS[k]
+    src = open(SRC).read()
+    assert before in src, before
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(before, after, 1))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-I", os.path.join(ROOT, "oracle"),
+                    "-o", str(so), str(path), "-lm"], check=True)
+    env = dict(os.environ, VETTAM_ORACLE_SO=str(so), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-x", "-q", "-p", "no:cacheprovider"], env=env, capture_output=True, text=True,
+                       cwd=ROOT, timeout=600)
+    assert r.returncode != 0, f"mutant survived: {after}"
