@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: implicit VET radiation step, cell-updates/s at 256^3, mixed precision vs FP64.
+
+Workload: the mixed-depth medium at 256^3 (lognormal density sigma 1.5, cell optical depth
+log-uniform over 1e-3..1e3 and spatially correlated, random SPD unit-trace Eddington tensor,
+central Gaussian source in E, T = 0.1, dt = 50 light-crossing times, periodic faces, FP32-exact
+inputs), 5 implicit steps.  A "step" is one rad_step call (the whole hot path: coefficient
+setup, Picard iterations of FP64 residual, Krylov solve, exchange solve, commit).
+
+The timed region starts with every input resident in HBM.  Both paths start from the same
+initial state.  Printed: one JSON line with the mixed-path throughput as `value`, the FP64
+path's throughput and the speedup, the error between the two and the oracle's residual of
+the mixed result, the roofline of the dominant kernel measured live with HIP events, and the
+FP64 CPU oracle timed on a bounded sample of the same recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "implicit VET rad-step cell-updates/s at 256^3; mixed vs FP64 speedup"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile):
+    """Warm up, restore the initial state, then time `steps` consecutive rad_step calls."""
+    E, F, T = (t.clone() for t in state0)
+    rho, kP, kR, f = coefs
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol)
+    p.coef_dtype = 1 if rho.dtype == torch.float32 else 0
+    ws = rad.alloc_workspace(rad.workspace_bytes(E.shape, p))
+    for s in range(warmup):
+        st = rad.rad_step(E, F, T, rho, kP, kR, f, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
+        log(f"  [{prec}] warmup step {s}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
+            f"{st['t_total_ms']:.0f} ms, res {st['scaled_residual']:.2e}")
+    for dst, src in zip((E, F, T), state0):
+        dst.copy_(src)
+    prev = None
+    stats = []
+    rad.profile(profile)
+    rad.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        if s == steps - 1:
+            prev = (E.clone(), F.clone(), T.clone())
+        st = rad.rad_step(E, F, T, rho, kP, kR, f, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
+        stats.append(st)
+        log(f"  [{prec}] step {s}: rc {st['rc']}, {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
+            f"{st['refine_sweeps']} FP64 residuals, {st['t_total_ms']:.0f} ms, res {st['scaled_residual']:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = rad.profile_read() if profile else {}
+    rad.profile(False)
+    del ws
+    return dict(seconds=t1 - t0, stats=stats, state=(E, F, T), prev=prev, profile=prof)
+
+
+def relerr(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cpu_baseline(n_sample, tol):
+    """FP64 oracle on the same recipe at n_sample^3 (periodic), one step, timed on the host cores."""
+    import oracle
+    from paper_2202_08778_amd import workloads as W
+    d = W.mixed_depth(n=n_sample, seed=3, steps=1, fp32_exact=True)
+    P = oracle.Problem(d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"], c=d["c"], aR=d["aR"],
+                       cv=d["cv"])
+    t0 = time.perf_counter()
+    _, _, _, st = P.step(d["E"], d["F"], d["T"], tol=tol, allow_unconverged=True)
+    sec = time.perf_counter() - t0
+    cells = n_sample ** 3
+    return {"value": cells / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"mixed-depth recipe at {n_sample}^3 (same generator, periodic, FP32-exact), 1 step, "
+                      f"tol {tol:g}: {sec:.1f} s, {st['picard_iters']} Picard / {st['krylov_iters']} Krylov "
+                      f"iterations, converged={st['converged']}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid edge (the metric is quoted at 256)")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=24)
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (one GPU's share is "
+              "the kernel at its real shape; see DESIGN.md for how the step would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2202_08778_amd import rad
+    from paper_2202_08778_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.n
+    log(f"generating the mixed-depth workload at {n}^3 ...")
+    d = W.mixed_depth_256(n=n, steps=args.steps)
+    dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
+    state0 = (dev(d["E"]), dev(d["F"]), dev(d["T"]))
+    c32 = tuple(dev(d[k], torch.float32) for k in ("rho", "kP", "kR", "f"))
+    N = n ** 3
+
+    log("mixed path (FP32 Krylov + FP64 residual/refinement/exchange, FP32 coefficient storage):")
+    mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile)
+    value = N * args.steps / mixed["seconds"]
+    out_m = [t.cpu().numpy() for t in mixed["state"]]
+
+    fp64 = None
+    if not args.no_fp64:
+        log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
+        c64 = tuple(dev(d[k]) for k in ("rho", "kP", "kR", "f"))
+        fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False)
+        del c64
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * mixed["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"mixed-depth medium {n}^3, periodic, dt = 50 light-crossing times, "
+                               f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
+                   "cells": N, "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
+        "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
+        "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / args.steps,
+        "converged_steps": sum(1 for s in mixed["stats"] if s["rc"] == 0),
+        "final_scaled_residual": mixed["stats"][-1]["scaled_residual"],
+    }
+    if fp64 is not None:
+        v64 = N * args.steps / fp64["seconds"]
+        out_d = [t.cpu().numpy() for t in fp64["state"]]
+        res["fp64_value"] = v64
+        res["fp64_ms_per_step"] = 1000.0 * fp64["seconds"] / args.steps
+        res["speedup_mixed_vs_fp64"] = value / v64
+        res["fp64_krylov_iters_per_step"] = sum(s["krylov_iters"] for s in fp64["stats"]) / args.steps
+        res["fp64_converged_steps"] = sum(1 for s in fp64["stats"] if s["rc"] == 0)
+        res["relerr_mixed_vs_fp64"] = {k: relerr(a, b) for k, a, b in zip(("E", "F", "T"), out_m, out_d)}
+
+    if not args.no_oracle_check:
+        import oracle
+        log("oracle residual of the mixed result (last step) ...")
+        P = oracle.Problem(d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"], c=d["c"], aR=d["aR"],
+                           cv=d["cv"])
+        prev = [t.cpu().numpy() for t in mixed["prev"]]
+        r = P.scaled_residual(*prev, *out_m)
+        res["oracle_scaled_residual_last_step"] = r[3]
+
+    prof = mixed["profile"]
+    if prof:
+        dom = max(prof, key=lambda k: prof[k]["ms"])
+        e = prof[dom]
+        gbs = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+        res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": 1000.0 * e["ms"] / e["launches"], "launches": e["launches"]}
+        res["kernel_time_share"] = {k: v["ms"] / (mixed["seconds"] * 1e3) for k, v in
+                                    sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+        res["kernel_gbs"] = {k: v["bytes"] / (v["ms"] * 1e-3) / 1e9 for k, v in prof.items() if v["ms"] > 0}
+
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline at {args.cpu_sample_n}^3 ...")
+        res["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.tol)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

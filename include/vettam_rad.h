@@ -1,0 +1,200 @@
+/*
+ * vettam_rad.h -- C ABI of the MI355X implicit VET radiation step library.
+ *
+ * The library advances the gray two-moment radiation equations (E, F) and the
+ * gas temperature T by one fully implicit backward-Euler step, as the
+ * implicit subsystem of Menon et al. 2022 (VETTAM), Sec. 2.3.2 eq.
+ * implicit1-3 with the gas velocity set to zero:
+ *
+ *   (1 + sP) E - E_n - sP aR T^4 + (dt/h) sum_d (PhiE_{i+1/2} - PhiE_{i-1/2}) = 0
+ *   (1 + sR) F - F_n             + (dt/h) sum_d (PhiF_{i+1/2} - PhiF_{i-1/2}) = 0
+ *   alpha (T - T_n) + sP (aR T^4 - E)                                       = 0
+ *
+ * sP = c dt rho kappa_P, sR = c dt rho kappa_R, alpha = rho c_v.  The face
+ * fluxes are first-order Godunov HLLE fluxes (Sec. 2.3.3) closed by the
+ * per-cell variable Eddington tensor f_ij (eq. closure), with the
+ * optical-depth wave-speed correction of eq. taucorrect and the same-level
+ * interface rule of eq. wavespeedtau:
+ *   PhiE   = (F_d,L + F_d,R)/2 - C (E_R - E_L)/2
+ *   PhiF_j = c^2 (f_dj,L E_L + f_dj,R E_R)/2 - C (F_j,R - F_j,L)/2
+ *   C = c sqrt(max(f_dd,L, f_dd,R)) sqrt((1 - exp(-tau))/tau),
+ *   tau = (tau_L + tau_R)/2,  tau_cell = (10 h rho kappa_R)^2 / (2 f_dd).
+ * The nonlinear system is solved by the Picard iteration of Sec. 2.3.4
+ * (radiation solve at a guessed temperature, then a per-cell Newton solve of
+ * eq. PicardTemp), with GMRES as the Krylov solver.
+ *
+ * Layout: structure of arrays, x fastest, index = i + nx*(j + ny*k).
+ *   E, T_gas, rho, kappa_P, kappa_R: one plane of nx*ny*nz values each.
+ *   F: three planes [Fx | Fy | Fz].   f_ij: six planes [xx|yy|zz|xy|xz|yz].
+ * All data pointers are DEVICE pointers owned by the caller.  E, F, T_gas are
+ * FP64 and are overwritten with the new state; rho, kappa_P, kappa_R and f_ij
+ * have the element type params->coef_dtype (FP64 or FP32) and are read only.
+ *
+ * Errors are returned, never thrown.  Host-side argument checks happen before
+ * any device work (RAD_EINVAL); rad_last_error() gives a thread-local message.
+ * A step that does not reach params->tol returns RAD_NOT_CONVERGED and leaves
+ * the last iterate in E, F, T_gas.  Invalid data found on the device
+ * (negative or non-finite rho, kappa, f_dd) returns RAD_EDATA before the state
+ * is touched.  `stream` is a hipStream_t; NULL means the default stream.
+ */
+#ifndef VETTAM_RAD_H
+#define VETTAM_RAD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RAD_OK = 0,
+    RAD_NOT_CONVERGED = 1,
+    RAD_EINVAL = -1,   /* bad argument (checked on the host before any launch) */
+    RAD_ENOMEM = -2,   /* workspace smaller than rad_workspace_bytes() */
+    RAD_EHIP = -3,     /* a HIP runtime call failed */
+    RAD_ENOTIMPL = -4,
+    RAD_EDATA = -5     /* invalid coefficient data found on the device */
+} rad_status;
+
+typedef enum { RAD_BC_PERIODIC = 0, RAD_BC_OUTFLOW = 1, RAD_BC_DIRICHLET = 2 } rad_bc_kind;
+typedef enum { RAD_FP64 = 0, RAD_MIXED = 1 } rad_precision;
+typedef enum { RAD_PICARD_LAGGED = 0, RAD_PICARD_LINEARISED = 1 } rad_picard_mode;
+typedef enum { RAD_F64 = 0, RAD_F32 = 1 } rad_dtype;
+
+typedef struct {
+    double c, a_R, c_v;   /* speed of light, radiation constant, gas heat capacity per mass */
+    double tol;           /* target of the scaled nonlinear residual (see rad_stats_t) */
+    double eps_R;         /* relative tolerance cap of each linear (Krylov) solve */
+    double eps_P;         /* > 0: also stop when the relative change of [E,F,T] < eps_P (Sec. 2.3.4) */
+    int max_picard;       /* Picard iterations per step */
+    int max_krylov;       /* Krylov iterations per linear solve */
+    int gmres_m;          /* GMRES restart length, 1..64 */
+    int prec;             /* rad_precision: FP64, or FP32 Krylov with FP64 residual/refinement */
+    int mode;             /* rad_picard_mode: paper's lagged emission, or emission linearised at T_* */
+    int coef_dtype;       /* rad_dtype of rho, kappa_P, kappa_R, f_ij */
+} rad_params_t;
+
+typedef struct {
+    int status;            /* rad_status of the step (per block in the batched call) */
+    int picard_iters;
+    int krylov_iters;      /* Krylov iterations summed over Picard iterations */
+    int refine_sweeps;     /* FP64 residual evaluations (GMRES restarts) */
+    int neg_cells;         /* cells whose exchange solve had no positive root (T set to 0) */
+    int bad_cells;         /* cells with invalid coefficient data */
+    double scaled_residual;/* max of the three parts below */
+    double res_E;          /* || R_E / W_E || / ||E||,  W_E = 1 + sP + (dt/2h) sum_faces C */
+    double res_F;          /* || R_F / W_F || / (||F|| + c ||E||),  W_F = 1 + sR + (dt/2h) sum C */
+    double res_T;          /* || R_T / W_T || / ||T||,  W_T = alpha + 4 sP aR T^3 */
+    double rel_change;     /* relative change of [E, F, T] over the last Picard iteration */
+    double t_total_ms;     /* wall time of the call (host clock) */
+} rad_stats_t;
+
+/* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-4, eps_P 0,
+ * max_picard 50, max_krylov 20000, gmres_m 30, FP64, linearised, FP64 coefficients. */
+void rad_default_params(rad_params_t *p);
+
+/* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */
+size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t *p);
+
+/* One implicit radiation step on a uniform grid (Sec. 2.3.1 steps iv-vi).
+ * bc[6]: faces -x,+x,-y,+y,-z,+z, each RAD_BC_PERIODIC (in pairs) or
+ * RAD_BC_OUTFLOW (zero-gradient ghost, Sec. 3.3).  dt > 0, dx > 0.
+ * workspace: device memory of at least rad_workspace_bytes(), 256-byte aligned.
+ * stats: host pointer, may be NULL.  The call returns after the step completed. */
+int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
+             const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
+             double dt, double dx, const int bc[6], const rad_params_t *p,
+             void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
+
+/* Nonlinear residual of the backward-Euler system at a state (E, F, T) given
+ * the old state (E_n, F_n, T_n): R holds 5 planes [R_E | R_Fx | R_Fy | R_Fz | R_T]
+ * (FP64, device).  Stream-ordered, asynchronous. */
+int rad_residual(int nx, int ny, int nz, const double *E_n, const double *F_n, const double *T_n,
+                 const double *E, const double *F, const double *T,
+                 const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
+                 double dt, double dx, const int bc[6], const rad_params_t *p, double *R, void *stream);
+
+/* Corrected HLLE wave speed of every low face (Sec. 2.3.3): Cd[i] is the speed
+ * of the face between cell i - e_d and cell i (three FP64 planes Cx|Cy|Cz);
+ * the neighbour across a domain face follows bc (outflow: the cell itself).
+ * Stream-ordered, asynchronous. */
+int rad_face_speeds(int nx, int ny, int nz, const void *rho, const void *kappa_R, const void *f_ij,
+                    double dx, const int bc[6], const rad_params_t *p, double *C, void *stream);
+
+/* Linear transport operator of one Picard iteration applied to x = (E, Fx, Fy, Fz):
+ *   y_E = dE * E + (dt/h) div PhiE,  y_Fj = (1 + sR) F_j + (dt/h) div PhiF_j.
+ * x, y: four planes; dE: one plane.  dtype RAD_F64 or RAD_F32 selects the
+ * element type of x, y, dE and the arithmetic.  Stream-ordered, asynchronous. */
+int rad_apply(int nx, int ny, int nz, const void *x, void *y, const void *dE,
+              const void *rho, const void *kappa_R, const void *f_ij,
+              double dt, double dx, const int bc[6], const rad_params_t *p, int dtype, void *stream);
+
+/* Per-cell gas temperature update of eq. PicardTemp: T >= 0 solving
+ * alpha (T - T_n) + sP (aR T^4 - E) = 0 by Newton's method (FP64).
+ * n cells; all arrays device.  Stream-ordered, asynchronous. */
+int rad_exchange(long long n, const double *E, const double *T_n, double *T,
+                 const void *rho, const void *kappa_P, double dt, const rad_params_t *p, void *stream);
+
+/* ---------------------------------------------------------------- batched
+ * Many independent blocks, each an n^3 interior with ng ghost layers of fixed
+ * Dirichlet data (E, F and its own rho, kappa, f), solved in one persistent
+ * launch replayed from a HIP graph.  Every packed arena (E, T, rho, kappa_P,
+ * kappa_R: one arena each; F: 3 consecutive arenas Fx|Fy|Fz; f_ij: 6) holds
+ * block b's (n+2ng)^3 region, x fastest, at element offset off[b]; each arena
+ * has total_cells elements (the largest off + (n+2ng)^3).  Only the first
+ * ghost layer enters the first-order stencil. */
+typedef struct {
+    int n;           /* interior edge length (cells), 1..64 */
+    int ng;          /* ghost layers (>= 1) */
+    double dx, dt;
+    long long off;   /* element offset of the block in every arena */
+} rad_block_desc_t;
+
+typedef struct rad_plan_s *rad_plan;
+
+/* Device workspace (bytes) for a batch. */
+size_t rad_batched_workspace_bytes(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p);
+
+/* Build a plan: validate the descriptors, order blocks (largest first,
+ * interleaved across the chip's XCDs), upload the descriptor table into the
+ * workspace and build the HIP graph of the persistent launch.  The workspace
+ * must stay valid for the plan's lifetime. */
+int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p,
+                     void *workspace, size_t ws_bytes, void *stream, rad_plan *out);
+
+/* Time the candidate launch shapes on the given data (state restored after
+ * each trial from a copy kept in scratch, which needs
+ * rad_autotune_scratch_bytes()) and keep the fastest in the plan. */
+size_t rad_autotune_scratch_bytes(rad_plan plan);
+int rad_autotune_batched(rad_plan plan, double *E, double *F, double *T_gas, const void *rho,
+                         const void *kappa_P, const void *kappa_R, const void *f_ij,
+                         void *scratch, size_t scratch_bytes, void *stream);
+
+/* One step of every block: a single graph launch, asynchronous on `stream`.
+ * dev_stats: device array of nblocks rad_stats_t (per-block status etc.). */
+int rad_step_batched(rad_plan plan, double *E, double *F, double *T_gas, const void *rho,
+                     const void *kappa_P, const void *kappa_R, const void *f_ij,
+                     rad_stats_t *dev_stats, void *stream);
+
+void rad_plan_destroy(rad_plan plan);
+
+/* ------------------------------------------------------------- profiling
+ * Per-kernel-class timing with HIP events recorded around every launch on
+ * the launch stream, plus the algorithmic bytes each launch moves (the
+ * minimum HBM traffic of its inputs and outputs).  Off by default; costs
+ * two event records per launch when on.  Not thread-safe. */
+void rad_profile_enable(int on);
+void rad_profile_reset(void);
+/* Number of kernel classes with at least one timed launch. */
+int rad_profile_count(void);
+/* Class idx: name (static string), summed milliseconds, summed algorithmic
+ * bytes and launch count.  Returns RAD_EINVAL for a bad index. */
+int rad_profile_get(int idx, const char **name, double *ms, double *bytes, long long *launches);
+
+/* Message of the last non-OK return on this thread ("" if none). */
+const char *rad_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -288,7 +288,11 @@ void or_scaled_residual(const or_grid *g, const or_coef *cf, const double *En, d
                 weights(g, cf, C, c, T, &WE, &WF, &WT);
                 rE += (R[0][c] / WE) * (R[0][c] / WE);
                 for (int q = 1; q < 4; ++q) rF += (R[q][c] / WF) * (R[q][c] / WF);
-                rT += (R[4][c] / WT) * (R[4][c] / WT);
+                /* T >= 0 is the physical range: where the exchange equation has no
+                 * non-negative root (R_T > 0 at T = 0) the constraint T = 0 is active
+                 * and the exchange row counts as satisfied */
+                double RT = (T[c] == 0.0 && R[4][c] > 0.0) ? 0.0 : R[4][c];
+                rT += (RT / WT) * (RT / WT);
                 nE += E[c] * E[c];
                 for (int q = 0; q < 3; ++q) nF += F[q][c] * F[q][c];
                 nT += T[c] * T[c];

@@ -1,0 +1,182 @@
+// rad_device.h -- device-side building blocks of the implicit VET radiation step (gfx950).
+//
+// Internally the flux is carried as Ft = F / c, so that the operator of one
+// Picard iteration becomes dimensionless and symmetric in its use of c:
+//   E rows:  dE E   + nu sum_d (PhiE_{+d} - PhiE_{-d}),
+//            PhiE   = (Ft_d,L + Ft_d,R)/2 - Ct (E_R - E_L)/2
+//   Ft rows: (1+sR) Ft_j + nu sum_d (PhiF_{+d} - PhiF_{-d}),
+//            PhiF_j = (f_dj,L E_L + f_dj,R E_R)/2 - Ct (Ft_j,R - Ft_j,L)/2
+// with nu = c dt / h and Ct = C / c the corrected HLLE speed of Sec. 2.3.3
+// (eq. taucorrect, eq. wavespeedtau same-level rule) divided by c.  This is the
+// paper's operator with the flux rows divided by c and the flux unknowns
+// multiplied by c; FP32 Krylov vectors then hold E and Ft at the same scale
+// in any unit system.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace vr {
+
+constexpr int kBlock = 256;   // threads per workgroup of the streaming kernels (4 wave64)
+constexpr int kMaxM = 64;     // largest GMRES restart length
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2 };
+
+// Geometry and constants of one uniform grid.
+struct Grid {
+    int nx, ny, nz;
+    long long N;      // cells
+    int bclo[3];      // boundary kind of the low face of each axis
+    int bchi[3];      // ... and of the high face
+    double nu;        // c dt / h
+    double cdt;       // c dt  (s = c dt rho kappa)
+    double tau_k;     // tau_cell = tau_k * sR^2 / f_dd  with tau_k = 50 / nu^2
+    double c, aR, cv;
+};
+
+// row d of the symmetric tensor in the (xx,yy,zz,xy,xz,yz) plane order: f_d0, f_d1, f_d2
+__host__ __device__ constexpr int tens_row(int d, int j)
+{
+    return d == j ? d : ((d + j) == 1 ? 3 : ((d + j) == 2 ? 4 : 5));
+}
+
+__device__ __forceinline__ float xexpm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double xexpm1(double x) { return expm1(x); }
+__device__ __forceinline__ float xsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
+
+// Optical-depth parameter of the wave-speed correction for one cell along one
+// axis, tau = (10 h rho kappa_R)^2 / (2 f_dd) = tau_k sR^2 / f_dd.
+// No opacity: tau = 0.  Zero diagonal factor with opacity: tau = +inf.
+template <class T>
+__device__ __forceinline__ T cell_tau(T sR, T fdd, T tau_k)
+{
+    if (sR == T(0)) return T(0);
+    if (fdd == T(0)) return T(INFINITY);
+    return tau_k * sR * sR / fdd;
+}
+
+// Corrected HLLE signal speed divided by c at a face between two cells:
+// sqrt(max f_dd) * sqrt((1 - exp(-tau)) / tau) with tau the mean of the cells' values.
+template <class T>
+__device__ __forceinline__ T face_speed(T fL, T fR, T sRL, T sRR, T tau_k)
+{
+    T tau = T(0.5) * (cell_tau(sRL, fL, tau_k) + cell_tau(sRR, fR, tau_k));
+    T fc = fL > fR ? fL : fR;
+    T corr;
+    if (tau == T(0))
+        corr = T(1);
+    else if (isinf(tau))
+        corr = T(0);
+    else
+        corr = xsqrt(-xexpm1(-tau) / tau);
+    return xsqrt(fc) * corr;
+}
+
+// Cell (i,j,k) from a linear index (x fastest).
+__device__ __forceinline__ void cell_ijk(const Grid &g, long long c, int &i, int &j, int &k)
+{
+    long long q = c / g.nx;
+    i = (int)(c - q * g.nx);
+    k = (int)(q / g.ny);
+    j = (int)(q - (long long)k * g.ny);
+}
+
+// Linear index of the neighbour across face (d, side) of cell c = (i,j,k):
+// periodic faces wrap, outflow faces return the cell itself (zero-gradient ghost).
+__device__ __forceinline__ long long neighbour(const Grid &g, int i, int j, int k, long long c, int d, int side)
+{
+    int q = d == 0 ? i : (d == 1 ? j : k);
+    int n = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+    long long stride = d == 0 ? 1LL : (d == 1 ? (long long)g.nx : (long long)g.nx * g.ny);
+    if (side) {
+        if (q + 1 < n) return c + stride;
+        return g.bchi[d] == BC_PERIODIC ? c - (long long)(n - 1) * stride : c;
+    }
+    if (q > 0) return c - stride;
+    return g.bclo[d] == BC_PERIODIC ? c + (long long)(n - 1) * stride : c;
+}
+
+// Transport part of the operator at one cell.  `ld(q, idx)` returns component q
+// (0: E, 1..3: Ft) of the operand at cell idx; `fl(t, idx)` the tensor plane t;
+// `sr(idx)` the cell's sR.  Accumulates nu * div(Phi) into div[4] and returns
+// the sum of Ct over faces whose neighbour is another cell (diagonal of the
+// transport part is 0.5 nu times that) and over all six faces (for scaling).
+template <class T, class LD, class FL, class SR>
+__device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, long long c, LD ld, FL fl, SR sr,
+                                          T div[4], T &sumC_nb, T &sumC_all)
+{
+    const T tk = (T)g.tau_k;
+    T Ec = ld(0, c);
+    T Fc[3] = {ld(1, c), ld(2, c), ld(3, c)};
+    T sRc = sr(c);
+    T dE = 0, dF[3] = {0, 0, 0};
+    sumC_nb = 0;
+    sumC_all = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T fcr[3] = {fl(tens_row(d, 0), c), fl(tens_row(d, 1), c), fl(tens_row(d, 2), c)};
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            long long nb = neighbour(g, i, j, k, c, d, side);
+            T En = ld(0, nb);
+            T Fn[3] = {ld(1, nb), ld(2, nb), ld(3, nb)};
+            T fnr[3] = {fl(tens_row(d, 0), nb), fl(tens_row(d, 1), nb), fl(tens_row(d, 2), nb)};
+            T C = face_speed<T>(fcr[d], fnr[d], sRc, sr(nb), tk);
+            sumC_all += C;
+            if (nb != c) sumC_nb += C;
+            // left/right states of the face
+            const T EL = side ? Ec : En, ER = side ? En : Ec;
+            const T *FL_ = side ? Fc : Fn;
+            const T *FR_ = side ? Fn : Fc;
+            const T *fL = side ? fcr : fnr;
+            const T *fR = side ? fnr : fcr;
+            T phiE = T(0.5) * (FL_[d] + FR_[d]) - T(0.5) * C * (ER - EL);
+            T sgn = side ? T(1) : T(-1);
+            dE += sgn * phiE;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                T phiF = T(0.5) * (fL[q] * EL + fR[q] * ER) - T(0.5) * C * (FR_[q] - FL_[q]);
+                dF[q] += sgn * phiF;
+            }
+        }
+    }
+    const T nu = (T)g.nu;
+    div[0] = nu * dE;
+    div[1] = nu * dF[0];
+    div[2] = nu * dF[1];
+    div[3] = nu * dF[2];
+}
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV per-thread values over the workgroup (kBlock threads, 1D) and store
+// them at partials[slot * NV + q].  Fixed order: reruns are bitwise identical.
+template <int NV>
+__device__ __forceinline__ void block_store(double (&v)[NV], double *partials, long long slot)
+{
+    __shared__ double sh[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) sh[q][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[threadIdx.x][w];
+        partials[slot * NV + threadIdx.x] = s;
+    }
+}
+
+}  // namespace vr

@@ -1,0 +1,45 @@
+// rad_host.h -- host-side helpers shared by the library's translation units:
+// error reporting, parameter validation, workspace alignment.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "../../include/vettam_rad.h"
+#include "rad_device.h"
+
+namespace vr {
+
+// Record a thread-local error message and return the status code.
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+int check_params(const rad_params_t *p);
+
+inline size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Kernel-class profiler (see rad_profile_* in the C ABI).  prof_begin returns a
+// token (-1 when profiling is off); prof_end records the closing event and the
+// launch's algorithmic bytes; prof_resolve turns pending event pairs into times
+// (call after the stream has been synchronised).
+int prof_begin(int kid, hipStream_t st);
+void prof_end(int token, hipStream_t st, double bytes);
+void prof_resolve();
+
+enum {
+    K_SETUP = 0, K_RESIDUAL, K_APPLY32, K_APPLY64, K_MULTIDOT32, K_MULTIDOT64, K_ORTH32, K_ORTH64,
+    K_UPDATEX32, K_UPDATEX64, K_EXCHANGE, K_COMMIT, K_REDUCE, K_BATCHED, K_NCLASS
+};
+
+}  // namespace vr
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return ::vr::fail(RAD_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define RAD_TRY(expr)               \
+    do {                            \
+        int r_ = (expr);            \
+        if (r_ != RAD_OK) return r_; \
+    } while (0)

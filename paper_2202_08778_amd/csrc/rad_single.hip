@@ -1,0 +1,852 @@
+// rad_single.hip -- one implicit radiation step on a uniform grid (gfx950).
+//
+// Host-driven Picard loop (Sec. 2.3.1 steps iv-vi):
+//   residual   r = b(T*) - A(T*) X  in FP64 for the linear system of the current
+//              iteration; its scaled norm is also the nonlinear residual
+//   Krylov     restarted GMRES(m) on the Jacobi-scaled system, Arnoldi in FP32
+//              (mixed) or FP64, solution accumulated into the FP64 state; each
+//              restart re-evaluates the FP64 residual (iterative refinement)
+//   exchange   per-cell FP64 Newton solve of eq. PicardTemp for T
+// Every vector operation and reduction runs in the kernels below; the host
+// only keeps the (m+1) x m Hessenberg matrix and decides when to stop.
+#include "rad_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace vr;
+
+namespace {
+
+// --------------------------------------------------------------- kernels
+
+// Coefficient setup, once per step: sR in the apply precision, an FP32 copy of
+// the tensor when the Krylov arithmetic is FP32 but the input is FP64, the
+// FP64 state X = (E, F/c), its copy X0 and T* = T_n; counts invalid cells.
+template <class CT, class AT>
+__global__ void __launch_bounds__(kBlock) k_setup(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP,
+                                                  const CT *__restrict__ kR, const CT *__restrict__ f, AT *__restrict__ sR,
+                                                  AT *__restrict__ fA, const double *__restrict__ E,
+                                                  const double *__restrict__ F, const double *__restrict__ T,
+                                                  double *__restrict__ X, double *__restrict__ X0,
+                                                  double *__restrict__ Tc, double *partials)
+{
+    const long long N = g.N;
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0};
+    if (c < N) {
+        double r = (double)rho[c], p = (double)kP[c], s = (double)kR[c];
+        sR[c] = (AT)(g.cdt * r * s);
+        bool bad = !(r >= 0) || !(p >= 0) || !(s >= 0) || !isfinite(r) || !isfinite(p) || !isfinite(s);
+        for (int t = 0; t < 6; ++t) {
+            double ft = (double)f[t * N + c];
+            if (!isfinite(ft) || (t < 3 && ft < 0)) bad = true;
+            if (fA) fA[t * N + c] = (AT)ft;
+        }
+        v[0] = bad ? 1.0 : 0.0;
+        double inv_c = 1.0 / g.c;
+        X[c] = X0[c] = E[c];
+        for (int q = 0; q < 3; ++q) X[(1 + q) * N + c] = X0[(1 + q) * N + c] = F[q * N + c] * inv_c;
+        Tc[c] = T[c];
+    }
+    block_store<1>(v, partials, blockIdx.x);
+}
+
+enum { RES_KRYLOV = 0, RES_PHYSICAL = 1 };
+
+// FP64 residual of the linear system of one Picard iteration at the state X,
+// with the emission taken at Ts (lagged: paper; linearised: Newton-consistent).
+// RES_KRYLOV: writes D^-1 r (Jacobi-scaled, Krylov precision) into out, the E
+// diagonal in the apply precision into dEA, and partial sums
+//   [sum (rE/WE)^2, sum (rF/WF)^2, sum E^2, sum Ft^2, sum (D^-1 r)^2].
+// RES_PHYSICAL: writes the nonlinear residual (R_E, R_F (physical), R_T) of
+// the state (X = E, F physical, Ts = T) into outR (5 planes).
+template <class CT, class KT, class AT, int MODE>
+__global__ void __launch_bounds__(kBlock)
+    k_residual(Grid g, int picard_mode, const double *__restrict__ En, const double *__restrict__ Fn,
+               const double *__restrict__ Tn, const double *__restrict__ Ts, const CT *__restrict__ rho,
+               const CT *__restrict__ kP, const CT *__restrict__ kR, const CT *__restrict__ f,
+               const double *__restrict__ XE, const double *__restrict__ XF, double xF, KT *__restrict__ out,
+               AT *__restrict__ dEA, double *__restrict__ outR, double *partials)
+{
+    const long long N = g.N;
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (c < N) {
+        int i, j, k;
+        cell_ijk(g, c, i, j, k);
+        const double cdt = g.cdt;
+        auto ld = [&](int q, long long idx) -> double { return q == 0 ? XE[idx] : xF * XF[(q - 1) * N + idx]; };
+        auto fl = [&](int t, long long idx) -> double { return (double)f[t * N + idx]; };
+        auto sr = [&](long long idx) -> double { return cdt * (double)rho[idx] * (double)kR[idx]; };
+        double div[4], sC_nb, sC_all;
+        transport<double>(g, i, j, k, c, ld, fl, sr, div, sC_nb, sC_all);
+
+        const double r_ = (double)rho[c];
+        const double sP = cdt * r_ * (double)kP[c], sR = sr(c), alpha = r_ * g.cv, aR = g.aR;
+        const double T = Ts[c], T3 = T * T * T, T4 = T3 * T;
+        double dE, bE;
+        if (picard_mode == 0) {
+            dE = 1.0 + sP;
+            bE = En[c] + sP * aR * T4;
+        } else {
+            const double den = alpha + 4.0 * sP * aR * T3;
+            const double eta = den > 0 ? 4.0 * sP * aR * T3 / den : 0.0;
+            dE = 1.0 + sP * (1.0 - eta);
+            bE = En[c] + eta * alpha * Tn[c] - 3.0 * (1.0 - eta) * sP * aR * T4;
+        }
+        const double E = ld(0, c);
+        const double rE = bE - (dE * E + div[0]);
+        const double invc = 1.0 / g.c;
+        double rF[3];
+        for (int q = 0; q < 3; ++q) rF[q] = Fn[q * N + c] * invc - ((1.0 + sR) * ld(1 + q, c) + div[1 + q]);
+        if (MODE == RES_PHYSICAL) {
+            outR[c] = -rE;
+            for (int q = 0; q < 3; ++q) outR[(1 + q) * N + c] = -rF[q] * g.c;
+            outR[4 * N + c] = alpha * (T - Tn[c]) + sP * (aR * T4 - E);
+        } else {
+            const double half = 0.5 * g.nu;
+            const double DE = dE + half * sC_nb, DF = 1.0 + sR + half * sC_nb;
+            const double WE = 1.0 + sP + half * sC_all, WF = 1.0 + sR + half * sC_all;
+            const double zE = rE / DE;
+            out[c] = (KT)zE;
+            dEA[c] = (AT)dE;
+            double zz = zE * zE, wf = 0, fn = 0;
+            for (int q = 0; q < 3; ++q) {
+                const double z = rF[q] / DF;
+                out[(1 + q) * N + c] = (KT)z;
+                zz += z * z;
+                wf += (rF[q] / WF) * (rF[q] / WF);
+                const double Fq = ld(1 + q, c);
+                fn += Fq * Fq;
+            }
+            v[0] = (rE / WE) * (rE / WE);
+            v[1] = wf;
+            v[2] = E * E;
+            v[3] = fn;
+            v[4] = zz;
+        }
+    }
+    if (MODE == RES_KRYLOV) block_store<5>(v, partials, blockIdx.x);
+}
+
+// w = D^-1 A (s x) in the apply precision AT (tensor stored as ST), s = *xs.
+// When prec == 0, y = A x (no scaling) and xF / yF rescale the flux components
+// on load / store (used by the physical-units entry point).
+template <class AT, class ST>
+__global__ void __launch_bounds__(kBlock)
+    k_apply(Grid g, const ST *__restrict__ f, const AT *__restrict__ sR, const ST *__restrict__ rho,
+            const ST *__restrict__ kR, const AT *__restrict__ dE, const AT *__restrict__ x,
+            const double *__restrict__ xs, AT *__restrict__ y, int prec, AT xF, AT yF)
+{
+    const long long N = g.N;
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    int i, j, k;
+    cell_ijk(g, c, i, j, k);
+    const AT s = xs ? (AT)(*xs) : AT(1);
+    const AT sF = s * xF;
+    auto ld = [&](int q, long long idx) -> AT { return q == 0 ? s * x[idx] : sF * x[q * N + idx]; };
+    auto fl = [&](int t, long long idx) -> AT { return (AT)f[t * N + idx]; };
+    const double cdt = g.cdt;
+    auto sr = [&](long long idx) -> AT {
+        return sR ? sR[idx] : (AT)(cdt * (double)rho[idx] * (double)kR[idx]);
+    };
+    AT div[4], sC_nb, sC_all;
+    transport<AT>(g, i, j, k, c, ld, fl, sr, div, sC_nb, sC_all);
+    const AT sRc = sr(c), dEc = dE[c];
+    AT yE = dEc * ld(0, c) + div[0];
+    AT yFq[3];
+    for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + sRc) * ld(1 + q, c) + div[1 + q];
+    if (prec) {
+        const AT half = AT(0.5) * (AT)g.nu;
+        yE /= dEc + half * sC_nb;
+        const AT DF = AT(1) + sRc + half * sC_nb;
+        for (int q = 0; q < 3; ++q) yFq[q] /= DF;
+    }
+    y[c] = yE;
+    for (int q = 0; q < 3; ++q) y[(1 + q) * N + c] = yFq[q] * yF;
+}
+
+// Raw dots <V_i, w> for i in [i0, i0+cnt) (cnt <= NV) and <w, w>, FP64 accumulation.
+template <class KT, int NV>
+__global__ void __launch_bounds__(kBlock)
+    k_multidot(const KT *__restrict__ V, long long stride, int i0, int cnt, const KT *__restrict__ w, long long n,
+               double *partials)
+{
+    double acc[NV + 1];
+#pragma unroll
+    for (int q = 0; q <= NV; ++q) acc[q] = 0;
+    const long long step = (long long)gridDim.x * kBlock;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += step) {
+        const double we = (double)w[e];
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q < cnt) acc[q] += (double)V[(long long)(i0 + q) * stride + e] * we;
+        acc[NV] += we * we;
+    }
+    block_store<NV + 1>(acc, partials, blockIdx.x);
+}
+
+// out = w - sum_i s_i^2 d_i V_i  (i < cnt), accumulating ||out||^2.  out may alias w.
+template <class KT>
+__global__ void __launch_bounds__(kBlock)
+    k_orth_update(const KT *__restrict__ V, long long stride, int cnt, const KT *w, KT *out,
+                  const double *__restrict__ dots, const double *__restrict__ s, long long n, double *partials)
+{
+    __shared__ double cf[kMaxM + 1];
+    if (threadIdx.x < cnt) cf[threadIdx.x] = s[threadIdx.x] * s[threadIdx.x] * dots[threadIdx.x];
+    __syncthreads();
+    double acc[1] = {0};
+    const long long step = (long long)gridDim.x * kBlock;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += step) {
+        double val = (double)w[e];
+        for (int i = 0; i < cnt; ++i) val -= cf[i] * (double)V[(long long)i * stride + e];
+        const KT st = (KT)val;
+        out[e] = st;
+        acc[0] += (double)st * (double)st;
+    }
+    block_store<1>(acc, partials, blockIdx.x);
+}
+
+// X += sum_i a_i V_i over the 4N-vector (FP64 state, Krylov-precision basis).
+struct Coefs {
+    double a[kMaxM + 1];
+};
+
+template <class KT>
+__global__ void __launch_bounds__(kBlock)
+    k_update_x(double *__restrict__ X, const KT *__restrict__ V, long long stride, int cnt, Coefs cf, long long n)
+{
+    const long long step = (long long)gridDim.x * kBlock;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += step) {
+        double acc = X[e];
+        for (int i = 0; i < cnt; ++i) acc += cf.a[i] * (double)V[(long long)i * stride + e];
+        X[e] = acc;
+    }
+}
+
+// Per-cell exchange solve (eq. PicardTemp) for T with E = X_E; then the
+// diagnostics of the Picard iteration, and X0 = X.  Partials:
+//   [sum (R_T/W_T)^2, sum T^2, sum dT^2, sum dE^2, sum E^2, sum dFt^2, sum Ft^2, neg]
+__device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP, double aR, double E, bool &neg)
+{
+    if (sP == 0.0) return Tn;
+    const double rhs = alpha * Tn + sP * E;
+    if (!(rhs > 0.0)) {
+        neg = true;
+        return 0.0;
+    }
+    // start above the root (smaller of the two one-term bounds); g is convex and
+    // increasing so Newton descends monotonically; stop when it stops decreasing
+    double T = sqrt(sqrt(rhs / (sP * aR)));
+    if (alpha > 0.0 && rhs / alpha < T) T = rhs / alpha;
+    for (int it = 0; it < 200; ++it) {
+        const double T3 = T * T * T;
+        const double gv = alpha * (T - Tn) + sP * (aR * T3 * T - E);
+        const double dg = alpha + 4.0 * sP * aR * T3;
+        const double Tnew = T - gv / dg;
+        if (!(Tnew < T)) break;
+        T = Tnew;
+    }
+    return T;
+}
+
+template <class CT>
+__global__ void __launch_bounds__(kBlock)
+    k_exchange(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP, const double *__restrict__ Tn,
+               double *__restrict__ Tc, double *__restrict__ X, double *__restrict__ X0, double *partials)
+{
+    const long long N = g.N;
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (c < N) {
+        const double r_ = (double)rho[c];
+        const double sP = g.cdt * r_ * (double)kP[c], alpha = r_ * g.cv, aR = g.aR;
+        const double E = X[c];
+        bool neg = false;
+        const double T = exchange_T(alpha, Tn[c], sP, aR, E, neg);
+        const double T3 = T * T * T;
+        // where no non-negative root exists T = 0 is the active bound (R_T > 0 there)
+        const double RT0 = alpha * (T - Tn[c]) + sP * (aR * T3 * T - E);
+        const double RT = (T == 0.0 && RT0 > 0.0) ? 0.0 : RT0;
+        const double WT = alpha + 4.0 * sP * aR * T3;
+        const double dT = T - Tc[c];
+        Tc[c] = T;
+        v[0] = WT > 0 ? (RT / WT) * (RT / WT) : 0.0;
+        v[1] = T * T;
+        v[2] = dT * dT;
+        const double dE = E - X0[c];
+        v[3] = dE * dE;
+        v[4] = E * E;
+        X0[c] = E;
+        for (int q = 1; q < 4; ++q) {
+            const double x = X[q * N + c], d = x - X0[q * N + c];
+            v[5] += d * d;
+            v[6] += x * x;
+            X0[q * N + c] = x;
+        }
+        v[7] = neg ? 1.0 : 0.0;
+    }
+    block_store<8>(v, partials, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_commit(long long N, double c_light, const double *__restrict__ X, const double *__restrict__ Tc,
+             double *__restrict__ E, double *__restrict__ F, double *__restrict__ T)
+{
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    E[c] = X[c];
+    for (int q = 0; q < 3; ++q) F[q * N + c] = X[(1 + q) * N + c] * c_light;
+    T[c] = Tc[c];
+}
+
+// Sums the nv columns of partials[nblk][nv] in a fixed order: columns [0, na)
+// go to out_a, columns [na, nv) to out_b.  If sq_col >= 0, 1/sqrt of that
+// column's sum is also written to *sdev (scale of a new Krylov vector).
+__global__ void __launch_bounds__(kBlock)
+    k_reduce(const double *__restrict__ partials, long long nblk, int nv, int na, double *out_a, double *out_b,
+             int sq_col, double *sdev)
+{
+    __shared__ double sh[kBlock / 64];
+    for (int q = 0; q < nv; ++q) {
+        double s = 0;
+        for (long long b = threadIdx.x; b < nblk; b += kBlock) s += partials[b * nv + q];
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0;
+            for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+            if (q < na)
+                out_a[q] = t;
+            else
+                out_b[q - na] = t;
+            if (q == sq_col) *sdev = t > 0 ? 1.0 / sqrt(t) : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Per-face speeds (FP64, physical units) for the rad_face_speeds entry point.
+template <class CT>
+__global__ void __launch_bounds__(kBlock)
+    k_face_speeds(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kR, const CT *__restrict__ f,
+                  double *__restrict__ C)
+{
+    const long long N = g.N;
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    int i, j, k;
+    cell_ijk(g, c, i, j, k);
+    const double sRc = g.cdt * (double)rho[c] * (double)kR[c];
+    for (int d = 0; d < 3; ++d) {
+        long long nb = neighbour(g, i, j, k, c, d, 0);
+        const double sRn = g.cdt * (double)rho[nb] * (double)kR[nb];
+        C[d * N + c] = g.c * face_speed<double>((double)f[d * N + nb], (double)f[d * N + c], sRn, sRc, g.tau_k);
+    }
+}
+
+template <class CT>
+__global__ void __launch_bounds__(kBlock)
+    k_exchange_only(long long n, Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP,
+                    const double *__restrict__ E, const double *__restrict__ Tn, double *__restrict__ T)
+{
+    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    const double r_ = (double)rho[c];
+    bool neg = false;
+    T[c] = exchange_T(r_ * g.cv, Tn[c], g.cdt * r_ * (double)kP[c], g.aR, E[c], neg);
+}
+
+// --------------------------------------------------------------- host side
+
+Grid make_grid(int nx, int ny, int nz, const int bc[6], double dt, double dx, const rad_params_t &p)
+{
+    Grid g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.N = (long long)nx * ny * nz;
+    for (int a = 0; a < 3; ++a) {
+        g.bclo[a] = bc[2 * a];
+        g.bchi[a] = bc[2 * a + 1];
+    }
+    g.c = p.c;
+    g.aR = p.a_R;
+    g.cv = p.c_v;
+    g.cdt = p.c * dt;
+    g.nu = p.c * dt / dx;
+    g.tau_k = 50.0 / (g.nu * g.nu);
+    return g;
+}
+
+int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6], const rad_params_t *p,
+                    bool allow_dirichlet)
+{
+    if (!p) return fail(RAD_EINVAL, "params is NULL");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(RAD_EINVAL, "grid extents must be >= 1");
+    if ((long long)nx * ny * nz > (1LL << 31)) return fail(RAD_EINVAL, "grid larger than 2^31 cells");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(RAD_EINVAL, "dt must be positive and finite");
+    if (!(dx > 0) || !std::isfinite(dx)) return fail(RAD_EINVAL, "dx must be positive and finite");
+    if (!bc) return fail(RAD_EINVAL, "bc is NULL");
+    for (int f = 0; f < 6; ++f) {
+        if (bc[f] != RAD_BC_PERIODIC && bc[f] != RAD_BC_OUTFLOW && !(allow_dirichlet && bc[f] == RAD_BC_DIRICHLET))
+            return fail(RAD_EINVAL, "unsupported boundary kind on face %d", f);
+    }
+    for (int a = 0; a < 3; ++a)
+        if ((bc[2 * a] == RAD_BC_PERIODIC) != (bc[2 * a + 1] == RAD_BC_PERIODIC))
+            return fail(RAD_EINVAL, "periodic faces must come in pairs (axis %d)", a);
+    return check_params(p);
+}
+
+struct Layout {
+    size_t X, X0, Tc, sR, dEA, fA, V, W, part, small, total;
+    long long nblk_cells, nblk_vec;
+    size_t ksz;
+};
+
+long long vec_blocks(long long n) { return std::min<long long>((n + kBlock - 1) / kBlock, 2048); }
+
+Layout layout(long long N, const rad_params_t &p)
+{
+    Layout L;
+    const bool mixed = p.prec == RAD_MIXED;
+    const size_t ksz = mixed ? 4 : 8;
+    L.ksz = ksz;
+    const int m = p.gmres_m;
+    L.nblk_cells = (N + kBlock - 1) / kBlock;
+    L.nblk_vec = vec_blocks(4 * N);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align_up(bytes);
+        return at;
+    };
+    L.X = take(4 * N * 8);
+    L.X0 = take(4 * N * 8);
+    L.Tc = take(N * 8);
+    L.sR = take(N * ksz);
+    L.dEA = take(N * ksz);
+    L.fA = (mixed && p.coef_dtype == RAD_F64) ? take(6 * N * ksz) : take(0);
+    L.V = take((size_t)(m + 1) * 4 * N * ksz);
+    L.W = take(4 * N * ksz);
+    L.part = take((size_t)std::max<long long>(L.nblk_cells, L.nblk_vec) * 24 * 8);
+    L.small = take(512 * 8);
+    L.total = o;
+    return L;
+}
+
+// Small device area (doubles) that reductions write and the host reads back.
+enum {
+    SM_RED = 0,     // generic reduction results (<= 16)
+    SM_DOTS = 32,   // <v_i, w>, i <= kMaxM (+16 slack for chunked writes)
+    SM_WW = 120,    // <w, w>
+    SM_NRM = 121,   // ||v_{j+1}||^2 after orthogonalisation
+    SM_S = 128,     // basis scales s_i = 1 / ||v_i||, i <= kMaxM
+    SM_TOTAL = 200
+};
+
+struct Solver {
+    Grid g;
+    rad_params_t p;
+    hipStream_t st;
+    char *ws;
+    Layout L;
+    const void *rho, *kP, *kR, *f;
+    const double *En, *Fn, *Tn;
+    double *E, *F, *T;
+    double *host;  // pinned staging, SM_TOTAL doubles
+    rad_stats_t stats;
+
+    template <class P>
+    P *at(size_t off) { return reinterpret_cast<P *>(ws + off); }
+    double *sm() { return at<double>(L.small); }
+    double *part() { return at<double>(L.part); }
+
+    void reduce(long long nblk, int nv, int na, double *out_a, double *out_b = nullptr, int sq_col = -1,
+                double *sdev = nullptr)
+    {
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, part(), nblk, nv, na, out_a, out_b, sq_col,
+                           sdev);
+    }
+    // launch under the kernel-class profiler (no-op when profiling is off)
+    template <class F>
+    void timed(int kid, double bytes, F &&launch)
+    {
+        const int tok = prof_begin(kid, st);
+        launch();
+        prof_end(tok, st, bytes);
+    }
+    // copy sm()[off, off+count) to host[off...] and wait
+    int read(int off, int count)
+    {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(host + off, sm() + off, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return RAD_OK;
+    }
+};
+
+template <class CT, class KT>
+int run_step(Solver &S)
+{
+    using AT = KT;
+    Grid &g = S.g;
+    const rad_params_t &p = S.p;
+    const long long N = g.N, n4 = 4 * N;
+    const dim3 gc((unsigned)S.L.nblk_cells), gv((unsigned)S.L.nblk_vec), bl(kBlock);
+    const CT *rho = (const CT *)S.rho, *kP = (const CT *)S.kP, *kR = (const CT *)S.kR, *f = (const CT *)S.f;
+    double *X = S.at<double>(S.L.X), *X0 = S.at<double>(S.L.X0), *Tc = S.at<double>(S.L.Tc);
+    AT *sR = S.at<AT>(S.L.sR), *dEA = S.at<AT>(S.L.dEA);
+    AT *fA = (p.prec == RAD_MIXED && p.coef_dtype == RAD_F64) ? S.at<AT>(S.L.fA) : nullptr;
+    KT *V = S.at<KT>(S.L.V), *W = S.at<KT>(S.L.W);
+    double *part = S.part(), *sm = S.sm(), *h = S.host;
+    const int m = p.gmres_m;
+    const long long stride = n4;
+    rad_stats_t &st = S.stats;
+
+    const double cb = sizeof(CT), kb = sizeof(KT), Nd = (double)N;
+    S.timed(K_SETUP, Nd * (9 * cb + 40 + kb + (fA ? 6 * kb : 0) + 72), [&] {
+        hipLaunchKernelGGL((k_setup<CT, AT>), gc, bl, 0, S.st, g, rho, kP, kR, f, sR, fA, S.En, S.Fn, S.Tn, X, X0,
+                           Tc, part);
+    });
+    S.reduce(S.L.nblk_cells, 1, 1, sm + SM_RED);
+    RAD_TRY(S.read(SM_RED, 1));
+    st.bad_cells = (int)h[SM_RED];
+    if (st.bad_cells > 0) return fail(RAD_EDATA, "%d cells with invalid rho/kappa/f data", st.bad_cells);
+
+    const int kApply = sizeof(KT) == 4 ? K_APPLY32 : K_APPLY64;
+    const int kDot = sizeof(KT) == 4 ? K_MULTIDOT32 : K_MULTIDOT64;
+    const int kOrth = sizeof(KT) == 4 ? K_ORTH32 : K_ORTH64;
+    const int kUpd = sizeof(KT) == 4 ? K_UPDATEX32 : K_UPDATEX64;
+    const double fb = fA ? kb : cb;   // bytes per stored tensor component read by the apply
+    auto apply = [&](const KT *x, const double *xs, KT *y) {
+        const int tok = prof_begin(kApply, S.st);
+        if (fA)
+            hipLaunchKernelGGL((k_apply<AT, AT>), gc, bl, 0, S.st, g, (const AT *)fA, sR, (const AT *)nullptr,
+                               (const AT *)nullptr, dEA, x, xs, y, 1, AT(1), AT(1));
+        else
+            hipLaunchKernelGGL((k_apply<AT, CT>), gc, bl, 0, S.st, g, f, sR, (const CT *)nullptr,
+                               (const CT *)nullptr, dEA, x, xs, y, 1, AT(1), AT(1));
+        prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 2 * kb));
+    };
+    // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
+    // its norm's inverse becomes the scale s_0 of V[0].
+    double nrm[5];
+    auto residual = [&]() -> int {
+        S.timed(K_RESIDUAL, Nd * (32 + 48 + 9 * cb + 5 * kb), [&] {
+            hipLaunchKernelGGL((k_residual<CT, KT, AT, RES_KRYLOV>), gc, bl, 0, S.st, g, p.mode, S.En, S.Fn, S.Tn,
+                               Tc, rho, kP, kR, f, X, X + N, 1.0, V, dEA, nullptr, part);
+        });
+        S.reduce(S.L.nblk_cells, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
+        RAD_TRY(S.read(SM_RED, 5));
+        for (int q = 0; q < 5; ++q) nrm[q] = h[SM_RED + q];
+        st.refine_sweeps++;
+        return RAD_OK;
+    };
+    // <V_i, w> for i < cnt into SM_DOTS and <w, w> into SM_WW
+    auto multidot = [&](int cnt, const KT *w) {
+        for (int i0 = 0; i0 < cnt; i0 += 16) {
+            const int c = std::min(16, cnt - i0);
+            S.timed(kDot, 4 * Nd * kb * (c + 1), [&] {
+                hipLaunchKernelGGL((k_multidot<KT, 16>), gv, bl, 0, S.st, V, stride, i0, c, w, n4, part);
+            });
+            S.reduce(S.L.nblk_vec, 17, 16, sm + SM_DOTS + i0, sm + SM_WW);
+        }
+    };
+
+    double resT = 0;
+    int status = RAD_NOT_CONVERGED;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gvec(m + 1), y(m), sv(m + 1);
+
+    for (int k = 0;; ++k) {
+        RAD_TRY(residual());
+        const double nE = std::sqrt(nrm[2]), nF = std::sqrt(nrm[3]);
+        st.res_E = nE > 0 ? std::sqrt(nrm[0]) / nE : std::sqrt(nrm[0]);
+        st.res_F = (nF + nE) > 0 ? std::sqrt(nrm[1]) / (nF + nE) : std::sqrt(nrm[1]);
+        st.res_T = resT;
+        const double res = std::max(std::max(st.res_E, st.res_F), resT);
+        st.scaled_residual = res;
+        if (k > 0 && (res <= p.tol || (p.eps_P > 0 && st.rel_change < p.eps_P))) {
+            status = RAD_OK;
+            break;
+        }
+        if (k >= p.max_picard) break;
+
+        // ---- Krylov solve of A d = r for the correction, accumulated into X.
+        // Linear tolerance: eps_R relative, tightened so the last solve reaches tol.
+        double beta = std::sqrt(nrm[4]);
+        const double rtol = std::min(1.0, std::max(std::min(p.eps_R, 1.0), 0.1 * p.tol / std::max(res, 1e-300)));
+        const double target = beta * rtol;
+        const double inner_floor = (sizeof(KT) == 4) ? 1e-5 : 0.0;  // FP32 Arnoldi resolves ~5 decades per cycle
+        int its = 0;
+        double beta_prev = INFINITY;
+        while (beta > target && beta > 0 && its < p.max_krylov && beta < 0.999 * beta_prev) {
+            beta_prev = beta;
+            const double cycle_target = std::max(target, beta * inner_floor);
+            RAD_TRY(S.read(SM_S, 1));
+            sv[0] = h[SM_S];
+            std::fill(gvec.begin(), gvec.end(), 0.0);
+            gvec[0] = beta;
+            int cols = 0;
+            for (int j = 0; j < m && its < p.max_krylov; ++j) {
+                KT *vn = V + (long long)(j + 1) * stride;
+                apply(V + (long long)j * stride, sm + SM_S + j, W);
+                ++its;
+                multidot(j + 1, W);
+                S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
+                    hipLaunchKernelGGL((k_orth_update<KT>), gv, bl, 0, S.st, V, stride, j + 1, W, vn, sm + SM_DOTS,
+                                       sm + SM_S, n4, part);
+                });
+                S.reduce(S.L.nblk_vec, 1, 1, sm + SM_NRM, nullptr, 0, sm + SM_S + j + 1);
+                RAD_TRY(S.read(0, SM_TOTAL));
+                const double ww = h[SM_WW];
+                double nn = h[SM_NRM];
+                for (int i = 0; i <= j; ++i) H[i * m + j] = sv[i] * h[SM_DOTS + i];
+                // second Gram-Schmidt pass when the first removed more than half the norm
+                if (nn < 0.5 * ww) {
+                    multidot(j + 1, vn);
+                    S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
+                        hipLaunchKernelGGL((k_orth_update<KT>), gv, bl, 0, S.st, V, stride, j + 1, vn, vn,
+                                           sm + SM_DOTS, sm + SM_S, n4, part);
+                    });
+                    S.reduce(S.L.nblk_vec, 1, 1, sm + SM_NRM, nullptr, 0, sm + SM_S + j + 1);
+                    RAD_TRY(S.read(0, SM_TOTAL));
+                    nn = h[SM_NRM];
+                    for (int i = 0; i <= j; ++i) H[i * m + j] += sv[i] * h[SM_DOTS + i];
+                }
+                const double hn = std::sqrt(nn);
+                sv[j + 1] = h[SM_S + j + 1];
+                H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double a = H[i * m + j], b = H[(i + 1) * m + j];
+                    H[i * m + j] = cs[i] * a + sn[i] * b;
+                    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+                }
+                const double a = H[j * m + j], b = H[(j + 1) * m + j];
+                const double rr = std::hypot(a, b);
+                cs[j] = rr > 0 ? a / rr : 1.0;
+                sn[j] = rr > 0 ? b / rr : 0.0;
+                H[j * m + j] = rr;
+                H[(j + 1) * m + j] = 0.0;
+                gvec[j + 1] = -sn[j] * gvec[j];
+                gvec[j] = cs[j] * gvec[j];
+                cols = j + 1;
+                if (std::fabs(gvec[j + 1]) <= cycle_target || hn <= 1e-14 * std::sqrt(ww)) break;
+            }
+            // y = H^-1 g;  X += sum_i y_i s_i V_i
+            Coefs cf;
+            for (int i = cols - 1; i >= 0; --i) {
+                double s = gvec[i];
+                for (int l = i + 1; l < cols; ++l) s -= H[i * m + l] * y[l];
+                y[i] = H[i * m + i] != 0 ? s / H[i * m + i] : 0.0;
+            }
+            for (int i = 0; i < cols; ++i) cf.a[i] = y[i] * sv[i];
+            S.timed(kUpd, 4 * Nd * (16 + kb * cols),
+                    [&] { hipLaunchKernelGGL((k_update_x<KT>), gv, bl, 0, S.st, X, V, stride, cols, cf, n4); });
+            RAD_TRY(residual());
+            beta = std::sqrt(nrm[4]);
+        }
+        st.krylov_iters += its;
+
+        // ---- exchange: per-cell Newton for T, diagnostics of the iteration
+        S.timed(K_EXCHANGE, Nd * (2 * cb + 16 + 64 + 40),
+                [&] { hipLaunchKernelGGL((k_exchange<CT>), gc, bl, 0, S.st, g, rho, kP, S.Tn, Tc, X, X0, part); });
+        S.reduce(S.L.nblk_cells, 8, 8, sm + SM_RED);
+        RAD_TRY(S.read(SM_RED, 8));
+        const double *e = h + SM_RED;
+        resT = e[1] > 0 ? std::sqrt(e[0] / e[1]) : std::sqrt(e[0]);
+        const double cE = e[4] > 0 ? std::sqrt(e[3] / e[4]) : 0.0;
+        const double cF = (e[6] + e[4]) > 0 ? std::sqrt(e[5]) / (std::sqrt(e[6]) + std::sqrt(e[4])) : 0.0;
+        const double cT = e[1] > 0 ? std::sqrt(e[2] / e[1]) : 0.0;
+        st.rel_change = std::max(cE, std::max(cF, cT));
+        st.neg_cells = (int)e[7];
+        st.picard_iters = k + 1;
+    }
+    S.timed(K_COMMIT, Nd * 80, [&] { hipLaunchKernelGGL(k_commit, gc, bl, 0, S.st, N, g.c, X, Tc, S.E, S.F, S.T); });
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(S.st));
+    prof_resolve();
+    st.status = status;
+    if (status != RAD_OK)
+        return fail(status, "not converged: scaled residual %.3e after %d Picard iterations", st.scaled_residual,
+                    st.picard_iters);
+    return RAD_OK;
+}
+
+double *pinned_staging()
+{
+    static thread_local double *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, SM_TOTAL * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        buf = nullptr;
+    return buf;
+}
+
+template <class AT, class CT>
+void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, const void *rho, const void *kR,
+                       const void *f, double c, hipStream_t st)
+{
+    const dim3 gc((unsigned)((g.N + kBlock - 1) / kBlock)), bl(kBlock);
+    hipLaunchKernelGGL((k_apply<AT, CT>), gc, bl, 0, st, g, (const CT *)f, (const AT *)nullptr, (const CT *)rho,
+                       (const CT *)kR, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y, 0,
+                       (AT)(1.0 / c), (AT)c);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t *p)
+{
+    if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
+    return layout((long long)nx * ny * nz, *p).total;
+}
+
+extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                        const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                        const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
+                        rad_stats_t *stats)
+{
+    clear_error();
+    auto t0 = std::chrono::steady_clock::now();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    if (!E || !F || !T_gas || !rho || !kappa_P || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
+    if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace) % 256) return fail(RAD_EINVAL, "workspace must be 256-byte aligned");
+    Solver S;
+    S.p = *p;
+    S.L = layout((long long)nx * ny * nz, *p);
+    if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
+    S.host = pinned_staging();
+    if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
+    S.g = make_grid(nx, ny, nz, bc, dt, dx, *p);
+    S.st = (hipStream_t)stream;
+    S.ws = (char *)workspace;
+    S.rho = rho;
+    S.kP = kappa_P;
+    S.kR = kappa_R;
+    S.f = f_ij;
+    S.En = E;
+    S.Fn = F;
+    S.Tn = T_gas;
+    S.E = E;
+    S.F = F;
+    S.T = T_gas;
+    std::memset(&S.stats, 0, sizeof(S.stats));
+    const bool mixed = p->prec == RAD_MIXED;
+    int rc;
+    if (p->coef_dtype == RAD_F64)
+        rc = mixed ? run_step<double, float>(S) : run_step<double, double>(S);
+    else
+        rc = mixed ? run_step<float, float>(S) : run_step<float, double>(S);
+    S.stats.status = rc;
+    S.stats.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S.stats;
+    return rc;
+}
+
+extern "C" int rad_residual(int nx, int ny, int nz, const double *E_n, const double *F_n, const double *T_n,
+                            const double *E, const double *F, const double *T, const void *rho, const void *kappa_P,
+                            const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6],
+                            const rad_params_t *p, double *R, void *stream)
+{
+    clear_error();
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    if (!E_n || !F_n || !T_n || !E || !F || !T || !rho || !kappa_P || !kappa_R || !f_ij || !R)
+        return fail(RAD_EINVAL, "NULL data pointer");
+    Grid g = make_grid(nx, ny, nz, bc, dt, dx, *p);
+    const dim3 gc((unsigned)((g.N + kBlock - 1) / kBlock)), bl(kBlock);
+    hipStream_t st = (hipStream_t)stream;
+    // the state's own temperature is the emission temperature: lagged form, T* = T
+    if (p->coef_dtype == RAD_F64)
+        hipLaunchKernelGGL((k_residual<double, double, double, RES_PHYSICAL>), gc, bl, 0, st, g, 0, E_n, F_n, T_n, T,
+                           (const double *)rho, (const double *)kappa_P, (const double *)kappa_R,
+                           (const double *)f_ij, E, F, 1.0 / p->c, (double *)nullptr, (double *)nullptr, R,
+                           (double *)nullptr);
+    else
+        hipLaunchKernelGGL((k_residual<float, double, double, RES_PHYSICAL>), gc, bl, 0, st, g, 0, E_n, F_n, T_n, T,
+                           (const float *)rho, (const float *)kappa_P, (const float *)kappa_R, (const float *)f_ij,
+                           E, F, 1.0 / p->c, (double *)nullptr, (double *)nullptr, R, (double *)nullptr);
+    HIP_TRY(hipGetLastError());
+    return RAD_OK;
+}
+
+extern "C" int rad_face_speeds(int nx, int ny, int nz, const void *rho, const void *kappa_R, const void *f_ij,
+                               double dx, const int bc[6], const rad_params_t *p, double *C, void *stream)
+{
+    clear_error();
+    RAD_TRY(check_grid_args(nx, ny, nz, 1.0, dx, bc, p, false));
+    if (!rho || !kappa_R || !f_ij || !C) return fail(RAD_EINVAL, "NULL data pointer");
+    // the wave speed does not depend on dt: evaluate with dt = dx / c (nu = 1)
+    Grid g = make_grid(nx, ny, nz, bc, dx / p->c, dx, *p);
+    const dim3 gc((unsigned)((g.N + kBlock - 1) / kBlock)), bl(kBlock);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->coef_dtype == RAD_F64)
+        hipLaunchKernelGGL((k_face_speeds<double>), gc, bl, 0, st, g, (const double *)rho, (const double *)kappa_R,
+                           (const double *)f_ij, C);
+    else
+        hipLaunchKernelGGL((k_face_speeds<float>), gc, bl, 0, st, g, (const float *)rho, (const float *)kappa_R,
+                           (const float *)f_ij, C);
+    HIP_TRY(hipGetLastError());
+    return RAD_OK;
+}
+
+extern "C" int rad_apply(int nx, int ny, int nz, const void *x, void *y, const void *dE, const void *rho,
+                         const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6],
+                         const rad_params_t *p, int dtype, void *stream)
+{
+    clear_error();
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    if (!x || !y || !dE || !rho || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
+    if (dtype != RAD_F64 && dtype != RAD_F32) return fail(RAD_EINVAL, "dtype must be RAD_F64 or RAD_F32");
+    Grid g = make_grid(nx, ny, nz, bc, dt, dx, *p);
+    hipStream_t st = (hipStream_t)stream;
+    const bool c32 = p->coef_dtype == RAD_F32;
+    if (dtype == RAD_F64) {
+        if (c32)
+            launch_apply_phys<double, float>(g, x, y, dE, rho, kappa_R, f_ij, p->c, st);
+        else
+            launch_apply_phys<double, double>(g, x, y, dE, rho, kappa_R, f_ij, p->c, st);
+    } else {
+        if (c32)
+            launch_apply_phys<float, float>(g, x, y, dE, rho, kappa_R, f_ij, p->c, st);
+        else
+            launch_apply_phys<float, double>(g, x, y, dE, rho, kappa_R, f_ij, p->c, st);
+    }
+    HIP_TRY(hipGetLastError());
+    return RAD_OK;
+}
+
+extern "C" int rad_exchange(long long n, const double *E, const double *T_n, double *T, const void *rho,
+                            const void *kappa_P, double dt, const rad_params_t *p, void *stream)
+{
+    clear_error();
+    if (!p) return fail(RAD_EINVAL, "params is NULL");
+    RAD_TRY(check_params(p));
+    if (n < 1) return fail(RAD_EINVAL, "n must be >= 1");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(RAD_EINVAL, "dt must be positive and finite");
+    if (!E || !T_n || !T || !rho || !kappa_P) return fail(RAD_EINVAL, "NULL data pointer");
+    Grid g;
+    std::memset(&g, 0, sizeof(g));
+    g.N = n;
+    g.cdt = p->c * dt;
+    g.aR = p->a_R;
+    g.cv = p->c_v;
+    g.c = p->c;
+    const dim3 gc((unsigned)((n + kBlock - 1) / kBlock)), bl(kBlock);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->coef_dtype == RAD_F64)
+        hipLaunchKernelGGL((k_exchange_only<double>), gc, bl, 0, st, n, g, (const double *)rho,
+                           (const double *)kappa_P, E, T_n, T);
+    else
+        hipLaunchKernelGGL((k_exchange_only<float>), gc, bl, 0, st, n, g, (const float *)rho, (const float *)kappa_P,
+                           E, T_n, T);
+    HIP_TRY(hipGetLastError());
+    return RAD_OK;
+}

@@ -1,0 +1,297 @@
+"""ctypes binding of libvettam_rad.so (the C ABI in include/vettam_rad.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors, workspaces) and the current
+stream; nothing here computes on the data.  If the library is missing the
+import of this module fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvettam_rad.so")
+
+RAD_OK, RAD_NOT_CONVERGED = 0, 1
+RAD_EINVAL, RAD_ENOMEM, RAD_EHIP, RAD_ENOTIMPL, RAD_EDATA = -1, -2, -3, -4, -5
+BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
+PREC = {"fp64": 0, "mixed": 1}
+MODE = {"lagged": 0, "linearised": 1}
+DTYPE = {"f64": 0, "f32": 1}
+
+
+class Params(ct.Structure):
+    _fields_ = [("c", ct.c_double), ("a_R", ct.c_double), ("c_v", ct.c_double), ("tol", ct.c_double),
+                ("eps_R", ct.c_double), ("eps_P", ct.c_double), ("max_picard", ct.c_int),
+                ("max_krylov", ct.c_int), ("gmres_m", ct.c_int), ("prec", ct.c_int), ("mode", ct.c_int),
+                ("coef_dtype", ct.c_int)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("status", ct.c_int), ("picard_iters", ct.c_int), ("krylov_iters", ct.c_int),
+                ("refine_sweeps", ct.c_int), ("neg_cells", ct.c_int), ("bad_cells", ct.c_int),
+                ("scaled_residual", ct.c_double), ("res_E", ct.c_double), ("res_F", ct.c_double),
+                ("res_T", ct.c_double), ("rel_change", ct.c_double), ("t_total_ms", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BlockDesc(ct.Structure):
+    _fields_ = [("n", ct.c_int), ("ng", ct.c_int), ("dx", ct.c_double), ("dt", ct.c_double),
+                ("off", ct.c_longlong)]
+
+
+class RadError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rad error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2202_08778_amd.build.build()")
+    L = ct.CDLL(LIB_PATH)
+    P, I, D, LL, SZ = ct.c_void_p, ct.c_int, ct.c_double, ct.c_longlong, ct.c_size_t
+    IA6 = ct.POINTER(ct.c_int)
+    PP = ct.POINTER(Params)
+    L.rad_default_params.argtypes = [PP]
+    L.rad_default_params.restype = None
+    L.rad_workspace_bytes.argtypes = [I, I, I, PP]
+    L.rad_workspace_bytes.restype = SZ
+    L.rad_step.argtypes = [I, I, I, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
+    L.rad_step.restype = I
+    L.rad_residual.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, D, D, IA6, PP, P, P]
+    L.rad_residual.restype = I
+    L.rad_face_speeds.argtypes = [I, I, I, P, P, P, D, IA6, PP, P, P]
+    L.rad_face_speeds.restype = I
+    L.rad_apply.argtypes = [I, I, I, P, P, P, P, P, P, D, D, IA6, PP, I, P]
+    L.rad_apply.restype = I
+    L.rad_exchange.argtypes = [LL, P, P, P, P, P, D, PP, P]
+    L.rad_exchange.restype = I
+    L.rad_batched_workspace_bytes.argtypes = [I, ct.POINTER(BlockDesc), PP]
+    L.rad_batched_workspace_bytes.restype = SZ
+    L.rad_plan_batched.argtypes = [I, ct.POINTER(BlockDesc), PP, P, SZ, P, ct.POINTER(P)]
+    L.rad_plan_batched.restype = I
+    L.rad_autotune_scratch_bytes.argtypes = [P]
+    L.rad_autotune_scratch_bytes.restype = SZ
+    L.rad_autotune_batched.argtypes = [P, P, P, P, P, P, P, P, P, SZ, P]
+    L.rad_autotune_batched.restype = I
+    L.rad_step_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
+    L.rad_step_batched.restype = I
+    L.rad_plan_destroy.argtypes = [P]
+    L.rad_plan_destroy.restype = None
+    L.rad_profile_enable.argtypes = [I]
+    L.rad_profile_enable.restype = None
+    L.rad_profile_reset.argtypes = []
+    L.rad_profile_reset.restype = None
+    L.rad_profile_count.argtypes = []
+    L.rad_profile_count.restype = I
+    L.rad_profile_get.argtypes = [I, ct.POINTER(ct.c_char_p), ct.POINTER(D), ct.POINTER(D), ct.POINTER(LL)]
+    L.rad_profile_get.restype = I
+    L.rad_last_error.argtypes = []
+    L.rad_last_error.restype = ct.c_char_p
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_residual", "rad_face_speeds",
+            "rad_apply", "rad_exchange", "rad_batched_workspace_bytes", "rad_plan_batched",
+            "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_destroy",
+            "rad_profile_enable", "rad_profile_reset", "rad_profile_count", "rad_profile_get", "rad_last_error")
+
+
+def last_error() -> str:
+    return lib.rad_last_error().decode()
+
+
+def params(**kw) -> Params:
+    """rad_params_t with library defaults, overridden by keyword (strings accepted for enums)."""
+    p = Params()
+    lib.rad_default_params(ct.byref(p))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PREC[v]
+        elif k == "mode" and isinstance(v, str):
+            v = MODE[v]
+        elif k == "coef_dtype" and isinstance(v, str):
+            v = DTYPE[v]
+        setattr(p, k, v)
+    return p
+
+
+def bc_array(bc):
+    if isinstance(bc, str):
+        bc = (bc,) * 6
+    if len(bc) == 3:
+        bc = (bc[0], bc[0], bc[1], bc[1], bc[2], bc[2])
+    return (ct.c_int * 6)(*[BC[b] if isinstance(b, str) else int(b) for b in bc])
+
+
+def _check(rc, allow=(RAD_OK,)):
+    if rc not in allow:
+        raise RadError(rc, last_error())
+    return rc
+
+
+# ------------------------------------------------------------ torch marshalling
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _coef_dtype(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError("coefficients must be float64 or float32")
+
+
+def workspace_bytes(shape, p: Params) -> int:
+    nz, ny, nx = shape
+    return int(lib.rad_workspace_bytes(nx, ny, nz, ct.byref(p)))
+
+
+def alloc_workspace(nbytes, device=None):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace=None, stream=None,
+             check=True):
+    """One implicit step in place on device tensors E (nz,ny,nx), F (3,...), T (...) (float64);
+    rho, kappa_P, kappa_R, f (6,...) of one float dtype.  Returns the stats dict."""
+    torch = _torch()
+    nz, ny, nx = E.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
+            _ptr(rho, cd, N, "rho"), _ptr(kappa_P, cd, N, "kappa_P"), _ptr(kappa_R, cd, N, "kappa_R"),
+            _ptr(f, cd, 6 * N, "f")]
+    need = int(lib.rad_workspace_bytes(nx, ny, nz, ct.byref(p)))
+    if workspace is None:
+        workspace = alloc_workspace(need, E.device)
+    st = Stats()
+    rc = lib.rad_step(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
+                      _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
+                      _stream(stream), ct.byref(st))
+    if check:
+        _check(rc)
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def rad_residual(En, Fn, Tn, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, R=None, stream=None):
+    """Nonlinear residual (5, nz, ny, nx) float64 of a state; asynchronous on the stream."""
+    torch = _torch()
+    nz, ny, nx = E.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    if R is None:
+        R = torch.empty((5, nz, ny, nx), dtype=torch.float64, device=E.device)
+    f64 = torch.float64
+    _check(lib.rad_residual(nx, ny, nz, _ptr(En, f64, N, "En"), _ptr(Fn, f64, 3 * N, "Fn"),
+                            _ptr(Tn, f64, N, "Tn"), _ptr(E, f64, N, "E"), _ptr(F, f64, 3 * N, "F"),
+                            _ptr(T, f64, N, "T"), _ptr(rho, cd, N, "rho"), _ptr(kappa_P, cd, N, "kappa_P"),
+                            _ptr(kappa_R, cd, N, "kappa_R"), _ptr(f, cd, 6 * N, "f"), float(dt), float(dx),
+                            bc_array(bc), ct.byref(p), _ptr(R, f64, 5 * N, "R"), _stream(stream)))
+    return R
+
+
+def rad_face_speeds(rho, kappa_R, f, dx, bc, p: Params, C=None, stream=None):
+    torch = _torch()
+    nz, ny, nx = rho.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    if C is None:
+        C = torch.empty((3, nz, ny, nx), dtype=torch.float64, device=rho.device)
+    _check(lib.rad_face_speeds(nx, ny, nz, _ptr(rho, cd, N, "rho"), _ptr(kappa_R, cd, N, "kappa_R"),
+                               _ptr(f, cd, 6 * N, "f"), float(dx), bc_array(bc), ct.byref(p),
+                               _ptr(C, torch.float64, 3 * N, "C"), _stream(stream)))
+    return C
+
+
+def rad_apply(x, dE, rho, kappa_R, f, dt, dx, bc, p: Params, y=None, stream=None):
+    """y = A x for x (4, nz, ny, nx) of float64 or float32 (physical units)."""
+    torch = _torch()
+    _, nz, ny, nx = x.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    dt_code = 0 if x.dtype == torch.float64 else 1
+    if y is None:
+        y = torch.empty_like(x)
+    _check(lib.rad_apply(nx, ny, nz, _ptr(x, x.dtype, 4 * N, "x"), _ptr(y, x.dtype, 4 * N, "y"),
+                         _ptr(dE, x.dtype, N, "dE"), _ptr(rho, cd, N, "rho"), _ptr(kappa_R, cd, N, "kappa_R"),
+                         _ptr(f, cd, 6 * N, "f"), float(dt), float(dx), bc_array(bc), ct.byref(p), dt_code,
+                         _stream(stream)))
+    return y
+
+
+def rad_exchange(E, Tn, rho, kappa_P, dt, p: Params, T=None, stream=None):
+    torch = _torch()
+    n = E.numel()
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    if T is None:
+        T = torch.empty_like(E)
+    f64 = torch.float64
+    _check(lib.rad_exchange(n, _ptr(E, f64, n, "E"), _ptr(Tn, f64, n, "Tn"), _ptr(T, f64, n, "T"),
+                            _ptr(rho, cd, n, "rho"), _ptr(kappa_P, cd, n, "kappa_P"), float(dt), ct.byref(p),
+                            _stream(stream)))
+    return T
+
+
+def profile(on=True):
+    lib.rad_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib.rad_profile_reset()
+
+
+def profile_read():
+    """{kernel class: {"ms", "bytes", "launches"}} accumulated since the last reset."""
+    out = {}
+    for i in range(lib.rad_profile_count()):
+        name, ms, b, n = ct.c_char_p(), ct.c_double(), ct.c_double(), ct.c_longlong()
+        _check(lib.rad_profile_get(i, ct.byref(name), ct.byref(ms), ct.byref(b), ct.byref(n)))
+        out[name.value.decode()] = {"ms": ms.value, "bytes": b.value, "launches": n.value}
+    return out

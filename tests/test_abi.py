@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every symbol the header declares, and rejects bad arguments
+on the host before touching the device (runs without a GPU)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vettam_rad.h")
+
+
+@pytest.fixture(scope="module")
+def rad():
+    from paper_2202_08778_amd import rad as r
+    return r
+
+
+def _declared():
+    src = open(HEADER).read()
+    decl = r"^(?:int|size_t|void|const char \*)\s*\*?\s*(rad_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol(rad):
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(rad.lib, n), n
+        assert n in rad.EXPORTED, n
+
+
+def test_defaults(rad):
+    p = rad.params()
+    assert (p.c, p.a_R, p.c_v) == (1.0, 1.0, 1.0)
+    assert p.gmres_m == 30 and p.prec == 0 and p.mode == 1
+
+
+def _step(rad, p, nx=4, ny=4, nz=4, ptr=0x1000, bc="periodic", dt=1.0, dx=1.0, ws=None, wsb=None):
+    st = rad.Stats()
+    need = rad.lib.rad_workspace_bytes(nx, ny, nz, ct.byref(p))
+    ws = ws if ws is not None else 0x10000
+    wsb = wsb if wsb is not None else need
+    P = lambda: ptr
+    return rad.lib.rad_step(nx, ny, nz, P(), P(), P(), P(), P(), P(), P(), dt, dx, rad.bc_array(bc),
+                            ct.byref(p), ws, wsb, None, ct.byref(st))
+
+
+@pytest.mark.parametrize("case,msg", [
+    (dict(nx=0), "extents"),
+    (dict(dt=-1.0), "dt"),
+    (dict(dt=float("nan")), "dt"),
+    (dict(dx=0.0), "dx"),
+    (dict(bc=("periodic", "outflow", "periodic", "periodic", "periodic", "periodic")), "pairs"),
+    (dict(bc="dirichlet"), "boundary"),
+    (dict(ptr=0), "NULL"),
+    (dict(ws=0), "workspace"),
+    (dict(ws=0x10001), "aligned"),
+    (dict(wsb=16), "too small"),
+])
+def test_rad_step_rejects_bad_arguments_on_host(rad, case, msg):
+    p = rad.params()
+    rc = _step(rad, p, **case)
+    assert rc in (rad.RAD_EINVAL, rad.RAD_ENOMEM)
+    assert msg in rad.last_error()
+
+
+@pytest.mark.parametrize("field,val", [("gmres_m", 0), ("gmres_m", 65), ("c", 0.0), ("tol", 0.0), ("prec", 7),
+                                       ("mode", 3), ("coef_dtype", 2), ("max_picard", 0), ("a_R", -1.0)])
+def test_rad_step_rejects_bad_params(rad, field, val):
+    p = rad.params()
+    setattr(p, field, val)
+    assert _step(rad, p) == rad.RAD_EINVAL
+    assert rad.lib.rad_workspace_bytes(4, 4, 4, ct.byref(p)) == 0
+
+
+def test_workspace_grows_with_restart_length_and_precision(rad):
+    a = rad.lib.rad_workspace_bytes(32, 32, 32, ct.byref(rad.params(gmres_m=10)))
+    b = rad.lib.rad_workspace_bytes(32, 32, 32, ct.byref(rad.params(gmres_m=20)))
+    c = rad.lib.rad_workspace_bytes(32, 32, 32, ct.byref(rad.params(gmres_m=20, prec="mixed")))
+    assert 0 < a < b and c < b
+    # basis of (m+1) 4-component vectors dominates
+    assert b - a >= 10 * 4 * 32 ** 3 * 8
+
+
+def test_other_entry_points_validate(rad):
+    p = rad.params()
+    bc = rad.bc_array("periodic")
+    assert rad.lib.rad_apply(4, 4, 4, None, None, None, None, None, None, 1.0, 1.0, bc, ct.byref(p), 0,
+                             None) == rad.RAD_EINVAL
+    assert rad.lib.rad_apply(4, 4, 4, 8, 8, 8, 8, 8, 8, 1.0, 1.0, bc, ct.byref(p), 5, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_exchange(0, 8, 8, 8, 8, 8, 1.0, ct.byref(p), None) == rad.RAD_EINVAL
+    assert rad.lib.rad_face_speeds(4, 4, 4, None, 8, 8, 1.0, bc, ct.byref(p), 8, None) == rad.RAD_EINVAL

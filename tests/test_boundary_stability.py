@@ -1,0 +1,38 @@
+"""Why the large mixed-depth workloads use periodic boundaries.
+
+The zero-gradient outflow condition (Sec. 3.3) read implicitly -- the ghost cell equals the
+current boundary cell -- makes the boundary face flux the cell's own physical flux, which couples
+E and F of that cell with weight nu/2 and no dissipation.  With dt of tens of light-crossing
+times and thick/thin contrast at the boundary, the Jacobi-scaled operator of one Picard iteration
+then has eigenvalues with negative real part (a growing boundary mode).  The same medium with
+periodic faces, or with outflow faces at a few crossing times, is positive definite in that
+sense.  Dense operators are assembled from the oracle's apply on a 6^3 grid."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_08778_amd import workloads as W
+
+
+def _min_real_eig(d):
+    P = oracle.Problem(d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"])
+    sh = d["E"].shape
+    N = int(np.prod(sh))
+    sP = d["c"] * d["dt"] * d["rho"] * d["kP"]
+    T, alpha = d["T"], d["rho"] * d["cv"]
+    eta = 4 * sP * T ** 3 / (alpha + 4 * sP * T ** 3)
+    dE = 1 + sP * (1 - eta)
+    A = np.zeros((4 * N, 4 * N))
+    for k in range(4 * N):
+        x = np.zeros(4 * N)
+        x[k] = 1.0
+        A[:, k] = P.apply(x.reshape((4,) + sh), dE).ravel()
+    return np.linalg.eigvals(A / np.diag(A)[:, None]).real.min()
+
+
+@pytest.mark.parametrize("bc,dt_cross,stable", [("outflow", 50.0, False), ("periodic", 50.0, True),
+                                                ("outflow", 2.0, True)])
+def test_implicit_outflow_operator_definiteness(bc, dt_cross, stable):
+    d = W.mixed_depth(shape=(6, 6, 6), seed=2, steps=1, bc=bc, dt_cross=dt_cross)
+    lam = _min_real_eig(d)
+    assert (lam > 0) == stable, lam
