@@ -33,11 +33,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile):
+def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30):
     """Warm up, restore the initial state, then time `steps` consecutive rad_step calls."""
     E, F, T = (t.clone() for t in state0)
     rho, kP, kR, f = coefs
-    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol)
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol, gmres_m=m)
     p.coef_dtype = 1 if rho.dtype == torch.float32 else 0
     ws = rad.alloc_workspace(rad.workspace_bytes(E.shape, p))
     for s in range(warmup):
@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid edge (the metric is quoted at 256)")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--gmres-m", type=int, default=30)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
@@ -123,7 +124,8 @@ def main():
     N = n ** 3
 
     log("mixed path (FP32 Krylov + FP64 residual/refinement/exchange, FP32 coefficient storage):")
-    mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile)
+    mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile,
+                     args.gmres_m)
     value = N * args.steps / mixed["seconds"]
     out_m = [t.cpu().numpy() for t in mixed["state"]]
 
@@ -131,7 +133,7 @@ def main():
     if not args.no_fp64:
         log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
         c64 = tuple(dev(d[k]) for k in ("rho", "kP", "kR", "f"))
-        fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False)
+        fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False, args.gmres_m)
         del c64
 
     res = {
@@ -149,7 +151,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"mixed-depth medium {n}^3, periodic, dt = 50 light-crossing times, "
                                f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
-                   "cells": N, "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
+                   "cells": N, "gmres_m": args.gmres_m,
+                   "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
         "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
         "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / args.steps,
         "converged_steps": sum(1 for s in mixed["stats"] if s["rc"] == 0),

@@ -98,48 +98,57 @@ __device__ __forceinline__ long long neighbour(const Grid &g, int i, int j, int 
     return g.bclo[d] == BC_PERIODIC ? c + (long long)(n - 1) * stride : c;
 }
 
-// Transport part of the operator at one cell.  `ld(q, idx)` returns component q
-// (0: E, 1..3: Ft) of the operand at cell idx; `fl(t, idx)` the tensor plane t;
-// `sr(idx)` the cell's sR.  Accumulates nu * div(Phi) into div[4] and returns
-// the sum of Ct over faces whose neighbour is another cell (diagonal of the
-// transport part is 0.5 nu times that) and over all six faces (for scaling).
+// Accumulate the HLLE flux of the face on side `side` (0: low, 1: high) along
+// axis d into the divergence sums dE, dF of the centre cell.  c* are the
+// centre's state (E, Ft) and tensor row d, n* the neighbour's; C the face speed.
+template <class T>
+__device__ __forceinline__ void face_flux_acc(int d, int side, T C, T Ec, const T (&Fc)[3], const T (&fcr)[3], T En,
+                                              const T (&Fn)[3], const T (&fnr)[3], T &dE, T (&dF)[3])
+{
+    const T EL = side ? Ec : En, ER = side ? En : Ec;
+    const T *FL_ = side ? Fc : Fn;
+    const T *FR_ = side ? Fn : Fc;
+    const T *fL = side ? fcr : fnr;
+    const T *fR = side ? fnr : fcr;
+    const T sgn = side ? T(1) : T(-1);
+    const T phiE = T(0.5) * (FL_[d] + FR_[d]) - T(0.5) * C * (ER - EL);
+    dE += sgn * phiE;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const T phiF = T(0.5) * (fL[q] * EL + fR[q] * ER) - T(0.5) * C * (FR_[q] - FL_[q]);
+        dF[q] += sgn * phiF;
+    }
+}
+
+// Transport part of the operator at one cell of a uniform grid.  `ld(q, idx)`
+// returns component q (0: E, 1..3: Ft) of the operand at cell idx; `fl(t, idx)`
+// the tensor plane t; `sr(idx)` the cell's sR.  Returns nu * div(Phi) in
+// div[4], the sum of Ct over faces whose neighbour is another cell (the
+// transport part's diagonal is 0.5 nu times that) and over all six faces.
 template <class T, class LD, class FL, class SR>
 __device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, long long c, LD ld, FL fl, SR sr,
                                           T div[4], T &sumC_nb, T &sumC_all)
 {
     const T tk = (T)g.tau_k;
-    T Ec = ld(0, c);
-    T Fc[3] = {ld(1, c), ld(2, c), ld(3, c)};
-    T sRc = sr(c);
+    const T Ec = ld(0, c);
+    const T Fc[3] = {ld(1, c), ld(2, c), ld(3, c)};
+    const T sRc = sr(c);
     T dE = 0, dF[3] = {0, 0, 0};
     sumC_nb = 0;
     sumC_all = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        T fcr[3] = {fl(tens_row(d, 0), c), fl(tens_row(d, 1), c), fl(tens_row(d, 2), c)};
+        const T fcr[3] = {fl(tens_row(d, 0), c), fl(tens_row(d, 1), c), fl(tens_row(d, 2), c)};
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-            long long nb = neighbour(g, i, j, k, c, d, side);
-            T En = ld(0, nb);
-            T Fn[3] = {ld(1, nb), ld(2, nb), ld(3, nb)};
-            T fnr[3] = {fl(tens_row(d, 0), nb), fl(tens_row(d, 1), nb), fl(tens_row(d, 2), nb)};
-            T C = face_speed<T>(fcr[d], fnr[d], sRc, sr(nb), tk);
+            const long long nb = neighbour(g, i, j, k, c, d, side);
+            const T En = ld(0, nb);
+            const T Fn[3] = {ld(1, nb), ld(2, nb), ld(3, nb)};
+            const T fnr[3] = {fl(tens_row(d, 0), nb), fl(tens_row(d, 1), nb), fl(tens_row(d, 2), nb)};
+            const T C = face_speed<T>(fcr[d], fnr[d], sRc, sr(nb), tk);
             sumC_all += C;
             if (nb != c) sumC_nb += C;
-            // left/right states of the face
-            const T EL = side ? Ec : En, ER = side ? En : Ec;
-            const T *FL_ = side ? Fc : Fn;
-            const T *FR_ = side ? Fn : Fc;
-            const T *fL = side ? fcr : fnr;
-            const T *fR = side ? fnr : fcr;
-            T phiE = T(0.5) * (FL_[d] + FR_[d]) - T(0.5) * C * (ER - EL);
-            T sgn = side ? T(1) : T(-1);
-            dE += sgn * phiE;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                T phiF = T(0.5) * (fL[q] * EL + fR[q] * ER) - T(0.5) * C * (FR_[q] - FL_[q]);
-                dF[q] += sgn * phiF;
-            }
+            face_flux_acc<T>(d, side, C, Ec, Fc, fcr, En, Fn, fnr, dE, dF);
         }
     }
     const T nu = (T)g.nu;
@@ -148,6 +157,36 @@ __device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, lo
     div[2] = nu * dF[1];
     div[3] = nu * dF[2];
 }
+
+// Gas temperature of eq. PicardTemp at one cell: the T >= 0 with
+// alpha (T - Tn) + sP (aR T^4 - E) = 0.  The function is increasing and convex
+// for T >= 0, so Newton's method (analytic derivative) started above the root,
+// at the smaller of the two one-term bounds, descends monotonically and stops
+// at round-off when an iterate no longer decreases.  With no non-negative root
+// (alpha Tn + sP E <= 0) it returns 0 and sets neg.
+__device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP, double aR, double E, bool &neg)
+{
+    if (sP == 0.0) return Tn;
+    const double rhs = alpha * Tn + sP * E;
+    if (!(rhs > 0.0)) {
+        neg = true;
+        return 0.0;
+    }
+    // start above the root (smaller of the two one-term bounds); g is convex and
+    // increasing so Newton descends monotonically; stop when it stops decreasing
+    double T = sqrt(sqrt(rhs / (sP * aR)));
+    if (alpha > 0.0 && rhs / alpha < T) T = rhs / alpha;
+    for (int it = 0; it < 200; ++it) {
+        const double T3 = T * T * T;
+        const double gv = alpha * (T - Tn) + sP * (aR * T3 * T - E);
+        const double dg = alpha + 4.0 * sP * aR * T3;
+        const double Tnew = T - gv / dg;
+        if (!(Tnew < T)) break;
+        T = Tnew;
+    }
+    return T;
+}
+
 
 // ------------------------------------------------------------------ reductions
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,15 @@ int fail(int status, const char *fmt, ...)
 }
 
 void clear_error() { g_err.clear(); }
+
+bool trace_enabled()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("VETTAM_RAD_TRACE");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
 
 int check_params(const rad_params_t *p)
 {

@@ -14,8 +14,10 @@ namespace vr {
 int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 int check_params(const rad_params_t *p);
+// VETTAM_RAD_TRACE=1 in the environment: per-iteration solver trace on stderr
+bool trace_enabled();
 
-inline size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
+__host__ __device__ inline size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Kernel-class profiler (see rad_profile_* in the C ABI).  prof_begin returns a
 // token (-1 when profiling is off); prof_end records the closing event and the

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -171,27 +172,78 @@ __global__ void __launch_bounds__(kBlock)
     for (int q = 0; q < 3; ++q) y[(1 + q) * N + c] = yFq[q] * yF;
 }
 
-// Raw dots <V_i, w> for i in [i0, i0+cnt) (cnt <= NV) and <w, w>, FP64 accumulation.
+// Four consecutive elements of a Krylov vector, loaded/stored as one 16-byte
+// (FP32) or two 16-byte (FP64) vector accesses and widened to FP64.
+template <class KT>
+struct Quad;
+template <>
+struct Quad<float> {
+    static __device__ __forceinline__ void load(const float *p, double (&v)[4])
+    {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+    static __device__ __forceinline__ void store(float *p, const double (&v)[4], double (&r)[4])
+    {
+        float4 q;
+        q.x = (float)v[0]; q.y = (float)v[1]; q.z = (float)v[2]; q.w = (float)v[3];
+        *reinterpret_cast<float4 *>(p) = q;
+        r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
+    }
+};
+template <>
+struct Quad<double> {
+    static __device__ __forceinline__ void load(const double *p, double (&v)[4])
+    {
+        const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+    static __device__ __forceinline__ void store(double *p, const double (&v)[4], double (&r)[4])
+    {
+        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+        for (int k = 0; k < 4; ++k) r[k] = v[k];
+    }
+};
+
+// Raw dots <V_i, w> for i in [i0, i0+NV) and <w, w>, FP64 accumulation.  The
+// vector count is a template parameter so all NV+1 loads of an element group
+// are issued back to back.  n (= 4N) is a multiple of 4.
 template <class KT, int NV>
 __global__ void __launch_bounds__(kBlock)
-    k_multidot(const KT *__restrict__ V, long long stride, int i0, int cnt, const KT *__restrict__ w, long long n,
+    k_multidot(const KT *__restrict__ V, long long stride, int i0, const KT *__restrict__ w, long long n,
                double *partials)
 {
     double acc[NV + 1];
 #pragma unroll
     for (int q = 0; q <= NV; ++q) acc[q] = 0;
-    const long long step = (long long)gridDim.x * kBlock;
-    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += step) {
-        const double we = (double)w[e];
+    const long long step = (long long)gridDim.x * kBlock * 4;
+    const KT *Vb = V + (long long)i0 * stride;
+    for (long long e = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; e < n; e += step) {
+        double wv[4];
+        Quad<KT>::load(w + e, wv);
+        double vv[NV][4];
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (q < cnt) acc[q] += (double)V[(long long)(i0 + q) * stride + e] * we;
-        acc[NV] += we * we;
+        for (int q = 0; q < NV; ++q) Quad<KT>::load(Vb + (long long)q * stride + e, vv[q]);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] += vv[q][0] * wv[0] + vv[q][1] * wv[1] + vv[q][2] * wv[2] + vv[q][3] * wv[3];
+        acc[NV] += wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2] + wv[3] * wv[3];
     }
     block_store<NV + 1>(acc, partials, blockIdx.x);
 }
 
-// out = w - sum_i s_i^2 d_i V_i  (i < cnt), accumulating ||out||^2.  out may alias w.
+template <class KT, int NV>
+void launch_multidot(int cnt, dim3 g, hipStream_t st, const KT *V, long long stride, int i0, const KT *w, long long n,
+                     double *partials)
+{
+    if constexpr (NV > 1) {
+        if (cnt < NV) return launch_multidot<KT, NV - 1>(cnt, g, st, V, stride, i0, w, n, partials);
+    }
+    hipLaunchKernelGGL((k_multidot<KT, NV>), g, dim3(kBlock), 0, st, V, stride, i0, w, n, partials);
+}
+
+// out = w - sum_i s_i^2 d_i V_i  (i < cnt), accumulating ||out||^2 of the stored
+// (rounded) values.  out may alias w.
 template <class KT>
 __global__ void __launch_bounds__(kBlock)
     k_orth_update(const KT *__restrict__ V, long long stride, int cnt, const KT *w, KT *out,
@@ -201,13 +253,29 @@ __global__ void __launch_bounds__(kBlock)
     if (threadIdx.x < cnt) cf[threadIdx.x] = s[threadIdx.x] * s[threadIdx.x] * dots[threadIdx.x];
     __syncthreads();
     double acc[1] = {0};
-    const long long step = (long long)gridDim.x * kBlock;
-    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += step) {
-        double val = (double)w[e];
-        for (int i = 0; i < cnt; ++i) val -= cf[i] * (double)V[(long long)i * stride + e];
-        const KT st = (KT)val;
-        out[e] = st;
-        acc[0] += (double)st * (double)st;
+    const long long step = (long long)gridDim.x * kBlock * 4;
+    for (long long e = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; e < n; e += step) {
+        double val[4];
+        Quad<KT>::load(w + e, val);
+        int i = 0;
+        for (; i + 4 <= cnt; i += 4) {
+            double a[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Quad<KT>::load(V + (long long)(i + u) * stride + e, a[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) val[k] -= cf[i + u] * a[u][k];
+        }
+        for (; i < cnt; ++i) {
+            double a[4];
+            Quad<KT>::load(V + (long long)i * stride + e, a);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) val[k] -= cf[i] * a[k];
+        }
+        double r[4];
+        Quad<KT>::store(out + e, val, r);
+        acc[0] += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
     }
     block_store<1>(acc, partials, blockIdx.x);
 }
@@ -221,40 +289,23 @@ template <class KT>
 __global__ void __launch_bounds__(kBlock)
     k_update_x(double *__restrict__ X, const KT *__restrict__ V, long long stride, int cnt, Coefs cf, long long n)
 {
-    const long long step = (long long)gridDim.x * kBlock;
-    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += step) {
-        double acc = X[e];
-        for (int i = 0; i < cnt; ++i) acc += cf.a[i] * (double)V[(long long)i * stride + e];
-        X[e] = acc;
+    const long long step = (long long)gridDim.x * kBlock * 4;
+    for (long long e = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; e < n; e += step) {
+        double acc[4], r[4];
+        Quad<double>::load(X + e, acc);
+        for (int i = 0; i < cnt; ++i) {
+            double a[4];
+            Quad<KT>::load(V + (long long)i * stride + e, a);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += cf.a[i] * a[k];
+        }
+        Quad<double>::store(X + e, acc, r);
     }
 }
 
 // Per-cell exchange solve (eq. PicardTemp) for T with E = X_E; then the
 // diagnostics of the Picard iteration, and X0 = X.  Partials:
 //   [sum (R_T/W_T)^2, sum T^2, sum dT^2, sum dE^2, sum E^2, sum dFt^2, sum Ft^2, neg]
-__device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP, double aR, double E, bool &neg)
-{
-    if (sP == 0.0) return Tn;
-    const double rhs = alpha * Tn + sP * E;
-    if (!(rhs > 0.0)) {
-        neg = true;
-        return 0.0;
-    }
-    // start above the root (smaller of the two one-term bounds); g is convex and
-    // increasing so Newton descends monotonically; stop when it stops decreasing
-    double T = sqrt(sqrt(rhs / (sP * aR)));
-    if (alpha > 0.0 && rhs / alpha < T) T = rhs / alpha;
-    for (int it = 0; it < 200; ++it) {
-        const double T3 = T * T * T;
-        const double gv = alpha * (T - Tn) + sP * (aR * T3 * T - E);
-        const double dg = alpha + 4.0 * sP * aR * T3;
-        const double Tnew = T - gv / dg;
-        if (!(Tnew < T)) break;
-        T = Tnew;
-    }
-    return T;
-}
-
 template <class CT>
 __global__ void __launch_bounds__(kBlock)
     k_exchange(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP, const double *__restrict__ Tn,
@@ -410,7 +461,7 @@ struct Layout {
     size_t ksz;
 };
 
-long long vec_blocks(long long n) { return std::min<long long>((n + kBlock - 1) / kBlock, 2048); }
+long long vec_blocks(long long n) { return std::min<long long>((n / 4 + kBlock - 1) / kBlock, 2048); }
 
 Layout layout(long long N, const rad_params_t &p)
 {
@@ -553,15 +604,16 @@ int run_step(Solver &S)
     auto multidot = [&](int cnt, const KT *w) {
         for (int i0 = 0; i0 < cnt; i0 += 16) {
             const int c = std::min(16, cnt - i0);
-            S.timed(kDot, 4 * Nd * kb * (c + 1), [&] {
-                hipLaunchKernelGGL((k_multidot<KT, 16>), gv, bl, 0, S.st, V, stride, i0, c, w, n4, part);
-            });
-            S.reduce(S.L.nblk_vec, 17, 16, sm + SM_DOTS + i0, sm + SM_WW);
+            S.timed(kDot, 4 * Nd * kb * (c + 1),
+                    [&] { launch_multidot<KT, 16>(c, gv, S.st, V, stride, i0, w, n4, part); });
+            S.reduce(S.L.nblk_vec, c + 1, c, sm + SM_DOTS + i0, sm + SM_WW);
         }
     };
 
     double resT = 0;
     int status = RAD_NOT_CONVERGED;
+    const bool trace = trace_enabled();
+    int reorth = 0, cycles = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gvec(m + 1), y(m), sv(m + 1);
 
     for (int k = 0;; ++k) {
@@ -608,8 +660,10 @@ int run_step(Solver &S)
                 const double ww = h[SM_WW];
                 double nn = h[SM_NRM];
                 for (int i = 0; i <= j; ++i) H[i * m + j] = sv[i] * h[SM_DOTS + i];
-                // second Gram-Schmidt pass when the first removed more than half the norm
-                if (nn < 0.5 * ww) {
+                // classical Gram-Schmidt, one pass (as PETSc's default GMRES); a second pass
+                // only when cancellation left less than 1e-3 of the norm
+                if (nn < 1e-6 * ww) {
+                    ++reorth;
                     multidot(j + 1, vn);
                     S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
                         hipLaunchKernelGGL((k_orth_update<KT>), gv, bl, 0, S.st, V, stride, j + 1, vn, vn,
@@ -650,6 +704,10 @@ int run_step(Solver &S)
             S.timed(kUpd, 4 * Nd * (16 + kb * cols),
                     [&] { hipLaunchKernelGGL((k_update_x<KT>), gv, bl, 0, S.st, X, V, stride, cols, cf, n4); });
             RAD_TRY(residual());
+            ++cycles;
+            if (trace)
+                std::fprintf(stderr, "[rad]   cycle: %d Arnoldi steps, estimate %.3e, true %.3e (target %.3e)\n", cols,
+                             std::fabs(gvec[cols]), std::sqrt(nrm[4]), target);
             beta = std::sqrt(nrm[4]);
         }
         st.krylov_iters += its;
@@ -667,6 +725,12 @@ int run_step(Solver &S)
         st.rel_change = std::max(cE, std::max(cF, cT));
         st.neg_cells = (int)e[7];
         st.picard_iters = k + 1;
+        if (trace)
+            std::fprintf(stderr,
+                         "[rad] picard %d: residual %.3e (E %.2e F %.2e T %.2e) -> krylov %d (total %d, cycles %d, "
+                         "reorth %d), rel_change %.2e, neg %d\n",
+                         k, res, st.res_E, st.res_F, resT, its, st.krylov_iters, cycles, reorth, st.rel_change,
+                         st.neg_cells);
     }
     S.timed(K_COMMIT, Nd * 80, [&] { hipLaunchKernelGGL(k_commit, gc, bl, 0, S.st, N, g.c, X, Tc, S.E, S.F, S.T); });
     HIP_TRY(hipGetLastError());

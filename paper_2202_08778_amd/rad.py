@@ -295,3 +295,99 @@ def profile_read():
         _check(lib.rad_profile_get(i, ct.byref(name), ct.byref(ms), ct.byref(b), ct.byref(n)))
         out[name.value.decode()] = {"ms": ms.value, "bytes": b.value, "launches": n.value}
     return out
+
+
+# ------------------------------------------------------------------ batched
+
+STATS_DTYPE = None
+
+
+def _stats_dtype():
+    import numpy as np
+    global STATS_DTYPE
+    if STATS_DTYPE is None:
+        STATS_DTYPE = np.dtype([(k, np.int32 if t is ct.c_int else np.float64) for k, t in Stats._fields_])
+        assert STATS_DTYPE.itemsize == ct.sizeof(Stats)
+    return STATS_DTYPE
+
+
+def pack_blocks(blocks):
+    """Pack per-block padded arrays ((n+2ng)^3 each, from workloads.batched_blocks) into arenas.
+
+    Returns (descs: BlockDesc array, arenas: dict of numpy arrays E (A), F (3, A), T, rho, kP, kR (A),
+    f (6, A)) with block b's region at element offset descs[b].off of every arena."""
+    import numpy as np
+    nb = len(blocks)
+    descs = (BlockDesc * nb)()
+    off = 0
+    for b, blk in enumerate(blocks):
+        m = blk["n"] + 2 * blk["ng"]
+        descs[b].n, descs[b].ng, descs[b].dx, descs[b].dt, descs[b].off = blk["n"], blk["ng"], blk["dx"], blk["dt"], off
+        off += m ** 3
+    A = off
+    ar = {"E": np.empty(A), "F": np.empty((3, A)), "T": np.empty(A), "rho": np.empty(A), "kP": np.empty(A),
+          "kR": np.empty(A), "f": np.empty((6, A))}
+    for b, blk in enumerate(blocks):
+        o, sz = descs[b].off, (blk["n"] + 2 * blk["ng"]) ** 3
+        for k in ("E", "T", "rho", "kP", "kR"):
+            ar[k][o:o + sz] = blk[k].ravel()
+        for q in range(3):
+            ar["F"][q, o:o + sz] = blk["F"][q].ravel()
+        for q in range(6):
+            ar["f"][q, o:o + sz] = blk["f"][q].ravel()
+    return descs, ar
+
+
+class Plan:
+    """A batched plan: owns its device workspace (a torch tensor) and the library plan handle."""
+
+    def __init__(self, descs, p: Params, device="cuda", stream=None):
+        self.descs = descs
+        self.nblocks = len(descs)
+        self.p = Params.from_buffer_copy(p)
+        need = int(lib.rad_batched_workspace_bytes(self.nblocks, descs, ct.byref(self.p)))
+        if need == 0:
+            _check(RAD_EINVAL if not last_error() else -1)
+        self.workspace = alloc_workspace(need, device)
+        h = ct.c_void_p()
+        _check(lib.rad_plan_batched(self.nblocks, descs, ct.byref(self.p), _ptr(self.workspace, name="workspace"),
+                                    self.workspace.numel(), _stream(stream), ct.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lib is not None:
+            try:
+                lib.rad_plan_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self.handle = None
+
+    def _args(self, E, F, T, rho, kP, kR, f):
+        torch = _torch()
+        A = E.numel()
+        cd = rho.dtype
+        f64 = torch.float64
+        return [_ptr(E, f64, A, "E"), _ptr(F, f64, 3 * A, "F"), _ptr(T, f64, A, "T"), _ptr(rho, cd, A, "rho"),
+                _ptr(kP, cd, A, "kappa_P"), _ptr(kR, cd, A, "kappa_R"), _ptr(f, cd, 6 * A, "f")]
+
+    def autotune(self, E, F, T, rho, kP, kR, f, stream=None):
+        n = int(lib.rad_autotune_scratch_bytes(self.handle))
+        scratch = alloc_workspace(n, E.device)
+        _check(lib.rad_autotune_batched(self.handle, *self._args(E, F, T, rho, kP, kR, f),
+                                        _ptr(scratch, name="scratch"), scratch.numel(), _stream(stream)))
+        _torch().cuda.synchronize()
+
+    def step(self, E, F, T, rho, kP, kR, f, stats=None, stream=None):
+        """One step of every block (asynchronous).  Returns the device stats buffer (uint8 tensor)."""
+        torch = _torch()
+        if stats is None:
+            stats = torch.empty(self.nblocks * ct.sizeof(Stats), dtype=torch.uint8, device=E.device)
+        _check(lib.rad_step_batched(self.handle, *self._args(E, F, T, rho, kP, kR, f),
+                                    _ptr(stats, name="stats"), _stream(stream)))
+        return stats
+
+    @staticmethod
+    def read_stats(stats):
+        import numpy as np
+        return np.frombuffer(stats.cpu().numpy().tobytes(), dtype=_stats_dtype())

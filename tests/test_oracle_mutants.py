@@ -50,7 +50,8 @@ def test_pins_catch_planted_mistake(k, tmp_path):
     subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-I", os.path.join(ROOT, "oracle"),
                     "-o", str(so), str(path), "-lm"], check=True)
     env = dict(os.environ, VETTAM_ORACLE_SO=str(so), OMP_NUM_THREADS="2")
+    # a mutant that stalls the solver is caught by the per-test time limit (the pins take ~5 s)
     r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        "-x", "-q", "-p", "no:cacheprovider"], env=env, capture_output=True, text=True,
-                       cwd=ROOT, timeout=600)
+                        "-x", "-q", "-p", "no:cacheprovider", "--timeout", "20"], env=env, capture_output=True,
+                       text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"mutant survived: {after}"
