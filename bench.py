@@ -67,6 +67,29 @@ def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=
     return dict(seconds=t1 - t0, stats=stats, state=(E, F, T), prev=prev, profile=prof)
 
 
+# kernel-class names of the library profiler -> kernel names in the rocprofv3 counter summary
+PROFILE_KERNELS = {"orth_update_fp32": "k_orth_update<float>", "apply_fp32": "k_apply<float, float>",
+                   "multidot_fp32": "k_multidot<float, 16>", "residual_fp64": "k_residual<float, float, float, 0>",
+                   "update_x_fp32": "k_update_x<float>"}
+
+
+def measured_traffic(kernel_class):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_256.json")
+    name = PROFILE_KERNELS.get(kernel_class)
+    if name is None or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = b"".join(open(os.path.join(ROOT, "paper_2202_08778_amd", "csrc", f), "rb").read()
+                   for f in ("rad_single.hip", "rad_device.h"))
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec["kernels"].get(name)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
 def relerr(a, b):
     import numpy as np
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
@@ -102,6 +125,8 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=24)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 4 plain device copies of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (one GPU's share is "
@@ -183,11 +208,21 @@ def main():
         e = prof[dom]
         gbs = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if n == 256 else None,
+                           "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
                            "avg_launch_us": 1000.0 * e["ms"] / e["launches"], "launches": e["launches"]}
         res["kernel_time_share"] = {k: v["ms"] / (mixed["seconds"] * 1e3) for k, v in
                                     sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
         res["kernel_gbs"] = {k: v["bytes"] / (v["ms"] * 1e-3) / 1e9 for k, v in prof.items() if v["ms"] > 0}
+
+    if args.copy_calibration:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+        del x, y
 
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline at {args.cpu_sample_n}^3 ...")
