@@ -306,7 +306,8 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
             }
         };
 
-        double resT = 0;
+        double resT = 0, best_res = INFINITY;
+        int best_at = 0;
         double nr[5];
         for (int kp = 0; status != RAD_EDATA; ++kp) {
             residual(nr);
@@ -322,6 +323,13 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                 break;
             }
             if (kp >= a.max_picard) break;
+            // stall: no new best residual within the last 5 Picard iterations
+            if (res < best_res) {
+                best_res = res;
+                best_at = kp;
+            } else if (kp - best_at >= 5) {
+                break;
+            }
 
             double beta = sqrt(nr[4]);
             const double rtol = fmin(1.0, fmax(fmin(a.eps_R, 1.0), 0.1 * a.tol / fmax(res, 1e-300)));
@@ -344,19 +352,27 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                     apply(vj, (KT)sh_s[j], Wv);
                     ++its;
                     __syncthreads();
-                    // dots <V_i, w>, i <= j, in chunks of 8, and <w, w>
+                    // dots <V_i, w>, i <= j, in chunks of 8, and <w, w>; indices past j are
+                    // clamped to j so every load of a chunk is issued unconditionally
                     double ww = 0;
                     for (int i0 = 0; i0 <= j; i0 += 8) {
                         double acc[9];
 #pragma unroll
                         for (int q = 0; q < 9; ++q) acc[q] = 0;
                         const int cnt = min(8, j + 1 - i0);
-                        for (int e = tid; e < n4; e += NT) {
-                            const double we = (double)Wv[e];
+                        const KT *vq[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) vq[q] = V + (long long)min(i0 + q, j) * n4;
+                        for (int e = 4 * tid; e < n4; e += 4 * NT) {
+                            double we[4];
+                            Quad<KT>::load(Wv + e, we);
+                            double vv[8][4];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) Quad<KT>::load(vq[q] + e, vv[q]);
 #pragma unroll
                             for (int q = 0; q < 8; ++q)
-                                if (q < cnt) acc[q] += (double)V[(long long)(i0 + q) * n4 + e] * we;
-                            acc[8] += we * we;
+                                acc[q] += vv[q][0] * we[0] + vv[q][1] * we[1] + vv[q][2] * we[2] + vv[q][3] * we[3];
+                            acc[8] += we[0] * we[0] + we[1] * we[1] + we[2] * we[2] + we[3] * we[3];
                         }
                         wg_sum<NT, 9>(acc, red);
                         if (tid == 0)
@@ -364,14 +380,32 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                         ww = acc[8];
                     }
                     __syncthreads();
+                    if (tid <= j) sh_a[tid] = sh_s[tid] * sh_s[tid] * sh_dots[tid];
+                    __syncthreads();
                     // v_{j+1} = w - sum_i s_i^2 d_i V_i
                     double nn[1] = {0};
-                    for (int e = tid; e < n4; e += NT) {
-                        double val = (double)Wv[e];
-                        for (int i = 0; i <= j; ++i) val -= sh_s[i] * sh_s[i] * sh_dots[i] * (double)V[(long long)i * n4 + e];
-                        const KT sv = (KT)val;
-                        vn[e] = sv;
-                        nn[0] += (double)sv * (double)sv;
+                    for (int e = 4 * tid; e < n4; e += 4 * NT) {
+                        double val[4];
+                        Quad<KT>::load(Wv + e, val);
+                        int i = 0;
+                        for (; i + 4 <= j + 1; i += 4) {
+                            double a4[4][4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) Quad<KT>::load(V + (long long)(i + u) * n4 + e, a4[u]);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) val[k] -= sh_a[i + u] * a4[u][k];
+                        }
+                        for (; i <= j; ++i) {
+                            double a1[4];
+                            Quad<KT>::load(V + (long long)i * n4 + e, a1);
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) val[k] -= sh_a[i] * a1[k];
+                        }
+                        double r[4];
+                        Quad<KT>::store(vn + e, val, r);
+                        nn[0] += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
                     }
                     wg_sum<NT, 1>(nn, red);
                     if (tid == 0) {
@@ -409,10 +443,16 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                     for (int i = 0; i < cols; ++i) sh_a[i] = yv[i] * sh_s[i];
                 }
                 __syncthreads();
-                for (int e = tid; e < n4; e += NT) {
-                    double acc = X[e];
-                    for (int i = 0; i < cols; ++i) acc += sh_a[i] * (double)V[(long long)i * n4 + e];
-                    X[e] = acc;
+                for (int e = 4 * tid; e < n4; e += 4 * NT) {
+                    double acc[4], r[4];
+                    Quad<double>::load(X + e, acc);
+                    for (int i = 0; i < cols; ++i) {
+                        double a1[4];
+                        Quad<KT>::load(V + (long long)i * n4 + e, a1);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) acc[k] += sh_a[i] * a1[k];
+                    }
+                    Quad<double>::store(X + e, acc, r);
                 }
                 __syncthreads();
                 residual(nr);

@@ -188,6 +188,40 @@ __device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP,
 }
 
 
+// Four consecutive elements of a Krylov vector, loaded/stored as one 16-byte
+// (FP32) or two 16-byte (FP64) vector accesses and widened to FP64.
+template <class KT>
+struct Quad;
+template <>
+struct Quad<float> {
+    static __device__ __forceinline__ void load(const float *p, double (&v)[4])
+    {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+    static __device__ __forceinline__ void store(float *p, const double (&v)[4], double (&r)[4])
+    {
+        float4 q;
+        q.x = (float)v[0]; q.y = (float)v[1]; q.z = (float)v[2]; q.w = (float)v[3];
+        *reinterpret_cast<float4 *>(p) = q;
+        r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
+    }
+};
+template <>
+struct Quad<double> {
+    static __device__ __forceinline__ void load(const double *p, double (&v)[4])
+    {
+        const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+    static __device__ __forceinline__ void store(double *p, const double (&v)[4], double (&r)[4])
+    {
+        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+        for (int k = 0; k < 4; ++k) r[k] = v[k];
+    }
+};
+
 // ------------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double v)

@@ -172,40 +172,6 @@ __global__ void __launch_bounds__(kBlock)
     for (int q = 0; q < 3; ++q) y[(1 + q) * N + c] = yFq[q] * yF;
 }
 
-// Four consecutive elements of a Krylov vector, loaded/stored as one 16-byte
-// (FP32) or two 16-byte (FP64) vector accesses and widened to FP64.
-template <class KT>
-struct Quad;
-template <>
-struct Quad<float> {
-    static __device__ __forceinline__ void load(const float *p, double (&v)[4])
-    {
-        const float4 q = *reinterpret_cast<const float4 *>(p);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    }
-    static __device__ __forceinline__ void store(float *p, const double (&v)[4], double (&r)[4])
-    {
-        float4 q;
-        q.x = (float)v[0]; q.y = (float)v[1]; q.z = (float)v[2]; q.w = (float)v[3];
-        *reinterpret_cast<float4 *>(p) = q;
-        r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
-    }
-};
-template <>
-struct Quad<double> {
-    static __device__ __forceinline__ void load(const double *p, double (&v)[4])
-    {
-        const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
-        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-    }
-    static __device__ __forceinline__ void store(double *p, const double (&v)[4], double (&r)[4])
-    {
-        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
-        *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
-        for (int k = 0; k < 4; ++k) r[k] = v[k];
-    }
-};
-
 // Raw dots <V_i, w> for i in [i0, i0+NV) and <w, w>, FP64 accumulation.  The
 // vector count is a template parameter so all NV+1 loads of an element group
 // are issued back to back.  n (= 4N) is a multiple of 4.
@@ -610,7 +576,8 @@ int run_step(Solver &S)
         }
     };
 
-    double resT = 0;
+    double resT = 0, best_res = INFINITY;
+    int best_at = 0;
     int status = RAD_NOT_CONVERGED;
     const bool trace = trace_enabled();
     int reorth = 0, cycles = 0;
@@ -629,6 +596,13 @@ int run_step(Solver &S)
             break;
         }
         if (k >= p.max_picard) break;
+        // stall: no new best residual within the last 5 Picard iterations (active-set cycling)
+        if (res < best_res) {
+            best_res = res;
+            best_at = k;
+        } else if (k - best_at >= 5) {
+            break;
+        }
 
         // ---- Krylov solve of A d = r for the correction, accumulated into X.
         // Linear tolerance: eps_R relative, tightened so the last solve reaches tol.
