@@ -64,7 +64,8 @@ typedef enum { RAD_F64 = 0, RAD_F32 = 1 } rad_dtype;
 typedef struct {
     double c, a_R, c_v;   /* speed of light, radiation constant, gas heat capacity per mass */
     double tol;           /* target of the scaled nonlinear residual (see rad_stats_t) */
-    double eps_R;         /* relative tolerance cap of each linear (Krylov) solve */
+    double eps_R;         /* relative tolerance of each linear (Krylov) solve; the last solves of a
+                             step are tightened to 0.1 tol / (current scaled residual) */
     double eps_P;         /* > 0: also stop when the relative change of [E,F,T] < eps_P (Sec. 2.3.4) */
     int max_picard;       /* Picard iterations per step */
     int max_krylov;       /* Krylov iterations per linear solve */
@@ -89,7 +90,7 @@ typedef struct {
     double t_total_ms;     /* wall time of the call (host clock) */
 } rad_stats_t;
 
-/* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-4, eps_P 0,
+/* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
  * max_picard 50, max_krylov 20000, gmres_m 30, FP64, linearised, FP64 coefficients. */
 void rad_default_params(rad_params_t *p);
 

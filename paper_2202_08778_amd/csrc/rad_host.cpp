@@ -173,7 +173,7 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->a_R = 1.0;
     p->c_v = 1.0;
     p->tol = 1e-10;
-    p->eps_R = 1e-4;
+    p->eps_R = 1e-2;
     p->eps_P = 0.0;
     p->max_picard = 50;
     p->max_krylov = 20000;

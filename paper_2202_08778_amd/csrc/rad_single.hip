@@ -10,6 +10,7 @@
 // Every vector operation and reduction runs in the kernels below; the host
 // only keeps the (m+1) x m Hessenberg matrix and decides when to stop.
 #include "rad_host.h"
+#include "rad_apply_tiled.h"
 
 #include <algorithm>
 #include <chrono>
@@ -134,44 +135,6 @@ __global__ void __launch_bounds__(kBlock)
     if (MODE == RES_KRYLOV) block_store<5>(v, partials, blockIdx.x);
 }
 
-// w = D^-1 A (s x) in the apply precision AT (tensor stored as ST), s = *xs.
-// When prec == 0, y = A x (no scaling) and xF / yF rescale the flux components
-// on load / store (used by the physical-units entry point).
-template <class AT, class ST>
-__global__ void __launch_bounds__(kBlock)
-    k_apply(Grid g, const ST *__restrict__ f, const AT *__restrict__ sR, const ST *__restrict__ rho,
-            const ST *__restrict__ kR, const AT *__restrict__ dE, const AT *__restrict__ x,
-            const double *__restrict__ xs, AT *__restrict__ y, int prec, AT xF, AT yF)
-{
-    const long long N = g.N;
-    long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= N) return;
-    int i, j, k;
-    cell_ijk(g, c, i, j, k);
-    const AT s = xs ? (AT)(*xs) : AT(1);
-    const AT sF = s * xF;
-    auto ld = [&](int q, long long idx) -> AT { return q == 0 ? s * x[idx] : sF * x[q * N + idx]; };
-    auto fl = [&](int t, long long idx) -> AT { return (AT)f[t * N + idx]; };
-    const double cdt = g.cdt;
-    auto sr = [&](long long idx) -> AT {
-        return sR ? sR[idx] : (AT)(cdt * (double)rho[idx] * (double)kR[idx]);
-    };
-    AT div[4], sC_nb, sC_all;
-    transport<AT>(g, i, j, k, c, ld, fl, sr, div, sC_nb, sC_all);
-    const AT sRc = sr(c), dEc = dE[c];
-    AT yE = dEc * ld(0, c) + div[0];
-    AT yFq[3];
-    for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + sRc) * ld(1 + q, c) + div[1 + q];
-    if (prec) {
-        const AT half = AT(0.5) * (AT)g.nu;
-        yE /= dEc + half * sC_nb;
-        const AT DF = AT(1) + sRc + half * sC_nb;
-        for (int q = 0; q < 3; ++q) yFq[q] /= DF;
-    }
-    y[c] = yE;
-    for (int q = 0; q < 3; ++q) y[(1 + q) * N + c] = yFq[q] * yF;
-}
-
 // Raw dots <V_i, w> for i in [i0, i0+NV) and <w, w>, FP64 accumulation.  The
 // vector count is a template parameter so all NV+1 loads of an element group
 // are issued back to back.  n (= 4N) is a multiple of 4.
@@ -209,41 +172,51 @@ void launch_multidot(int cnt, dim3 g, hipStream_t st, const KT *V, long long str
 }
 
 // out = w - sum_i s_i^2 d_i V_i  (i < cnt), accumulating ||out||^2 of the stored
-// (rounded) values.  out may alias w.
-template <class KT>
+// (rounded) values.  out may alias w.  The basis is consumed in fully unrolled
+// chunks of 16 vectors; indices past cnt are clamped to cnt-1 with a zero
+// coefficient, so all loads of a chunk issue back to back.
+template <class KT, int CH>
 __global__ void __launch_bounds__(kBlock)
     k_orth_update(const KT *__restrict__ V, long long stride, int cnt, const KT *w, KT *out,
                   const double *__restrict__ dots, const double *__restrict__ s, long long n, double *partials)
 {
-    __shared__ double cf[kMaxM + 1];
-    if (threadIdx.x < cnt) cf[threadIdx.x] = s[threadIdx.x] * s[threadIdx.x] * dots[threadIdx.x];
+    __shared__ double cf[kMaxM + CH];
+    for (int t = threadIdx.x; t < kMaxM + CH; t += kBlock)
+        cf[t] = t < cnt ? s[t] * s[t] * dots[t] : 0.0;
     __syncthreads();
     double acc[1] = {0};
     const long long step = (long long)gridDim.x * kBlock * 4;
     for (long long e = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; e < n; e += step) {
         double val[4];
         Quad<KT>::load(w + e, val);
-        int i = 0;
-        for (; i + 4 <= cnt; i += 4) {
-            double a[4][4];
+        for (int i0 = 0; i0 < cnt; i0 += CH) {
+            double a[CH][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) Quad<KT>::load(V + (long long)(i + u) * stride + e, a[u]);
+            for (int u = 0; u < CH; ++u) Quad<KT>::load(V + (long long)min(i0 + u, cnt - 1) * stride + e, a[u]);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < CH; ++u)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) val[k] -= cf[i + u] * a[u][k];
-        }
-        for (; i < cnt; ++i) {
-            double a[4];
-            Quad<KT>::load(V + (long long)i * stride + e, a);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) val[k] -= cf[i] * a[k];
+                for (int k = 0; k < 4; ++k) val[k] -= cf[i0 + u] * a[u][k];
         }
         double r[4];
         Quad<KT>::store(out + e, val, r);
         acc[0] += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
     }
     block_store<1>(acc, partials, blockIdx.x);
+}
+
+// chunk width by basis size: small counts do not pay for a 16-wide chunk
+template <class KT>
+void launch_orth_update(int cnt, dim3 g, hipStream_t st, const KT *V, long long stride, const KT *w, KT *out,
+                        const double *dots, const double *s, long long n, double *partials)
+{
+    if (cnt <= 4)
+        hipLaunchKernelGGL((k_orth_update<KT, 4>), g, dim3(kBlock), 0, st, V, stride, cnt, w, out, dots, s, n, partials);
+    else if (cnt <= 8)
+        hipLaunchKernelGGL((k_orth_update<KT, 8>), g, dim3(kBlock), 0, st, V, stride, cnt, w, out, dots, s, n, partials);
+    else
+        hipLaunchKernelGGL((k_orth_update<KT, 16>), g, dim3(kBlock), 0, st, V, stride, cnt, w, out, dots, s, n,
+                           partials);
 }
 
 // X += sum_i a_i V_i over the 4N-vector (FP64 state, Krylov-precision basis).
@@ -422,7 +395,7 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, V, W, part, small, total;
+    size_t X, X0, Tc, sR, dEA, fA, Cf, V, W, part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
@@ -450,6 +423,7 @@ Layout layout(long long N, const rad_params_t &p)
     L.sR = take(N * ksz);
     L.dEA = take(N * ksz);
     L.fA = (mixed && p.coef_dtype == RAD_F64) ? take(6 * N * ksz) : take(0);
+    L.Cf = take(3 * N * ksz);
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
     L.part = take((size_t)std::max<long long>(L.nblk_cells, L.nblk_vec) * 24 * 8);
@@ -542,15 +516,22 @@ int run_step(Solver &S)
     const int kOrth = sizeof(KT) == 4 ? K_ORTH32 : K_ORTH64;
     const int kUpd = sizeof(KT) == 4 ? K_UPDATEX32 : K_UPDATEX64;
     const double fb = fA ? kb : cb;   // bytes per stored tensor component read by the apply
+    const TileGeom tg = tile_geom(g);
+    const dim3 gt((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)), bt(256);
+    AT *Cf = S.at<AT>(S.L.Cf);
+    S.timed(K_SETUP, Nd * (3 * cb + 3 * kb), [&] {
+        hipLaunchKernelGGL((k_face_coef<CT, AT>), gc, bl, 0, S.st, g, rho, kR, f, Cf);
+    });
     auto apply = [&](const KT *x, const double *xs, KT *y) {
         const int tok = prof_begin(kApply, S.st);
         if (fA)
-            hipLaunchKernelGGL((k_apply<AT, AT>), gc, bl, 0, S.st, g, (const AT *)fA, sR, (const AT *)nullptr,
-                               (const AT *)nullptr, dEA, x, xs, y, 1, AT(1), AT(1));
+            hipLaunchKernelGGL((k_apply_tiled<AT, AT>), gt, bt, 0, S.st, g, tg, (const AT *)fA, sR,
+                               (const AT *)nullptr, (const AT *)nullptr, (const AT *)Cf, dEA, x, xs, y, 1, AT(1),
+                               AT(1));
         else
-            hipLaunchKernelGGL((k_apply<AT, CT>), gc, bl, 0, S.st, g, f, sR, (const CT *)nullptr,
-                               (const CT *)nullptr, dEA, x, xs, y, 1, AT(1), AT(1));
-        prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 2 * kb));
+            hipLaunchKernelGGL((k_apply_tiled<AT, CT>), gt, bt, 0, S.st, g, tg, f, sR, (const CT *)nullptr,
+                               (const CT *)nullptr, (const AT *)Cf, dEA, x, xs, y, 1, AT(1), AT(1));
+        prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
     };
     // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
     // its norm's inverse becomes the scale s_0 of V[0].
@@ -626,8 +607,7 @@ int run_step(Solver &S)
                 ++its;
                 multidot(j + 1, W);
                 S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
-                    hipLaunchKernelGGL((k_orth_update<KT>), gv, bl, 0, S.st, V, stride, j + 1, W, vn, sm + SM_DOTS,
-                                       sm + SM_S, n4, part);
+                    launch_orth_update<KT>(j + 1, gv, S.st, V, stride, W, vn, sm + SM_DOTS, sm + SM_S, n4, part);
                 });
                 S.reduce(S.L.nblk_vec, 1, 1, sm + SM_NRM, nullptr, 0, sm + SM_S + j + 1);
                 RAD_TRY(S.read(0, SM_TOTAL));
@@ -640,8 +620,7 @@ int run_step(Solver &S)
                     ++reorth;
                     multidot(j + 1, vn);
                     S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
-                        hipLaunchKernelGGL((k_orth_update<KT>), gv, bl, 0, S.st, V, stride, j + 1, vn, vn,
-                                           sm + SM_DOTS, sm + SM_S, n4, part);
+                        launch_orth_update<KT>(j + 1, gv, S.st, V, stride, vn, vn, sm + SM_DOTS, sm + SM_S, n4, part);
                     });
                     S.reduce(S.L.nblk_vec, 1, 1, sm + SM_NRM, nullptr, 0, sm + SM_S + j + 1);
                     RAD_TRY(S.read(0, SM_TOTAL));
@@ -729,9 +708,10 @@ template <class AT, class CT>
 void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, const void *rho, const void *kR,
                        const void *f, double c, hipStream_t st)
 {
-    const dim3 gc((unsigned)((g.N + kBlock - 1) / kBlock)), bl(kBlock);
-    hipLaunchKernelGGL((k_apply<AT, CT>), gc, bl, 0, st, g, (const CT *)f, (const AT *)nullptr, (const CT *)rho,
-                       (const CT *)kR, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y, 0,
+    const TileGeom tg = tile_geom(g);
+    hipLaunchKernelGGL((k_apply_tiled<AT, CT>), dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)), dim3(256), 0,
+                       st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
+                       (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y, 0,
                        (AT)(1.0 / c), (AT)c);
 }
 
