@@ -119,7 +119,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid edge (the metric is quoted at 256)")
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--gmres-m", type=int, default=30)
+    ap.add_argument("--gmres-m", type=int, default=8,
+                    help="GMRES restart length (8 is fastest on this workload: orthogonalisation grows with m "
+                         "while the iteration count barely changes)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")

@@ -91,7 +91,7 @@ typedef struct {
 } rad_stats_t;
 
 /* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
- * max_picard 50, max_krylov 20000, gmres_m 30, FP64, linearised, FP64 coefficients. */
+ * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients. */
 void rad_default_params(rad_params_t *p);
 
 /* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */

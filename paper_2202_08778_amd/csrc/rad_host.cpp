@@ -177,7 +177,7 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->eps_P = 0.0;
     p->max_picard = 50;
     p->max_krylov = 20000;
-    p->gmres_m = 30;
+    p->gmres_m = 12;
     p->prec = RAD_FP64;
     p->mode = RAD_PICARD_LINEARISED;
     p->coef_dtype = RAD_F64;

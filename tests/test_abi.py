@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(rad):
 def test_defaults(rad):
     p = rad.params()
     assert (p.c, p.a_R, p.c_v) == (1.0, 1.0, 1.0)
-    assert p.gmres_m == 30 and p.prec == 0 and p.mode == 1
+    assert p.gmres_m == 12 and p.prec == 0 and p.mode == 1 and p.eps_R == 1e-2
 
 
 def _step(rad, p, nx=4, ny=4, nz=4, ptr=0x1000, bc="periodic", dt=1.0, dx=1.0, ws=None, wsb=None):
