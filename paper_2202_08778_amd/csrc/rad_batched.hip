@@ -151,8 +151,9 @@ template <class CT, class KT, int NT>
 __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
 {
     constexpr int W = NT / 64;
+    constexpr int DC = 8;  // basis vectors per multi-dot pass
     __shared__ double red[16 * W];
-    __shared__ double sh_dots[kMaxM + 8], sh_s[kMaxM + 2], sh_a[kMaxM + 1];
+    __shared__ double sh_dots[kMaxM + DC], sh_s[kMaxM + 2], sh_a[kMaxM + 1], sh_y[kMaxM];
     __shared__ double sh_H[(kMaxM + 1) * kMaxM], sh_cs[kMaxM], sh_sn[kMaxM], sh_g[kMaxM + 1];
     __shared__ int sh_flag, sh_b;
 
@@ -352,32 +353,32 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                     apply(vj, (KT)sh_s[j], Wv);
                     ++its;
                     __syncthreads();
-                    // dots <V_i, w>, i <= j, in chunks of 8, and <w, w>; indices past j are
+                    // dots <V_i, w>, i <= j, in chunks of DC, and <w, w>; indices past j are
                     // clamped to j so every load of a chunk is issued unconditionally
                     double ww = 0;
-                    for (int i0 = 0; i0 <= j; i0 += 8) {
-                        double acc[9];
+                    for (int i0 = 0; i0 <= j; i0 += DC) {
+                        double acc[DC + 1];
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) acc[q] = 0;
-                        const int cnt = min(8, j + 1 - i0);
-                        const KT *vq[8];
+                        for (int q = 0; q <= DC; ++q) acc[q] = 0;
+                        const int cnt = min(DC, j + 1 - i0);
+                        const KT *vq[DC];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) vq[q] = V + (long long)min(i0 + q, j) * n4;
+                        for (int q = 0; q < DC; ++q) vq[q] = V + (long long)min(i0 + q, j) * n4;
                         for (int e = 4 * tid; e < n4; e += 4 * NT) {
                             double we[4];
                             Quad<KT>::load(Wv + e, we);
-                            double vv[8][4];
+                            double vv[DC][4];
 #pragma unroll
-                            for (int q = 0; q < 8; ++q) Quad<KT>::load(vq[q] + e, vv[q]);
+                            for (int q = 0; q < DC; ++q) Quad<KT>::load(vq[q] + e, vv[q]);
 #pragma unroll
-                            for (int q = 0; q < 8; ++q)
+                            for (int q = 0; q < DC; ++q)
                                 acc[q] += vv[q][0] * we[0] + vv[q][1] * we[1] + vv[q][2] * we[2] + vv[q][3] * we[3];
-                            acc[8] += we[0] * we[0] + we[1] * we[1] + we[2] * we[2] + we[3] * we[3];
+                            acc[DC] += we[0] * we[0] + we[1] * we[1] + we[2] * we[2] + we[3] * we[3];
                         }
-                        wg_sum<NT, 9>(acc, red);
+                        wg_sum<NT, DC + 1>(acc, red);
                         if (tid == 0)
                             for (int q = 0; q < cnt; ++q) sh_dots[i0 + q] = acc[q];
-                        ww = acc[8];
+                        ww = acc[DC];
                     }
                     __syncthreads();
                     if (tid <= j) sh_a[tid] = sh_s[tid] * sh_s[tid] * sh_dots[tid];
@@ -434,13 +435,12 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                 }
                 // y = H^-1 g;  X += sum_i y_i s_i V_i
                 if (tid == 0) {
-                    double yv[kMaxM];
                     for (int i = cols - 1; i >= 0; --i) {
                         double s = sh_g[i];
-                        for (int l = i + 1; l < cols; ++l) s -= sh_H[i * m + l] * yv[l];
-                        yv[i] = sh_H[i * m + i] != 0 ? s / sh_H[i * m + i] : 0.0;
+                        for (int l = i + 1; l < cols; ++l) s -= sh_H[i * m + l] * sh_y[l];
+                        sh_y[i] = sh_H[i * m + i] != 0 ? s / sh_H[i * m + i] : 0.0;
                     }
-                    for (int i = 0; i < cols; ++i) sh_a[i] = yv[i] * sh_s[i];
+                    for (int i = 0; i < cols; ++i) sh_a[i] = sh_y[i] * sh_s[i];
                 }
                 __syncthreads();
                 for (int e = 4 * tid; e < n4; e += 4 * NT) {
@@ -614,8 +614,8 @@ struct rad_plan_s {
     WsLayout L;
     char *ws = nullptr;
     int cus = 0;
-    int nt = 256;
-    int per_cu = 2;
+    int nt = 512;
+    int per_cu = 1;
     bool lpt = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -816,8 +816,8 @@ extern "C" int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const
     P->L = L;
     P->ws = (char *)workspace;
     P->cus = device_cus();
-    P->nt = 256;
-    P->per_cu = 2;
+    P->nt = 512;  // one 8-wave workgroup per CU unless the autotune cache says otherwise
+    P->per_cu = 1;
     P->lpt = true;
     cache_lookup(P);
     int rc = RAD_OK;
@@ -888,7 +888,7 @@ extern "C" int rad_autotune_batched(rad_plan P, double *E, double *F, double *T_
         int nt, per_cu;
         bool lpt;
     };
-    const Cand cands[] = {{256, 2, true}, {256, 1, true}, {512, 1, true}, {512, 2, true}, {256, 2, false}};
+    const Cand cands[] = {{512, 1, true}, {512, 2, true}, {256, 2, true}, {256, 1, true}, {512, 1, false}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -901,15 +901,15 @@ extern "C" int rad_autotune_batched(rad_plan P, double *E, double *F, double *T_
         P->lpt = c.lpt;
         if ((rc = upload_order(P, st)) != RAD_OK) break;
         fill_args(P, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, tstats);
+        // one timed trial per candidate: a trial is a whole batched step (seconds),
+        // far longer than any cache or code warm-up
         float ms = 0;
-        for (int rep = 0; rep < 2 && rc == RAD_OK; ++rep) {  // first run warms caches and code
-            if ((rc = restore()) != RAD_OK) break;
-            if (hipEventRecord(e0, st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
-            if (rc == RAD_OK) rc = launch_direct(P, st);
-            if (rc == RAD_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
-            if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "trial failed");
-            if (rc == RAD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(RAD_EHIP, "timing failed");
-        }
+        if ((rc = restore()) != RAD_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+        if (rc == RAD_OK) rc = launch_direct(P, st);
+        if (rc == RAD_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+        if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "trial failed");
+        if (rc == RAD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(RAD_EHIP, "timing failed");
         if (rc != RAD_OK) break;
         if (trace_enabled())
             std::fprintf(stderr, "[rad] autotune nt=%d per_cu=%d lpt=%d: %.3f ms\n", c.nt, c.per_cu, (int)c.lpt, ms);

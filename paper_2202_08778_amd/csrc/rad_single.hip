@@ -381,6 +381,8 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
     if (!p) return fail(RAD_EINVAL, "params is NULL");
     if (nx < 1 || ny < 1 || nz < 1) return fail(RAD_EINVAL, "grid extents must be >= 1");
     if ((long long)nx * ny * nz > (1LL << 31)) return fail(RAD_EINVAL, "grid larger than 2^31 cells");
+    // the stencil addresses one z plane through a buffer descriptor (bytes < 2^31)
+    if ((long long)nx * ny > (1LL << 27)) return fail(RAD_EINVAL, "nx * ny larger than 2^27 cells");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(RAD_EINVAL, "dt must be positive and finite");
     if (!(dx > 0) || !std::isfinite(dx)) return fail(RAD_EINVAL, "dx must be positive and finite");
     if (!bc) return fail(RAD_EINVAL, "bc is NULL");
@@ -525,12 +527,11 @@ int run_step(Solver &S)
     auto apply = [&](const KT *x, const double *xs, KT *y) {
         const int tok = prof_begin(kApply, S.st);
         if (fA)
-            hipLaunchKernelGGL((k_apply_tiled<AT, AT>), gt, bt, 0, S.st, g, tg, (const AT *)fA, sR,
-                               (const AT *)nullptr, (const AT *)nullptr, (const AT *)Cf, dEA, x, xs, y, 1, AT(1),
-                               AT(1));
+            hipLaunchKernelGGL((k_apply_tiled<AT, AT, true>), gt, bt, 0, S.st, g, tg, (const AT *)fA, sR,
+                               (const AT *)nullptr, (const AT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
         else
-            hipLaunchKernelGGL((k_apply_tiled<AT, CT>), gt, bt, 0, S.st, g, tg, f, sR, (const CT *)nullptr,
-                               (const CT *)nullptr, (const AT *)Cf, dEA, x, xs, y, 1, AT(1), AT(1));
+            hipLaunchKernelGGL((k_apply_tiled<AT, CT, true>), gt, bt, 0, S.st, g, tg, f, sR, (const CT *)nullptr,
+                               (const CT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
         prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
     };
     // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
@@ -709,9 +710,9 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
                        const void *f, double c, hipStream_t st)
 {
     const TileGeom tg = tile_geom(g);
-    hipLaunchKernelGGL((k_apply_tiled<AT, CT>), dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)), dim3(256), 0,
-                       st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
-                       (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y, 0,
+    hipLaunchKernelGGL((k_apply_tiled<AT, CT, false>), dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)),
+                       dim3(256), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
+                       (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
                        (AT)(1.0 / c), (AT)c);
 }
 
