@@ -1,15 +1,19 @@
-// rad_apply_tiled.h -- the operator apply as a 2.5D z-marching stencil (gfx950).
+// rad_apply_tiled.h -- the transport stencil as a 2.5D z-marching tile sweep (gfx950).
 //
-// A workgroup of 256 threads (64 x 4) owns a 64 x 8 cell column of the grid
-// over a range of z planes.  For the current plane k the tile and a one-cell
-// x/y halo live in LDS (state, tensor, sR); the planes k-1 and k+1 of the
-// thread's own cells live in registers, so every value is read from HBM once
-// per z-range (the halo rows are read by the neighbouring tile too and hit in
-// L2, since tiles are assigned to XCDs in contiguous ranges).  Every LDS slot
-// and every z neighbour is first mapped through the boundary rule (periodic:
-// wrap, outflow: the boundary cell itself), so boundary faces and ragged tile
-// edges need no special cases: a face whose mapped neighbour is the cell
-// itself carries the cell's physical flux and no dissipation.
+// A workgroup owns a 64 x 8 cell column of the grid over a range of z planes
+// (FP32: 256 threads, two cells each along y; FP64: 512 threads, one cell
+// each).  Two LDS slots hold the planes k and k+1 of the tile with a one-cell
+// x/y halo (state, tensor, sR, low-face speeds); the plane k-1 of the thread's
+// own cells lives in registers.  Planes k+2 and k+3 are in flight in two
+// register sets used alternately, so every HBM value is read once per z-range
+// and each load has two planes of work to arrive (the halo rows are read by the
+// neighbouring tile too and hit in L2, since tiles are assigned to XCDs in
+// contiguous ranges).  Every LDS slot and every z neighbour is first mapped
+// through the boundary rule (periodic: wrap, outflow: the boundary cell
+// itself), so boundary faces and ragged tile edges need no special cases: a
+// face whose mapped neighbour is the cell itself carries the cell's physical
+// flux and no dissipation.  The per-cell epilogue is a functor: the Krylov
+// operator apply and the FP64 residual of one Picard iteration share the sweep.
 #pragma once
 #include "rad_device.h"
 
@@ -17,12 +21,26 @@
 
 namespace vr {
 
-constexpr int kTX = 64;          // tile width (x), one wave per row
-constexpr int kTYT = 4;          // thread rows
-constexpr int kCPT = 2;          // cells per thread along y
-constexpr int kTY = kTYT * kCPT; // tile height (y)
+constexpr int kTX = 64;  // tile width (x), one wave per row
+constexpr int kTY = 8;   // tile height (y)
 constexpr int kLX = kTX + 2, kLY = kTY + 2;
 constexpr int kHalo = 2 * kTX + 2 * kTY;
+
+// thread rows of the tile, cells per thread along y and planes in flight
+// (prefetch depth), by arithmetic type: FP64 records take twice the registers
+template <class AT>
+struct TileShape {
+    static constexpr int TYT = 4, CPT = 2, DEPTH = 2;
+};
+template <>
+struct TileShape<double> {
+    static constexpr int TYT = 8, CPT = 1, DEPTH = 1;
+};
+template <class AT>
+constexpr int tile_threads()
+{
+    return 64 * TileShape<AT>::TYT;
+}
 
 // Workgroup barrier that orders LDS only: global loads issued before it stay in
 // flight (a full __syncthreads would wait for them as well).
@@ -71,23 +89,35 @@ __device__ __forceinline__ void st_off(T *base, unsigned off, T v)
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (size_t)(off * (unsigned)sizeof(T))) = v;
 }
 
-// y = D^-1 A (s x) (PRE: Jacobi-scaled Krylov operator) or y = A x with flux
-// rescaling xF/yF (!PRE: the physical operator).
-// PRE: sR (c dt rho kappa_R) and Cf (the corrected face speeds divided by c at
-// the three low faces of every cell, planes x|y|z) are precomputed once per step.
-// !PRE: both are derived per cell and face from rho, kR and f.
+// LDS record of one cell: x (4, scaled), f (6), sR, low-face speeds (PRE: 3)
+template <bool PRE>
+struct Rec {
+    static constexpr int IX = 0, IF = 4, IS = 10, IC = 11, NL = 11 + (PRE ? 3 : 0);
+};
+
+// Transport sums of one cell: dEs = sum_faces +-PhiE, dF likewise (without the
+// factor nu), the face speeds of the non-self faces (Jacobi diagonal) and of
+// all six faces (residual weights; a self face takes the cell's own speed).
+template <class AT>
+struct CellSums {
+    AT Ec, Fc[3], sc, dEs, dF[3], sumC_nb, sumC_all;
+};
+
+// The sweep.  PRE: sR and the low-face speeds Cf (divided by c, planes x|y|z)
+// are precomputed; otherwise both are derived from rho, kR and f per face.
+// lex(pb, o, e) loads the NE per-cell extras of the epilogue (plane base pb,
+// in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell.
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
-template <class AT, class ST, bool PRE>
-__global__ void __launch_bounds__(256)
-    k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
-                  const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
-                  const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
-                  AT *__restrict__ y, AT xF, AT yF)
+template <class AT, class ST, bool PRE, bool CALL, int NE, class LEX, class EPI>
+__device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
+                                           const AT *__restrict__ sR, const ST *__restrict__ rho,
+                                           const ST *__restrict__ kR, const AT *__restrict__ Cf,
+                                           const AT *__restrict__ x, AT s, AT sF,
+                                           AT (&lds)[2][Rec<PRE>::NL][kLY][kLX], LEX lex, EPI epi)
 {
-    // LDS record of one cell: x (4, scaled), f (6), sR, low-face speeds (PRE: 3)
+    constexpr int TYT = TileShape<AT>::TYT, CPT = TileShape<AT>::CPT;
     constexpr int NC = PRE ? 3 : 0;
-    constexpr int IX = 0, IF = 4, IS = 10, IC = 11, NL = 11 + NC;
-    __shared__ AT lds[2][NL][kLY][kLX];  // planes k and k+1, slot = plane parity
+    constexpr int IX = Rec<PRE>::IX, IF = Rec<PRE>::IF, IS = Rec<PRE>::IS, IC = Rec<PRE>::IC, NL = Rec<PRE>::NL;
 
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
@@ -103,18 +133,15 @@ __global__ void __launch_bounds__(256)
     const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * tg.kz;
     const int z1 = min(z0 + tg.kz, g.nz);
     const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
-
-    const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
-    const AT sF = s * xF;
     const AT cdt = (AT)g.cdt;
 
     // in-plane offsets of the thread's (mapped) cells and of its LDS halo cell
     const int gx = x0 + lx;
     const int mx = map_axis(gx, g.nx, g.bclo[0], g.bchi[0]);
-    unsigned off[kCPT];
-    bool active[kCPT];
-    for (int c = 0; c < kCPT; ++c) {
-        const int gy = y0 + ly + kTYT * c;
+    unsigned off[CPT];
+    bool active[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        const int gy = y0 + ly + TYT * c;
         off[c] = (unsigned)mx + (unsigned)g.nx * (unsigned)map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
         active[c] = gx < g.nx && gy < g.ny;  // then off[c] is the cell's own offset
     }
@@ -133,25 +160,24 @@ __global__ void __launch_bounds__(256)
     // self-faces (mapped neighbour is the cell itself): excluded from the Jacobi diagonal
     const bool selfx_lo = map_axis(gx - 1, g.nx, g.bclo[0], g.bchi[0]) == mx;
     const bool selfx_hi = map_axis(gx + 1, g.nx, g.bclo[0], g.bchi[0]) == mx;
-    bool selfy_lo[kCPT], selfy_hi[kCPT];
-    for (int c = 0; c < kCPT; ++c) {
-        const int gy = y0 + ly + kTYT * c;
+    bool selfy_lo[CPT], selfy_hi[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        const int gy = y0 + ly + TYT * c;
         const int my = map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
         selfy_lo[c] = map_axis(gy - 1, g.ny, g.bclo[1], g.bchi[1]) == my;
         selfy_hi[c] = map_axis(gy + 1, g.ny, g.bclo[1], g.bchi[1]) == my;
     }
     auto mapz = [&](int q) { return map_axis(q, g.nz, g.bclo[2], g.bchi[2]); };
 
-    // one cell's record in registers (in flight from HBM), plus its dE
+    // one cell's record in registers (in flight from HBM)
     struct Full {
         AT v[NL];
-        AT d;
     };
     // z-neighbour subset below the current plane: x (4), f row z (xz, yz, zz), sR
     struct ZRow {
         AT x[4], f[3], s;
     };
-    auto load_full = [&](int kp, unsigned o, Full &u, bool own) __attribute__((always_inline)) {
+    auto load_full = [&](int kp, unsigned o, Full &u) __attribute__((always_inline)) {
         const long long pb = plane * kp;
         u.v[IX] = s * ld_off(x + pb, o);
 #pragma unroll
@@ -165,31 +191,35 @@ __global__ void __launch_bounds__(256)
         } else {
             u.v[IS] = cdt * (AT)ld_off(rho + pb, o) * (AT)ld_off(kR + pb, o);
         }
-        u.d = (PRE && own) ? ld_off(dE + pb, o) : AT(0);
     };
     auto put = [&](int sl, int sy, int sxx, const Full &u) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < NL; ++q) lds[sl][q][sy][sxx] = u.v[q];
     };
 
-    ZRow prev[kCPT];
-    AT dcur[kCPT], dnxt[kCPT];
-    const AT tk = (AT)g.tau_k, nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
+    ZRow prev[CPT];
+    AT ex[CPT][NE > 0 ? NE : 1];
+    const AT tk = (AT)g.tau_k;
 
     // Plane k of the tile from LDS slot a, its upper z neighbour from slot b,
-    // the lower one from registers; writes y for the thread's cells.
+    // the lower one from registers.
     auto compute = [&](int k, int a, int b) __attribute__((always_inline)) {
-        const long long pb = plane * k;
         const bool selfz_lo = mapz(k - 1) == k, selfz_hi = mapz(k + 1) == k;
 #pragma unroll
-        for (int c = 0; c < kCPT; ++c) {
+        for (int c = 0; c < CPT; ++c) {
             // ragged-edge cells are computed from their mapped (in-range) values
             // and not stored, so the arithmetic has no divergent branch
-            const int sy = ly + kTYT * c + 1, sxx = lx + 1;
-            const AT Ec = lds[a][IX][sy][sxx];
-            const AT Fc[3] = {lds[a][IX + 1][sy][sxx], lds[a][IX + 2][sy][sxx], lds[a][IX + 3][sy][sxx]};
-            const AT sc = lds[a][IS][sy][sxx];
-            AT dEs = 0, dF[3] = {0, 0, 0}, sumC_nb = 0;
+            const int sy = ly + TYT * c + 1, sxx = lx + 1;
+            CellSums<AT> S;
+            S.Ec = lds[a][IX][sy][sxx];
+            for (int q = 0; q < 3; ++q) S.Fc[q] = lds[a][IX + 1 + q][sy][sxx];
+            S.sc = lds[a][IS][sy][sxx];
+            S.dEs = 0;
+            S.dF[0] = S.dF[1] = S.dF[2] = 0;
+            S.sumC_nb = 0;
+            S.sumC_all = 0;
+            // a self face's speed for the residual weights: the cell with itself
+            auto self_speed = [&](AT fdd) { return face_speed<AT>(fdd, fdd, S.sc, S.sc, tk); };
             // x and y faces
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
@@ -208,15 +238,33 @@ __global__ void __launch_bounds__(256)
                     if constexpr (PRE)
                         Cface = side ? lds[a][IC + d][ny_][nx_] : lds[a][IC + d][sy][sxx];
                     else
-                        Cface = face_speed<AT>(fcr[d], fnr[d], sc, lds[a][IS][ny_][nx_], tk);
+                        Cface = face_speed<AT>(fcr[d], fnr[d], S.sc, lds[a][IS][ny_][nx_], tk);
                     const bool self = d == 0 ? (side ? selfx_hi : selfx_lo) : (side ? selfy_hi[c] : selfy_lo[c]);
-                    sumC_nb += self ? AT(0) : Cface;
-                    face_flux_acc<AT>(d, side, Cface, Ec, Fc, fcr, En, Fn, fnr, dEs, dF);
+                    S.sumC_nb += self ? AT(0) : Cface;
+                    if constexpr (CALL) {
+                        if (PRE && side && self)
+                            S.sumC_all += self_speed(fcr[d]);
+                        else
+                            S.sumC_all += Cface;
+                    }
+                    face_flux_acc<AT>(d, side, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
                 }
             }
-            // z faces
+            // z faces: lower from registers, upper from slot b
             const AT fcr[3] = {lds[a][IF + tens_row(2, 0)][sy][sxx], lds[a][IF + tens_row(2, 1)][sy][sxx],
                                lds[a][IF + tens_row(2, 2)][sy][sxx]};
+            {
+                const ZRow &P = prev[c];
+                const AT Fn[3] = {P.x[1], P.x[2], P.x[3]};
+                AT Cface;
+                if constexpr (PRE)
+                    Cface = lds[a][IC + 2][sy][sxx];
+                else
+                    Cface = face_speed<AT>(fcr[2], P.f[2], S.sc, P.s, tk);
+                S.sumC_nb += selfz_lo ? AT(0) : Cface;
+                if constexpr (CALL) S.sumC_all += Cface;
+                face_flux_acc<AT>(2, 0, Cface, S.Ec, S.Fc, fcr, P.x[0], Fn, P.f, S.dEs, S.dF);
+            }
             {
                 const AT En = lds[b][IX][sy][sxx];
                 const AT Fn[3] = {lds[b][IX + 1][sy][sxx], lds[b][IX + 2][sy][sxx], lds[b][IX + 3][sy][sxx]};
@@ -226,114 +274,136 @@ __global__ void __launch_bounds__(256)
                 if constexpr (PRE)
                     Cface = lds[b][IC + 2][sy][sxx];
                 else
-                    Cface = face_speed<AT>(fcr[2], fnr[2], sc, lds[b][IS][sy][sxx], tk);
-                sumC_nb += selfz_hi ? AT(0) : Cface;
-                face_flux_acc<AT>(2, 1, Cface, Ec, Fc, fcr, En, Fn, fnr, dEs, dF);
+                    Cface = face_speed<AT>(fcr[2], fnr[2], S.sc, lds[b][IS][sy][sxx], tk);
+                S.sumC_nb += selfz_hi ? AT(0) : Cface;
+                if constexpr (CALL) {
+                    if (PRE && selfz_hi)
+                        S.sumC_all += self_speed(fcr[2]);
+                    else
+                        S.sumC_all += Cface;
+                }
+                face_flux_acc<AT>(2, 1, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
             }
-            {
-                const ZRow &P = prev[c];
-                const AT Fn[3] = {P.x[1], P.x[2], P.x[3]};
-                AT Cface;
-                if constexpr (PRE)
-                    Cface = lds[a][IC + 2][sy][sxx];
-                else
-                    Cface = face_speed<AT>(fcr[2], P.f[2], sc, P.s, tk);
-                sumC_nb += selfz_lo ? AT(0) : Cface;
-                face_flux_acc<AT>(2, 0, Cface, Ec, Fc, fcr, P.x[0], Fn, P.f, dEs, dF);
-            }
-            AT yE, yFq[3];
-            if constexpr (PRE) {
-                const AT dEc = dcur[c];
-                yE = (dEc * Ec + nu * dEs) * (AT(1) / (dEc + half * sumC_nb));
-                const AT iDF = AT(1) / (AT(1) + sc + half * sumC_nb);
-                for (int q = 0; q < 3; ++q) yFq[q] = ((AT(1) + sc) * Fc[q] + nu * dF[q]) * iDF;
-            } else {
-                const AT dEc = ld_off(dE + pb, off[c]);
-                yE = dEc * Ec + nu * dEs;
-                for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + sc) * Fc[q] + nu * dF[q];
-            }
-            if (active[c]) {
-                st_off(y + pb, off[c], yE);
-                for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, off[c], yFq[q] * yF);
-            }
+            epi(k, c, off[c], active[c], S, ex[c]);
             // this plane becomes the lower neighbour of the next one
             ZRow &P = prev[c];
-            P.x[0] = Ec;
-            for (int q = 0; q < 3; ++q) P.x[1 + q] = Fc[q];
+            P.x[0] = S.Ec;
+            for (int q = 0; q < 3; ++q) P.x[1 + q] = S.Fc[q];
             for (int q = 0; q < 3; ++q) P.f[q] = fcr[q];
-            P.s = sc;
+            P.s = S.sc;
         }
     };
 
-    // Pipeline: plane k is computed while planes k+2 and k+3 are in flight
-    // (two register sets used alternately), so each load has two planes of
-    // work to arrive before it is written to LDS.  Every load of the steady
-    // state is unconditional (lanes without a halo cell re-read their own
-    // cell, an L2 hit), so the compiler's wait counts stay two planes deep.
+    // Pipeline (DEPTH 2): plane k is computed while planes k+2 and k+3 are in
+    // flight (two register sets used alternately), so each load has two planes
+    // of work to arrive before it is written to LDS; DEPTH 1 keeps plane k+2 in
+    // flight only.  Every load of the steady state is unconditional (lanes
+    // without a halo cell re-read their own cell, an L2 hit), so the compiler's
+    // wait counts stay a full set deep.  The epilogue's per-cell extras of plane
+    // k are issued ahead of the prefetch, so waiting for them leaves it in flight.
+    constexpr int DEPTH = TileShape<AT>::DEPTH;
     const unsigned hsrc = hly >= 0 ? hoff : off[0];
-    Full S0[kCPT], S1[kCPT], H0, H1;
+    Full S0[CPT], S1[DEPTH == 2 ? CPT : 1], H0, H1;
     {
         Full t;
-        for (int c = 0; c < kCPT; ++c) {
-            load_full(mapz(z0 - 1), off[c], t, false);
+        for (int c = 0; c < CPT; ++c) {
+            load_full(mapz(z0 - 1), off[c], t);
             prev[c].x[0] = t.v[IX];
             for (int q = 0; q < 3; ++q) prev[c].x[1 + q] = t.v[IX + 1 + q];
             for (int q = 0; q < 3; ++q) prev[c].f[q] = t.v[IF + tens_row(2, q)];
             prev[c].s = t.v[IS];
         }
-        for (int c = 0; c < kCPT; ++c) {
-            load_full(z0, off[c], t, true);
-            put(0, ly + kTYT * c + 1, lx + 1, t);
-            dcur[c] = t.d;
+        for (int c = 0; c < CPT; ++c) {
+            load_full(z0, off[c], t);
+            put(0, ly + TYT * c + 1, lx + 1, t);
         }
-        load_full(z0, hsrc, t, false);
+        load_full(z0, hsrc, t);
         if (hly >= 0) put(0, hly, hlx, t);
     }
-    for (int c = 0; c < kCPT; ++c) load_full(mapz(z0 + 1), off[c], S0[c], true);
-    load_full(mapz(z0 + 1), hsrc, H0, false);
-    for (int c = 0; c < kCPT; ++c) load_full(mapz(min(z0 + 2, z1)), off[c], S1[c], true);
-    load_full(mapz(min(z0 + 2, z1)), hsrc, H1, false);
+    for (int c = 0; c < CPT; ++c) load_full(mapz(z0 + 1), off[c], S0[c]);
+    load_full(mapz(z0 + 1), hsrc, H0);
+    if constexpr (DEPTH == 2) {
+        for (int c = 0; c < CPT; ++c) load_full(mapz(min(z0 + 2, z1)), off[c], S1[c]);
+        load_full(mapz(min(z0 + 2, z1)), hsrc, H1);
+    }
 
-    // one plane: LOAD issues plane k+3 (needed when k+3 <= z1)
-    auto iter = [&](auto LOAD, int t, Full (&S)[kCPT], Full &H) __attribute__((always_inline)) {
+    // one plane: LOAD issues plane k+1+DEPTH (needed when k+1+DEPTH <= z1)
+    auto iter = [&](auto LOAD, int t, Full (&S)[CPT], Full &H) __attribute__((always_inline)) {
         const int k = z0 + t;
         const int a = t & 1, b = a ^ 1;
-        // plane k+1 (issued two planes ago) into the free slot
-        for (int c = 0; c < kCPT; ++c) {
-            put(b, ly + kTYT * c + 1, lx + 1, S[c]);
-            dnxt[c] = S[c].d;
-        }
+        // plane k+1 (issued DEPTH planes ago) into the free slot
+        for (int c = 0; c < CPT; ++c) put(b, ly + TYT * c + 1, lx + 1, S[c]);
         if (hly >= 0) put(b, hly, hlx, H);
+        if constexpr (NE > 0)
+            for (int c = 0; c < CPT; ++c) lex(plane * k, off[c], ex[c]);
         if constexpr (decltype(LOAD)::value) {
-            const int kp = mapz(k + 3);
-            for (int c = 0; c < kCPT; ++c) load_full(kp, off[c], S[c], true);
-            load_full(kp, hsrc, H, false);
+            const int kp = mapz(k + 1 + DEPTH);
+            for (int c = 0; c < CPT; ++c) load_full(kp, off[c], S[c]);
+            load_full(kp, hsrc, H);
         }
         lds_barrier();
         compute(k, a, b);
         lds_barrier();
-        for (int c = 0; c < kCPT; ++c) dcur[c] = dnxt[c];
     };
     constexpr std::true_type L1{};
     constexpr std::false_type L0{};
     const int nzr = z1 - z0;
-    int t = 0;
-    for (; t + 4 <= nzr; t += 2) {
-        iter(L1, t, S0, H0);
-        iter(L1, t + 1, S1, H1);
+    if constexpr (DEPTH == 2) {
+        int t = 0;
+        for (; t + 4 <= nzr; t += 2) {
+            iter(L1, t, S0, H0);
+            iter(L1, t + 1, S1, H1);
+        }
+        // the last one to three planes (t is even)
+        const int r = nzr - t;
+        if (r == 3) {
+            iter(L1, t, S0, H0);
+            iter(L0, t + 1, S1, H1);
+            iter(L0, t + 2, S0, H0);
+        } else if (r == 2) {
+            iter(L0, t, S0, H0);
+            iter(L0, t + 1, S1, H1);
+        } else if (r == 1) {
+            iter(L0, t, S0, H0);
+        }
+    } else {
+        for (int t = 0; t + 1 < nzr; ++t) iter(L1, t, S0, H0);
+        iter(L0, nzr - 1, S0, H0);
     }
-    // the last one to three planes (t is even)
-    const int r = nzr - t;
-    if (r == 3) {
-        iter(L1, t, S0, H0);
-        iter(L0, t + 1, S1, H1);
-        iter(L0, t + 2, S0, H0);
-    } else if (r == 2) {
-        iter(L0, t, S0, H0);
-        iter(L0, t + 1, S1, H1);
-    } else if (r == 1) {
-        iter(L0, t, S0, H0);
-    }
+}
+
+// y = D^-1 A (s x) (PRE: Jacobi-scaled Krylov operator, dE the E diagonal of
+// the Picard iteration) or y = A x with flux rescaling xF/yF (!PRE: the
+// physical operator of one Picard iteration with E diagonal dE).
+template <class AT, class ST, bool PRE>
+__global__ void __launch_bounds__(tile_threads<AT>())
+    k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
+                  const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
+                  const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
+                  AT *__restrict__ y, AT xF, AT yF)
+{
+    __shared__ AT lds[2][Rec<PRE>::NL][kLY][kLX];
+    const long long N = g.N;
+    const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
+    const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
+    auto lex = [&](long long pb, unsigned o, AT(&e)[1]) __attribute__((always_inline)) { e[0] = ld_off(dE + pb, o); };
+    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[1])
+                   __attribute__((always_inline)) {
+        const long long pb = (long long)g.nx * g.ny * k;
+        const AT dEc = e[0];
+        AT yE = dEc * S.Ec + nu * S.dEs, yFq[3];
+        for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + S.sc) * S.Fc[q] + nu * S.dF[q];
+        if constexpr (PRE) {
+            yE *= AT(1) / (dEc + half * S.sumC_nb);
+            const AT iDF = AT(1) / (AT(1) + S.sc + half * S.sumC_nb);
+            for (int q = 0; q < 3; ++q) yFq[q] *= iDF;
+        }
+        if (active) {
+            st_off(y + pb, o, yE);
+            for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, o, yFq[q] * yF);
+        }
+    };
+    tile_sweep<AT, ST, PRE, false, 1>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

@@ -231,12 +231,12 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum NV per-thread values over the workgroup (kBlock threads, 1D) and store
+// Sum NV per-thread values over the workgroup (NT threads, 1D) and store
 // them at partials[slot * NV + q].  Fixed order: reruns are bitwise identical.
-template <int NV>
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_store(double (&v)[NV], double *partials, long long slot)
 {
-    __shared__ double sh[NV][kBlock / 64];
+    __shared__ double sh[NV][NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -247,7 +247,7 @@ __device__ __forceinline__ void block_store(double (&v)[NV], double *partials, l
     if (threadIdx.x < NV) {
         double s = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += sh[threadIdx.x][w];
+        for (int w = 0; w < NT / 64; ++w) s += sh[threadIdx.x][w];
         partials[slot * NV + threadIdx.x] = s;
     }
 }

@@ -31,7 +31,8 @@ namespace {
 template <class CT, class AT>
 __global__ void __launch_bounds__(kBlock) k_setup(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP,
                                                   const CT *__restrict__ kR, const CT *__restrict__ f, AT *__restrict__ sR,
-                                                  AT *__restrict__ fA, const double *__restrict__ E,
+                                                  double *__restrict__ sR64, AT *__restrict__ fA,
+                                                  const double *__restrict__ E,
                                                   const double *__restrict__ F, const double *__restrict__ T,
                                                   double *__restrict__ X, double *__restrict__ X0,
                                                   double *__restrict__ Tc, double *partials)
@@ -42,6 +43,7 @@ __global__ void __launch_bounds__(kBlock) k_setup(Grid g, const CT *__restrict__
     if (c < N) {
         double r = (double)rho[c], p = (double)kP[c], s = (double)kR[c];
         sR[c] = (AT)(g.cdt * r * s);
+        if (sR64) sR64[c] = g.cdt * r * s;
         bool bad = !(r >= 0) || !(p >= 0) || !(s >= 0) || !isfinite(r) || !isfinite(p) || !isfinite(s);
         for (int t = 0; t < 6; ++t) {
             double ft = (double)f[t * N + c];
@@ -133,6 +135,75 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     if (MODE == RES_KRYLOV) block_store<5>(v, partials, blockIdx.x);
+}
+
+// The RES_KRYLOV residual of k_residual as a tile sweep: FP64 state, stored
+// coefficients, and the face speeds and sR precomputed in FP64 once per step
+// (the same values k_residual derives per face).  Partial sums per tile.
+template <class CT, class KT, class DT>
+__global__ void __launch_bounds__(tile_threads<double>())
+    k_residual_tiled(Grid g, TileGeom tg, int picard_mode, const double *__restrict__ En,
+                     const double *__restrict__ Fn, const double *__restrict__ Tn, const double *__restrict__ Ts,
+                     const CT *__restrict__ rho, const CT *__restrict__ kP, const CT *__restrict__ f,
+                     const double *__restrict__ sR64, const double *__restrict__ Cf64, const double *__restrict__ X,
+                     KT *__restrict__ out, DT *__restrict__ dEA, double *partials)
+{
+    __shared__ double lds[2][Rec<true>::NL][kLY][kLX];
+    const long long N = g.N;
+    const long long plane = (long long)g.nx * g.ny;
+    const double invc = 1.0 / g.c, nu = g.nu, half = 0.5 * g.nu, aR = g.aR, cdt = g.cdt, cv = g.cv;
+    double acc[5] = {0, 0, 0, 0, 0};
+    auto lex = [&](long long pb, unsigned o, double(&e)[8]) __attribute__((always_inline)) {
+        e[0] = ld_off(En + pb, o);
+        for (int q = 0; q < 3; ++q) e[1 + q] = ld_off(Fn + q * N + pb, o);
+        e[4] = ld_off(Tn + pb, o);
+        e[5] = ld_off(Ts + pb, o);
+        e[6] = (double)ld_off(rho + pb, o);
+        e[7] = (double)ld_off(kP + pb, o);
+    };
+    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<double> &S, const double(&e)[8])
+                   __attribute__((always_inline)) {
+        const long long pb = plane * k;
+        const double r_ = e[6];
+        const double sP = cdt * r_ * e[7], sR = S.sc, alpha = r_ * cv;
+        const double T = e[5], T3 = T * T * T, T4 = T3 * T;
+        double dE, bE;
+        if (picard_mode == 0) {
+            dE = 1.0 + sP;
+            bE = e[0] + sP * aR * T4;
+        } else {
+            const double den = alpha + 4.0 * sP * aR * T3;
+            const double eta = den > 0 ? 4.0 * sP * aR * T3 / den : 0.0;
+            dE = 1.0 + sP * (1.0 - eta);
+            bE = e[0] + eta * alpha * e[4] - 3.0 * (1.0 - eta) * sP * aR * T4;
+        }
+        const double E = S.Ec;
+        const double rE = bE - (dE * E + nu * S.dEs);
+        const double DE = dE + half * S.sumC_nb, DF = 1.0 + sR + half * S.sumC_nb;
+        const double WE = 1.0 + sP + half * S.sumC_all, WF = 1.0 + sR + half * S.sumC_all;
+        const double zE = rE / DE;
+        double zF[3], zz = zE * zE, wf = 0, fn = 0;
+        for (int q = 0; q < 3; ++q) {
+            const double rF = e[1 + q] * invc - ((1.0 + sR) * S.Fc[q] + nu * S.dF[q]);
+            zF[q] = rF / DF;
+            zz += zF[q] * zF[q];
+            wf += (rF / WF) * (rF / WF);
+            fn += S.Fc[q] * S.Fc[q];
+        }
+        if (active) {
+            st_off(out + pb, o, (KT)zE);
+            for (int q = 0; q < 3; ++q) st_off(out + (1 + q) * N + pb, o, (KT)zF[q]);
+            st_off(dEA + pb, o, (DT)dE);
+            acc[0] += (rE / WE) * (rE / WE);
+            acc[1] += wf;
+            acc[2] += E * E;
+            acc[3] += fn;
+            acc[4] += zz;
+        }
+    };
+    tile_sweep<double, CT, true, true, 8>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64, X, 1.0,
+                                          1.0, lds, lex, epi);
+    block_store<5, tile_threads<double>()>(acc, partials, blockIdx.x);
 }
 
 // Raw dots <V_i, w> for i in [i0, i0+NV) and <w, w>, FP64 accumulation.  The
@@ -397,7 +468,7 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, V, W, part, small, total;
+    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, V, W, part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
@@ -426,6 +497,9 @@ Layout layout(long long N, const rad_params_t &p)
     L.dEA = take(N * ksz);
     L.fA = (mixed && p.coef_dtype == RAD_F64) ? take(6 * N * ksz) : take(0);
     L.Cf = take(3 * N * ksz);
+    // FP64 sR and face speeds of the FP64 residual (the FP64 path shares sR and Cf)
+    L.sR64 = take(mixed ? N * 8 : 0);
+    L.Cf64 = take(mixed ? 3 * N * 8 : 0);
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
     L.part = take((size_t)std::max<long long>(L.nblk_cells, L.nblk_vec) * 24 * 8);
@@ -503,10 +577,12 @@ int run_step(Solver &S)
     const long long stride = n4;
     rad_stats_t &st = S.stats;
 
+    const bool mixed = sizeof(KT) == 4;
+    double *sR64 = mixed ? S.at<double>(S.L.sR64) : (double *)sR;
     const double cb = sizeof(CT), kb = sizeof(KT), Nd = (double)N;
-    S.timed(K_SETUP, Nd * (9 * cb + 40 + kb + (fA ? 6 * kb : 0) + 72), [&] {
-        hipLaunchKernelGGL((k_setup<CT, AT>), gc, bl, 0, S.st, g, rho, kP, kR, f, sR, fA, S.En, S.Fn, S.Tn, X, X0,
-                           Tc, part);
+    S.timed(K_SETUP, Nd * (9 * cb + 40 + kb + (mixed ? 8 : 0) + (fA ? 6 * kb : 0) + 72), [&] {
+        hipLaunchKernelGGL((k_setup<CT, AT>), gc, bl, 0, S.st, g, rho, kP, kR, f, sR, mixed ? sR64 : nullptr, fA,
+                           S.En, S.Fn, S.Tn, X, X0, Tc, part);
     });
     S.reduce(S.L.nblk_cells, 1, 1, sm + SM_RED);
     RAD_TRY(S.read(SM_RED, 1));
@@ -519,11 +595,17 @@ int run_step(Solver &S)
     const int kUpd = sizeof(KT) == 4 ? K_UPDATEX32 : K_UPDATEX64;
     const double fb = fA ? kb : cb;   // bytes per stored tensor component read by the apply
     const TileGeom tg = tile_geom(g);
-    const dim3 gt((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)), bt(256);
+    const dim3 gt((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)), bt(tile_threads<AT>()),
+        bt64(tile_threads<double>());
     AT *Cf = S.at<AT>(S.L.Cf);
+    double *Cf64 = mixed ? S.at<double>(S.L.Cf64) : (double *)Cf;
     S.timed(K_SETUP, Nd * (3 * cb + 3 * kb), [&] {
         hipLaunchKernelGGL((k_face_coef<CT, AT>), gc, bl, 0, S.st, g, rho, kR, f, Cf);
     });
+    if (mixed)
+        S.timed(K_SETUP, Nd * (3 * cb + 3 * 8), [&] {
+            hipLaunchKernelGGL((k_face_coef<CT, double>), gc, bl, 0, S.st, g, rho, kR, f, Cf64);
+        });
     auto apply = [&](const KT *x, const double *xs, KT *y) {
         const int tok = prof_begin(kApply, S.st);
         if (fA)
@@ -538,11 +620,12 @@ int run_step(Solver &S)
     // its norm's inverse becomes the scale s_0 of V[0].
     double nrm[5];
     auto residual = [&]() -> int {
-        S.timed(K_RESIDUAL, Nd * (32 + 48 + 9 * cb + 5 * kb), [&] {
-            hipLaunchKernelGGL((k_residual<CT, KT, AT, RES_KRYLOV>), gc, bl, 0, S.st, g, p.mode, S.En, S.Fn, S.Tn,
-                               Tc, rho, kP, kR, f, X, X + N, 1.0, V, dEA, nullptr, part);
+        // streams X, En/Fn/Tn/Ts, sR and face speeds (FP64), f, rho, kP; writes V[0], dE
+        S.timed(K_RESIDUAL, Nd * (32 + 48 + 32 + 8 * cb + 5 * kb), [&] {
+            hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT>), gt, bt64, 0, S.st, g, tg, p.mode, S.En, S.Fn, S.Tn,
+                               Tc, rho, kP, f, sR64, Cf64, X, V, dEA, part);
         });
-        S.reduce(S.L.nblk_cells, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
+        S.reduce(gt.x, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
         RAD_TRY(S.read(SM_RED, 5));
         for (int q = 0; q < 5; ++q) nrm[q] = h[SM_RED + q];
         st.refine_sweeps++;
@@ -711,7 +794,7 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
 {
     const TileGeom tg = tile_geom(g);
     hipLaunchKernelGGL((k_apply_tiled<AT, CT, false>), dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)),
-                       dim3(256), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
+                       dim3(tile_threads<AT>()), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
                        (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
                        (AT)(1.0 / c), (AT)c);
 }
