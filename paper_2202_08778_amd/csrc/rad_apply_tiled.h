@@ -67,10 +67,13 @@ inline TileGeom tile_geom(const Grid &g)
     TileGeom t;
     t.tiles_x = (g.nx + kTX - 1) / kTX;
     t.tiles_y = (g.ny + kTY - 1) / kTY;
-    // z-range per workgroup: enough workgroups to fill the chip several times over
+    // z-range per workgroup: long enough that the two extra planes read per
+    // column stay a small fraction, at most 64 planes so that x/y neighbours
+    // progress together (their shared halo rows then hit in L2), and at least
+    // 1024 tiles to fill the chip (measured best at 256^3: 32, at 512^3: 64)
     const long long cols = (long long)t.tiles_x * t.tiles_y;
     int kz = g.nz;
-    while (kz > 8 && cols * ((g.nz + kz - 1) / kz) < 4096) kz = (kz + 1) / 2;
+    while (kz > 8 && (kz > 64 || cols * ((g.nz + kz - 1) / kz) < 1024)) kz = (kz + 1) / 2;
     t.kz = kz;
     t.tiles_z = (g.nz + kz - 1) / kz;
     return t;
