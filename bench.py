@@ -67,26 +67,20 @@ def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=
     return dict(seconds=t1 - t0, stats=stats, state=(E, F, T), prev=prev, profile=prof)
 
 
-# kernel-class names of the library profiler -> kernel names in the rocprofv3 counter summary
-PROFILE_KERNELS = {"orth_update_fp32": "k_orth_update<float>", "apply_fp32": "k_apply<float, float>",
-                   "multidot_fp32": "k_multidot<float, 16>", "residual_fp64": "k_residual<float, float, float, 0>",
-                   "update_x_fp32": "k_update_x<float>"}
-
-
 def measured_traffic(kernel_class):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since the counters were taken."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy) of one library kernel
+    class, from the committed rocprofv3 counter summary of the 256^3 mixed step, or None when the kernel
+    sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_256.json")
-    name = PROFILE_KERNELS.get(kernel_class)
-    if name is None or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = b"".join(open(os.path.join(ROOT, "paper_2202_08778_amd", "csrc", f), "rb").read()
-                   for f in ("rad_single.hip", "rad_device.h"))
+                   for f in ("rad_single.hip", "rad_device.h", "rad_apply_tiled.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
-    k = rec["kernels"].get(name)
+    k = rec.get("classes", {}).get(kernel_class)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
