@@ -106,12 +106,62 @@ def cpu_baseline(n_sample, tol):
                       f"iterations, converged={st['converged']}"}
 
 
+def bench_batched(args, torch, np, rad, W):
+    """The batched path: 1024 independent Dirichlet blocks (edges 8..32, per-block dt and kappa), mixed
+    precision, one persistent launch per step replayed from a HIP graph, inputs restored before each step."""
+    batch = W.batched_blocks(nblocks=1024, seed=4)
+    descs, ar = rad.pack_blocks(batch["blocks"])
+    cells = sum(b["n"] ** 3 for b in batch["blocks"])
+    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1)
+    g = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
+    dev = [g(ar["E"]), g(ar["F"]), g(ar["T"])] + [g(ar[k], torch.float32) for k in ("rho", "kP", "kR", "f")]
+    init = [t.clone() for t in dev[:3]]
+    plan = rad.Plan(descs, p)
+    if args.autotune:
+        log("autotuning the batched launch shape ...")
+        plan.autotune(*dev)
+    stats = None
+    times = []
+    for s in range(args.warmup + args.steps):
+        for t, t0 in zip(dev[:3], init):
+            t.copy_(t0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = plan.step(*dev)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if s >= args.warmup:
+            times.append(dt)
+        log(f"  [batched] {'warmup ' if s < args.warmup else ''}step {s}: {1000 * dt:.0f} ms")
+    st = rad.Plan.read_stats(stats)
+    sec = sum(times)
+    conv = int((st["status"] == 0).sum())
+    res = {"metric": "batched implicit VET rad-step cell-updates/s (1024 AMR-like blocks, mixed precision)",
+           "value": cells * args.steps / sec, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1000.0 * sec / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "1024 Dirichlet blocks, edges uniform on {8,12,16,24,32}, dt 1..1000 crossings, "
+                                  "kappa 1e-2..1e3 per block, one persistent graph-replayed launch per step",
+                      "cells": cells, "gmres_m": p.gmres_m,
+                      "launch": dict(zip(("threads", "per_cu", "largest_first"), plan.launch_shape()))},
+           "blocks_converged": conv, "blocks": len(batch["blocks"]),
+           "krylov_iters_max_block": int(st["krylov_iters"].max()),
+           "krylov_iters_total": int(st["krylov_iters"].sum())}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid edge (the metric is quoted at 256)")
+    ap.add_argument("--n", type=int, default=None, help="grid edge (default 256; 512 for --workload scale)")
+    ap.add_argument("--workload", choices=("precision", "scale"), default="precision",
+                    help="precision: mixed-depth 256^3 recipe (the metric's workload); scale: lognormal sigma 2, "
+                         "optical depth 1e-4..1e4, dt = 200 crossings (512^3, 3 steps)")
+    ap.add_argument("--batched", action="store_true",
+                    help="instead: the batched path on 1024 AMR-like Dirichlet blocks (one graph replay per step)")
+    ap.add_argument("--autotune", action="store_true", help="with --batched: autotune the launch shape first")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--gmres-m", type=int, default=8,
                     help="GMRES restart length (8 is fastest on this workload: orthogonalisation grows with m "
@@ -136,9 +186,14 @@ def main():
     from paper_2202_08778_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    n = args.n
-    log(f"generating the mixed-depth workload at {n}^3 ...")
-    d = W.mixed_depth_256(n=n, steps=args.steps)
+    if args.batched:
+        return bench_batched(args, torch, np, rad, W)
+    scale = args.workload == "scale"
+    n = args.n or (512 if scale else 256)
+    log(f"generating the {args.workload} workload at {n}^3 ...")
+    d = W.mixed_depth_512(n=n, steps=args.steps) if scale else W.mixed_depth_256(n=n, steps=args.steps)
+    recipe = ("lognormal sigma 2, optical depth 1e-4..1e4, dt = 200 light-crossing times" if scale else
+              "lognormal sigma 1.5, optical depth 1e-3..1e3, dt = 50 light-crossing times")
     dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
     state0 = (dev(d["E"]), dev(d["F"]), dev(d["T"]))
     c32 = tuple(dev(d[k], torch.float32) for k in ("rho", "kP", "kR", "f"))
@@ -170,7 +225,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"mixed-depth medium {n}^3, periodic, dt = 50 light-crossing times, "
+        "config": {"workload": f"mixed-depth medium {n}^3 ({recipe}), periodic, "
                                f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
                    "cells": N, "gmres_m": args.gmres_m,
                    "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},

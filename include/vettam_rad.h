@@ -156,10 +156,12 @@ typedef struct rad_plan_s *rad_plan;
 /* Device workspace (bytes) for a batch. */
 size_t rad_batched_workspace_bytes(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p);
 
-/* Build a plan: validate the descriptors, order blocks (largest first,
- * interleaved across the chip's XCDs), upload the descriptor table into the
- * workspace and build the HIP graph of the persistent launch.  The workspace
- * must stay valid for the plan's lifetime. */
+/* Build a plan: validate the descriptors, order blocks (largest first),
+ * upload the descriptor table into the workspace and build the HIP graph of
+ * the persistent launch.  The launch shape comes from the autotune cache
+ * ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad) when it holds this batch
+ * signature, else 512-thread workgroups, one per CU.  The workspace must stay
+ * valid for the plan's lifetime. */
 int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p,
                      void *workspace, size_t ws_bytes, void *stream, rad_plan *out);
 
@@ -176,6 +178,10 @@ int rad_autotune_batched(rad_plan plan, double *E, double *F, double *T_gas, con
 int rad_step_batched(rad_plan plan, double *E, double *F, double *T_gas, const void *rho,
                      const void *kappa_P, const void *kappa_R, const void *f_ij,
                      rad_stats_t *dev_stats, void *stream);
+
+/* The plan's launch shape: threads per workgroup, workgroups per CU and
+ * whether blocks are queued largest first (any output may be NULL). */
+int rad_plan_launch_shape(rad_plan plan, int *threads, int *per_cu, int *largest_first);
 
 void rad_plan_destroy(rad_plan plan);
 

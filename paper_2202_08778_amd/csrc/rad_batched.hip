@@ -934,6 +934,16 @@ extern "C" int rad_autotune_batched(rad_plan P, double *E, double *F, double *T_
     return RAD_OK;
 }
 
+extern "C" int rad_plan_launch_shape(rad_plan P, int *threads, int *per_cu, int *largest_first)
+{
+    clear_error();
+    if (!P) return fail(RAD_EINVAL, "plan is NULL");
+    if (threads) *threads = P->nt;
+    if (per_cu) *per_cu = P->per_cu;
+    if (largest_first) *largest_first = P->lpt ? 1 : 0;
+    return RAD_OK;
+}
+
 extern "C" void rad_plan_destroy(rad_plan P)
 {
     if (!P) return;

@@ -80,6 +80,8 @@ def _load():
     L.rad_autotune_batched.restype = I
     L.rad_step_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
     L.rad_step_batched.restype = I
+    L.rad_plan_launch_shape.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
+    L.rad_plan_launch_shape.restype = I
     L.rad_plan_destroy.argtypes = [P]
     L.rad_plan_destroy.restype = None
     L.rad_profile_enable.argtypes = [I]
@@ -99,7 +101,8 @@ lib = _load()
 
 EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_residual", "rad_face_speeds",
             "rad_apply", "rad_exchange", "rad_batched_workspace_bytes", "rad_plan_batched",
-            "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_destroy",
+            "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_launch_shape",
+            "rad_plan_destroy",
             "rad_profile_enable", "rad_profile_reset", "rad_profile_count", "rad_profile_get", "rad_last_error")
 
 
@@ -386,6 +389,12 @@ class Plan:
         _check(lib.rad_step_batched(self.handle, *self._args(E, F, T, rho, kP, kR, f),
                                     _ptr(stats, name="stats"), _stream(stream)))
         return stats
+
+    def launch_shape(self):
+        """(threads per workgroup, workgroups per CU, largest-first queue) of the plan's launch."""
+        t, c, l = ct.c_int(), ct.c_int(), ct.c_int()
+        _check(lib.rad_plan_launch_shape(self.handle, ct.byref(t), ct.byref(c), ct.byref(l)))
+        return t.value, c.value, bool(l.value)
 
     @staticmethod
     def read_stats(stats):

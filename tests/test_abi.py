@@ -91,3 +91,4 @@ def test_other_entry_points_validate(rad):
     assert rad.lib.rad_apply(4, 4, 4, 8, 8, 8, 8, 8, 8, 1.0, 1.0, bc, ct.byref(p), 5, None) == rad.RAD_EINVAL
     assert rad.lib.rad_exchange(0, 8, 8, 8, 8, 8, 1.0, ct.byref(p), None) == rad.RAD_EINVAL
     assert rad.lib.rad_face_speeds(4, 4, 4, None, 8, 8, 1.0, bc, ct.byref(p), 8, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_plan_launch_shape(None, None, None, None) == rad.RAD_EINVAL

@@ -74,6 +74,8 @@ def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1):
     plan = rad.Plan(descs, p)
     if autotune:
         plan.autotune(*dev)
+    nt, per_cu, _ = plan.launch_shape()
+    assert nt in (256, 512) and per_cu in (1, 2)
     outs, stats = [], []
     init = [t.clone() for t in dev[:3]]
     for r in range(reps):
