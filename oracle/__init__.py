@@ -79,6 +79,8 @@ def lib():
                                   ct.POINTER(P), P, ct.POINTER(_Stats)]
         L.or_rad_step.restype = ct.c_int
         L.or_num_threads.restype = ct.c_int
+        L.or_closure.argtypes = [ct.c_long, ct.c_int, ct.c_double] + [ct.c_void_p] * 5
+        L.or_closure.restype = None
         _lib = L
     return _lib
 
@@ -217,3 +219,18 @@ def exchange_T(alpha, Tn, sP, aR, E):
     neg = ct.c_int(0)
     T = lib().or_exchange_T(float(alpha), float(Tn), float(sP), float(aR), float(E), ct.byref(neg))
     return T, bool(neg.value)
+
+
+CLOSURE = {"eddington": 0, "m1": 1}
+
+
+def closure(E, F, kind="m1", c=1.0):
+    """Local closure of Sec. 4.1 from the time-lagged (E, F): f of shape (6,) + E.shape (xx, yy, zz, xy, xz, yz)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    assert F.shape == (3,) + E.shape
+    f = np.empty((6,) + E.shape, dtype=np.float64)
+    fp = (ct.c_void_p * 6)(*(f[q].ctypes.data for q in range(6)))
+    lib().or_closure(E.size, CLOSURE[kind], float(c), E.ctypes.data, F[0].ctypes.data, F[1].ctypes.data,
+                     F[2].ctypes.data, fp)
+    return f

@@ -650,3 +650,42 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
     free(o.dE); free(o.pre[0]); free(o.pre[1]);
     return st->converged ? 0 : 1;
 }
+
+/* ------------------------------------------------------------------------
+ * Local closures of the closure comparison (Sec. 4.1): the Eddington
+ * approximation f = I/3, and the M1 closure from the time-lagged state,
+ *   f = (1 - chi)/2 I + (3 chi - 1)/2 n n,   n = F / |F|,
+ *   chi = (3 + 4 g^2) / (5 + 2 sqrt(4 - 3 g^2)),   g = |F| / (c E).
+ * Readings where the paper is silent: g is clipped to [0, 1] (|F| <= cE for a
+ * physical field); where E <= 0, g = 1 if F != 0 and g = 0 if F = 0; with F = 0
+ * the n n term has zero weight (chi(0) = 1/3), so n is not needed. */
+void or_closure(long ncells, int kind, double c, const double *E, const double *Fx, const double *Fy,
+                const double *Fz, double *const f[6])
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < ncells; ++i) {
+        double fxx = 1.0 / 3.0, fyy = 1.0 / 3.0, fzz = 1.0 / 3.0, fxy = 0.0, fxz = 0.0, fyz = 0.0;
+        if (kind == OR_M1) {
+            const double F2 = Fx[i] * Fx[i] + Fy[i] * Fy[i] + Fz[i] * Fz[i];
+            const double Fm = sqrt(F2);
+            double g;
+            if (E[i] > 0.0)
+                g = Fm / (c * E[i]);
+            else
+                g = F2 > 0.0 ? 1.0 : 0.0;
+            if (g > 1.0) g = 1.0;
+            const double chi = (3.0 + 4.0 * g * g) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * g * g));
+            const double iso = 0.5 * (1.0 - chi), beam = 0.5 * (3.0 * chi - 1.0);
+            double nx = 0.0, ny = 0.0, nz = 0.0;
+            if (F2 > 0.0) { nx = Fx[i] / Fm; ny = Fy[i] / Fm; nz = Fz[i] / Fm; }
+            fxx = iso + beam * nx * nx;
+            fyy = iso + beam * ny * ny;
+            fzz = iso + beam * nz * nz;
+            fxy = beam * nx * ny;
+            fxz = beam * nx * nz;
+            fyz = beam * ny * nz;
+        }
+        f[0][i] = fxx; f[1][i] = fyy; f[2][i] = fzz;
+        f[3][i] = fxy; f[4][i] = fxz; f[5][i] = fyz;
+    }
+}

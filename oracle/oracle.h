@@ -115,6 +115,13 @@ double or_exchange_T(double alpha, double Tn, double sP, double aR, double E, in
 int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                 double *E, double *const F[3], double *T, or_stats *st);
 
+/* Local closures (Sec. 4.1): kind OR_EDDINGTON gives f = I/3, OR_M1 the M1
+ * tensor from the lagged (E, F) (see oracle.c for the readings).  Unpadded
+ * arrays of ncells; f[0..5] = xx, yy, zz, xy, xz, yz. */
+enum { OR_EDDINGTON = 0, OR_M1 = 1 };
+void or_closure(long ncells, int kind, double c, const double *E, const double *Fx, const double *Fy,
+                const double *Fz, double *const f[6]);
+
 int or_num_threads(void);
 
 #ifdef __cplusplus

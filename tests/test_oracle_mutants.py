@@ -35,6 +35,12 @@ MUTANTS = [
     ("return cf->rho[i] * g->cv; }", "return g->cv; }"),
     ("double q = 10.0 * g->h * sigR;", "double q = 10.0 * sigR;"),
     ("for (int d = 0; d < 3; ++d) div +=", "for (int d = 0; d < 2; ++d) div +="),
+    ("const double chi = (3.0 + 4.0 * g * g)", "const double chi = (3.0 + 2.0 * g * g)"),
+    ("beam = 0.5 * (3.0 * chi - 1.0);", "beam = 0.5 * (3.0 * chi + 1.0);"),
+    ("if (g > 1.0) g = 1.0;", "if (g > 2.0) g = 2.0;"),
+    ("g = Fm / (c * E[i]);", "g = Fm / E[i];"),
+    ("fxy = beam * nx * ny;", "fxy = beam * nx * nz;"),
+    ("double fxx = 1.0 / 3.0, fyy = 1.0 / 3.0,", "double fxx = 1.0 / 3.0, fyy = 0.3,"),
 ]
 
 

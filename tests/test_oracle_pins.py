@@ -483,3 +483,114 @@ def test_diffusing_pulse_l1_in_paper_range(regime, steps_list):
         s = 4 * D * t * mu * mu + 1
         an = np.exp(-mu * mu * x * x / s) / math.sqrt(s)
         assert _l1(E.ravel(), an) < 0.06
+
+
+# ---------------------------------------------------------- local closures (Sec. 4.1)
+
+def _as_mats(f):
+    """(6, ...) tensor planes -> (..., 3, 3) symmetric matrices."""
+    xx, yy, zz, xy, xz, yz = f
+    return np.stack([np.stack([xx, xy, xz], -1), np.stack([xy, yy, yz], -1), np.stack([xz, yz, zz], -1)], -2)
+
+
+def _boosted_isotropic_chi(g):
+    """Eddington factor of a radiation field that is isotropic in a frame moving at speed beta c:
+    flux factor g = 4 beta / (3 + beta^2) and chi = (1 + 3 beta^2) / (3 + beta^2) (Levermore's
+    derivation of the M1 relation, independent of the closed form in chi(g))."""
+    g = np.asarray(g, dtype=np.float64)
+    beta = np.where(g > 0, (2.0 - np.sqrt(4.0 - 3.0 * g * g)) / np.where(g > 0, g, 1.0), 0.0)
+    return (1.0 + 3.0 * beta ** 2) / (3.0 + beta ** 2)
+
+
+def test_eddington_closure_is_isotropic_third():
+    rng = np.random.default_rng(21)
+    E = rng.uniform(0.1, 2.0, 50)
+    F = rng.standard_normal((3, 50))
+    f = oracle.closure(E, F, "eddington", c=3.0)
+    assert np.all(f[:3] == 1.0 / 3.0) and np.all(f[3:] == 0.0)
+
+
+def test_m1_limits_zero_flux_and_free_streaming():
+    c = 2.5
+    rng = np.random.default_rng(22)
+    E = rng.uniform(0.5, 3.0, 40)
+    f0 = oracle.closure(E, np.zeros((3, 40)), "m1", c=c)
+    assert np.allclose(f0[:3], 1.0 / 3.0, rtol=0, atol=1e-16) and np.all(f0[3:] == 0.0)
+    n = rng.standard_normal((3, 40))
+    n /= np.linalg.norm(n, axis=0)
+    for scale in (1.0, 1.7):   # |F| = cE, and an unphysical |F| > cE clipped to it
+        f = _as_mats(oracle.closure(E, scale * c * E * n, "m1", c=c))
+        # free streaming: f = n n (rank one, eigenvalue 1 along n, 0 across)
+        assert np.allclose(f, np.einsum("i...,j...->...ij", n, n), rtol=0, atol=1e-14)
+
+
+def test_m1_eigenstructure_matches_boosted_isotropic_field():
+    """Along n the eigenvalue is the Eddington factor chi, across it (1 - chi) / 2 (unit trace); chi
+    agrees with the boosted-isotropic parametrisation for every flux factor in [0, 1]."""
+    c = 0.7
+    rng = np.random.default_rng(23)
+    m = 400
+    E = rng.uniform(0.2, 5.0, m)
+    g = np.concatenate([np.linspace(0, 1, 101), rng.uniform(0, 1, m - 101)])
+    n = rng.standard_normal((3, m))
+    n /= np.linalg.norm(n, axis=0)
+    F = g * c * E * n
+    f = _as_mats(oracle.closure(E, F, "m1", c=c))
+    chi = _boosted_isotropic_chi(g)
+    assert np.allclose(np.trace(f, axis1=-2, axis2=-1), 1.0, rtol=0, atol=1e-14)
+    assert np.allclose(f, np.swapaxes(f, -1, -2), rtol=0, atol=0)
+    fn = np.einsum("kij,jk->ki", f, n)
+    assert np.allclose(fn, (chi * n).T, rtol=0, atol=1e-14)
+    u = np.cross(n.T, rng.standard_normal((m, 3)))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    assert np.allclose(np.einsum("kij,kj->ki", f, u), 0.5 * (1 - chi)[:, None] * u, rtol=0, atol=1e-14)
+    # chi grows monotonically from 1/3 (isotropic) to 1 (a beam)
+    order = np.argsort(g)
+    lam = np.einsum("ki,ki->k", fn, n.T)[order]
+    assert abs(lam[0] - 1 / 3) < 1e-15 and abs(lam[-1] - 1.0) < 1e-14 and np.all(np.diff(lam) >= -1e-15)
+
+
+def test_m1_rotation_covariance_and_nonpositive_energy():
+    rng = np.random.default_rng(24)
+    m = 64
+    E = rng.uniform(0.1, 2.0, m)
+    F = 0.6 * E * rng.standard_normal((3, m)) / np.sqrt(3)
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    a, b, cc, d = q
+    R = np.array([[a * a + b * b - cc * cc - d * d, 2 * (b * cc - a * d), 2 * (b * d + a * cc)],
+                  [2 * (b * cc + a * d), a * a - b * b + cc * cc - d * d, 2 * (cc * d - a * b)],
+                  [2 * (b * d - a * cc), 2 * (cc * d + a * b), a * a - b * b - cc * cc + d * d]])
+    f = _as_mats(oracle.closure(E, F, "m1"))
+    fr = _as_mats(oracle.closure(E, R @ F, "m1"))
+    assert np.allclose(fr, R @ f @ R.T, rtol=0, atol=1e-14)
+    # readings: E <= 0 with a flux is a beam along F; E <= 0 without flux is isotropic
+    Ez = np.array([0.0, -1.0, -2.0])
+    Fz = np.array([[0.0, 3.0, 0.0], [0.0, 4.0, 0.0], [0.0, 0.0, 0.0]])
+    fz = _as_mats(oracle.closure(Ez, Fz, "m1"))
+    assert np.allclose(fz[0], np.eye(3) / 3, atol=1e-16) and np.allclose(fz[2], np.eye(3) / 3, atol=1e-16)
+    nb = np.array([0.6, 0.8, 0.0])
+    assert np.allclose(fz[1], np.outer(nb, nb), atol=1e-15)
+
+
+def test_m1_closed_streaming_evolution_matches_dft():
+    """A beam (F = cE along x, sigma = 0) closed by M1 recomputed from the lagged state before every
+    step keeps f = e_x e_x, so three closure-coupled steps equal three steps of implicit upwinding."""
+    n, nu, c, steps = 48, 1.3, 2.0, 3
+    h = 1.0 / n
+    rng = np.random.default_rng(25)
+    E0 = 1.0 + np.exp(-((np.arange(n) - n / 2) / 5.0) ** 2) + 0.1 * rng.standard_normal(n)
+    shape = (1, 1, n)
+    E = E0.reshape(shape)
+    F = np.zeros((3,) + shape)
+    F[0] = c * E
+    T = np.ones(shape)
+    zero = np.zeros(shape)
+    for _ in range(steps):
+        f = oracle.closure(E, F, "m1", c=c)
+        P = _problem(dict(rho=np.ones(shape), kP=zero, kR=zero, f=f, dt=nu * h / c, dx=h, bc="periodic", c=c))
+        E, F, T, st = P.step(E, F, T, tol=1e-14)
+    k = np.arange(n)
+    expect = np.real(np.fft.ifft(np.fft.fft(E0) / (1.0 + nu * (1.0 - np.exp(-2j * np.pi * k / n))) ** steps))
+    assert np.max(np.abs(E.reshape(n) - expect)) <= 1e-11 * np.max(np.abs(expect))
+    assert np.max(np.abs(F[1])) == 0.0 and np.max(np.abs(F[2])) == 0.0
