@@ -205,6 +205,20 @@ def main():
     value = N * args.steps / mixed["seconds"]
     out_m = [t.cpu().numpy() for t in mixed["state"]]
 
+    # local M1 closure (Sec. 4.1) from the final state, FP32 output as the mixed path consumes it
+    rad.profile_reset()
+    rad.profile(True)
+    fcl = torch.empty((6, n, n, n), dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        rad.rad_closure(mixed["state"][0], mixed["state"][1], "m1", d["c"], f=fcl)
+    torch.cuda.synchronize()
+    cl = rad.profile_read().get("closure")
+    rad.profile(False)
+    del fcl
+    closure = None if not cl else {"kernel": "k_closure (M1, FP32 out)", "us_per_launch": 1000 * cl["ms"] / cl["launches"],
+                                   "algorithmic_bytes_per_launch": cl["bytes"] / cl["launches"],
+                                   "achieved_GBps": cl["bytes"] / (cl["ms"] * 1e-3) / 1e9}
+
     fp64 = None
     if not args.no_fp64:
         log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
@@ -253,6 +267,8 @@ def main():
         r = P.scaled_residual(*prev, *out_m)
         res["oracle_scaled_residual_last_step"] = r[3]
 
+    if closure:
+        res["closure_m1"] = closure
     prof = mixed["profile"]
     if prof:
         dom = max(prof, key=lambda k: prof[k]["ms"])

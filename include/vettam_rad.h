@@ -136,6 +136,22 @@ int rad_apply(int nx, int ny, int nz, const void *x, void *y, const void *dE,
 int rad_exchange(long long n, const double *E, const double *T_n, double *T,
                  const void *rho, const void *kappa_P, double dt, const rad_params_t *p, void *stream);
 
+/* ---------------------------------------------------------------- closures
+ * Local closures of Sec. 4.1 (the comparison of closures), evaluated from the
+ * time-lagged state to give f_ij for the next step:
+ *   RAD_CLOSURE_EDDINGTON: f = I/3 (the Eddington approximation);
+ *   RAD_CLOSURE_M1: f = (1 - chi)/2 I + (3 chi - 1)/2 n n, n = F/|F|,
+ *     chi = (3 + 4 g^2) / (5 + 2 sqrt(4 - 3 g^2)), g = |F| / (c E),
+ *     with g clipped to [0, 1]; where E <= 0, g = 1 if F != 0 and 0 if F = 0.
+ * E (ncells) and F (three planes Fx|Fy|Fz of ncells) are FP64 device arrays;
+ * f_ij (six planes xx|yy|zz|xy|xz|yz of ncells, caller-owned) is written in
+ * out_dtype (RAD_F64 or RAD_F32).  FP64 arithmetic; one streaming pass,
+ * asynchronous on `stream`.  ncells = 0 is a no-op. */
+typedef enum { RAD_CLOSURE_EDDINGTON = 0, RAD_CLOSURE_M1 = 1 } rad_closure_kind;
+
+int rad_closure(long long ncells, const double *E, const double *F, int kind, double c, void *f_ij,
+                int out_dtype, void *stream);
+
 /* ---------------------------------------------------------------- batched
  * Many independent blocks, each an n^3 interior with ng ghost layers of fixed
  * Dirichlet data (E, F and its own rho, kappa, f), solved in one persistent

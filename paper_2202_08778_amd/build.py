@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvettam_rad.so")
-SOURCES = ["rad_host.cpp", "rad_single.hip", "rad_batched.hip"]
+SOURCES = ["rad_host.cpp", "rad_single.hip", "rad_batched.hip", "rad_closure.hip"]
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

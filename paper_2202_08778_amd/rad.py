@@ -80,6 +80,8 @@ def _load():
     L.rad_autotune_batched.restype = I
     L.rad_step_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
     L.rad_step_batched.restype = I
+    L.rad_closure.argtypes = [ct.c_longlong, P, P, I, ct.c_double, P, I, P]
+    L.rad_closure.restype = I
     L.rad_plan_launch_shape.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
     L.rad_plan_launch_shape.restype = I
     L.rad_plan_destroy.argtypes = [P]
@@ -100,7 +102,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_residual", "rad_face_speeds",
-            "rad_apply", "rad_exchange", "rad_batched_workspace_bytes", "rad_plan_batched",
+            "rad_apply", "rad_exchange", "rad_closure", "rad_batched_workspace_bytes", "rad_plan_batched",
             "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_launch_shape",
             "rad_plan_destroy",
             "rad_profile_enable", "rad_profile_reset", "rad_profile_count", "rad_profile_get", "rad_last_error")
@@ -280,6 +282,23 @@ def rad_exchange(E, Tn, rho, kappa_P, dt, p: Params, T=None, stream=None):
                             _ptr(rho, cd, n, "rho"), _ptr(kappa_P, cd, n, "kappa_P"), float(dt), ct.byref(p),
                             _stream(stream)))
     return T
+
+
+CLOSURE = {"eddington": 0, "m1": 1}
+
+
+def rad_closure(E, F, kind="m1", c=1.0, out_dtype=None, f=None, stream=None):
+    """Eddington tensor of a local closure (Sec. 4.1) from the lagged (E, F): returns f_ij with shape
+    (6,) + E.shape (planes xx, yy, zz, xy, xz, yz) in out_dtype (float64 default, or float32)."""
+    torch = _torch()
+    n = E.numel()
+    f64 = torch.float64
+    if f is None:
+        f = torch.empty((6,) + tuple(E.shape), dtype=out_dtype or f64, device=E.device)
+    od = 0 if f.dtype == f64 else 1
+    _check(lib.rad_closure(n, _ptr(E, f64, n, "E"), _ptr(F, f64, 3 * n, "F"), CLOSURE[kind], float(c),
+                           _ptr(f, f.dtype, 6 * n, "f"), od, _stream(stream)))
+    return f
 
 
 def profile(on=True):

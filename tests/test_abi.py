@@ -92,3 +92,10 @@ def test_other_entry_points_validate(rad):
     assert rad.lib.rad_exchange(0, 8, 8, 8, 8, 8, 1.0, ct.byref(p), None) == rad.RAD_EINVAL
     assert rad.lib.rad_face_speeds(4, 4, 4, None, 8, 8, 1.0, bc, ct.byref(p), 8, None) == rad.RAD_EINVAL
     assert rad.lib.rad_plan_launch_shape(None, None, None, None) == rad.RAD_EINVAL
+    # closures: bad kind, c, dtype or pointers are rejected on the host; an empty grid is a no-op
+    assert rad.lib.rad_closure(8, 8, 8, 2, 1.0, 8, 0, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_closure(8, 8, 8, 1, 0.0, 8, 0, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_closure(8, 8, 8, 1, 1.0, 8, 3, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_closure(8, None, 8, 1, 1.0, 8, 0, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_closure(-1, 8, 8, 1, 1.0, 8, 0, None) == rad.RAD_EINVAL
+    assert rad.lib.rad_closure(0, None, None, 1, 1.0, None, 0, None) == rad.RAD_OK
