@@ -73,6 +73,10 @@ typedef struct {
     int prec;             /* rad_precision: FP64, or FP32 Krylov with FP64 residual/refinement */
     int mode;             /* rad_picard_mode: paper's lagged emission, or emission linearised at T_* */
     int coef_dtype;       /* rad_dtype of rho, kappa_P, kappa_R, f_ij */
+    int anderson_m;       /* 0: plain Picard; 1..5: Anderson acceleration of the Picard map
+                             T_* -> T(E(T_*)) with this many past iterates (the acceleration the
+                             paper names for its linearly convergent Picard iteration, Sec. 4.3).
+                             Single-grid rad_step only; the batched plan requires 0. */
 } rad_params_t;
 
 typedef struct {
@@ -91,7 +95,8 @@ typedef struct {
 } rad_stats_t;
 
 /* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
- * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients. */
+ * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients,
+ * anderson_m 0. */
 void rad_default_params(rad_params_t *p);
 
 /* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */

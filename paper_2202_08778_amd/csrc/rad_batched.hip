@@ -801,6 +801,7 @@ extern "C" int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const
     if (!out) return fail(RAD_EINVAL, "out is NULL");
     *out = nullptr;
     RAD_TRY(check_params(p));
+    if (p->anderson_m != 0) return fail(RAD_EINVAL, "the batched path runs plain Picard: anderson_m must be 0");
     Geometry G;
     RAD_TRY(check_blocks(nblocks, desc, G));
     if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");

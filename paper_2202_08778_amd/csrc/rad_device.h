@@ -20,6 +20,7 @@ namespace vr {
 
 constexpr int kBlock = 256;   // threads per workgroup of the streaming kernels (4 wave64)
 constexpr int kMaxM = 64;     // largest GMRES restart length
+constexpr int kMaxAnderson = 5;  // most past iterates of the Anderson-accelerated Picard map
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2 };
 

@@ -51,6 +51,8 @@ int check_params(const rad_params_t *p)
         return fail(RAD_EINVAL, "unknown Picard mode %d", p->mode);
     if (p->coef_dtype != RAD_F64 && p->coef_dtype != RAD_F32)
         return fail(RAD_EINVAL, "unknown coefficient dtype %d", p->coef_dtype);
+    if (p->anderson_m < 0 || p->anderson_m > kMaxAnderson)
+        return fail(RAD_EINVAL, "anderson_m must be in [0, %d]", kMaxAnderson);
     return RAD_OK;
 }
 
@@ -182,4 +184,5 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->prec = RAD_FP64;
     p->mode = RAD_PICARD_LINEARISED;
     p->coef_dtype = RAD_F64;
+    p->anderson_m = 0;
 }

@@ -319,7 +319,8 @@ __global__ void __launch_bounds__(kBlock)
 template <class CT>
 __global__ void __launch_bounds__(kBlock)
     k_exchange(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP, const double *__restrict__ Tn,
-               double *__restrict__ Tc, double *__restrict__ X, double *__restrict__ X0, double *partials)
+               double *__restrict__ Tc, double *__restrict__ X, double *__restrict__ X0, double *partials,
+               double *__restrict__ Gk, double *__restrict__ fk)
 {
     const long long N = g.N;
     long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -337,6 +338,10 @@ __global__ void __launch_bounds__(kBlock)
         const double WT = alpha + 4.0 * sP * aR * T3;
         const double dT = T - Tc[c];
         Tc[c] = T;
+        if (Gk) {  // Picard map value and its residual for the Anderson history
+            Gk[c] = T;
+            fk[c] = dT;
+        }
         v[0] = WT > 0 ? (RT / WT) * (RT / WT) : 0.0;
         v[1] = T * T;
         v[2] = dT * dT;
@@ -353,6 +358,127 @@ __global__ void __launch_bounds__(kBlock)
         v[7] = neg ? 1.0 : 0.0;
     }
     block_store<8>(v, partials, blockIdx.x);
+}
+
+// Anderson acceleration of the Picard map T_* -> G(T_*) = T(E(T_*)) (the
+// acceleration Sec. 4.3 names for the linearly convergent lagged iteration).
+// History slots i < H hold past map values G_i and residuals f_i = G_i - T_*,i.
+struct AAHist {
+    const double *f[kMaxAnderson];
+    const double *G[kMaxAnderson];
+    double gamma[kMaxAnderson];
+};
+
+// Normal equations of min_gamma || f_k - sum_i gamma_i (f_k - f_i) ||: with
+// d_i = f_k - f_i, partial sums of d_i d_j (i <= j), then d_i f_k, then f_k f_k.
+template <int H>
+__global__ void __launch_bounds__(kBlock)
+    k_aa_gram(long long N, const double *__restrict__ fk, AAHist h, double *partials)
+{
+    constexpr int NV = H * (H + 1) / 2 + H + 1;
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0;
+    const long long step = (long long)gridDim.x * kBlock;
+    for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < N; c += step) {
+        const double r = fk[c];
+        double d[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) d[i] = r - h.f[i][c];
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i)
+#pragma unroll
+            for (int j = i; j < H; ++j) v[q++] += d[i] * d[j];
+#pragma unroll
+        for (int i = 0; i < H; ++i) v[q++] += d[i] * r;
+        v[q] += r * r;
+    }
+    block_store<NV>(v, partials, blockIdx.x);
+}
+
+// Next guess T_* = G_k - sum_i gamma_i (G_k - G_i), kept >= 0, and the scaled
+// gas-energy residual R_T at (E, T_*) for the convergence test of that state.
+template <class CT, int H>
+__global__ void __launch_bounds__(kBlock)
+    k_aa_mix(Grid g, const double *__restrict__ Gk, AAHist h, const CT *__restrict__ rho, const CT *__restrict__ kP,
+             const double *__restrict__ Tn, const double *__restrict__ X, double *__restrict__ Tc, double *partials)
+{
+    const long long N = g.N;
+    double v[2] = {0, 0};
+    const long long step = (long long)gridDim.x * kBlock;
+    for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < N; c += step) {
+        const double gk = Gk[c];
+        double T = gk;
+#pragma unroll
+        for (int i = 0; i < H; ++i) T -= h.gamma[i] * (gk - h.G[i][c]);
+        T = fmax(T, 0.0);
+        Tc[c] = T;
+        const double r_ = (double)rho[c];
+        const double sP = g.cdt * r_ * (double)kP[c], alpha = r_ * g.cv, aR = g.aR, E = X[c];
+        const double T3 = T * T * T;
+        const double RT0 = alpha * (T - Tn[c]) + sP * (aR * T3 * T - E);
+        const double RT = (T == 0.0 && RT0 > 0.0) ? 0.0 : RT0;
+        const double WT = alpha + 4.0 * sP * aR * T3;
+        v[0] += WT > 0 ? (RT / WT) * (RT / WT) : 0.0;
+        v[1] += T * T;
+    }
+    block_store<2>(v, partials, blockIdx.x);
+}
+
+template <int H>
+void launch_aa_gram(int h, dim3 g, hipStream_t st, long long N, const double *fk, const AAHist &hist,
+                    double *partials)
+{
+    if constexpr (H > 1) {
+        if (h < H) return launch_aa_gram<H - 1>(h, g, st, N, fk, hist, partials);
+    }
+    hipLaunchKernelGGL((k_aa_gram<H>), g, dim3(kBlock), 0, st, N, fk, hist, partials);
+}
+
+template <class CT, int H>
+void launch_aa_mix(int h, dim3 gr, hipStream_t st, const Grid &g, const double *Gk, const AAHist &hist,
+                   const CT *rho, const CT *kP, const double *Tn, const double *X, double *Tc, double *partials)
+{
+    if constexpr (H > 1) {
+        if (h < H) return launch_aa_mix<CT, H - 1>(h, gr, st, g, Gk, hist, rho, kP, Tn, X, Tc, partials);
+    }
+    hipLaunchKernelGGL((k_aa_mix<CT, H>), gr, dim3(kBlock), 0, st, g, Gk, hist, rho, kP, Tn, X, Tc, partials);
+}
+
+// Solve (D + lambda I) gamma = b for a symmetric positive semi-definite D of
+// order n by Cholesky; lambda = 1e-12 max diag.  False if a pivot vanishes.
+bool aa_solve(int n, const double *D, const double *b, double *gamma)
+{
+    double L[kMaxAnderson][kMaxAnderson] = {};
+    double dmax = 0;
+    for (int i = 0; i < n; ++i) dmax = std::max(dmax, D[i * n + i]);
+    if (!(dmax > 0)) return false;
+    const double lam = 1e-12 * dmax;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = D[i * n + j] + (i == j ? lam : 0.0);
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(s > 1e-14 * dmax)) return false;
+                L[i][i] = std::sqrt(s);
+            } else {
+                L[i][j] = s / L[j][j];
+            }
+        }
+    }
+    double y[kMaxAnderson];
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+        y[i] = s / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k][i] * gamma[k];
+        gamma[i] = s / L[i][i];
+    }
+    return true;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -468,7 +594,7 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, V, W, part, small, total;
+    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, V, W, part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
@@ -500,6 +626,10 @@ Layout layout(long long N, const rad_params_t &p)
     // FP64 sR and face speeds of the FP64 residual (the FP64 path shares sR and Cf)
     L.sR64 = take(mixed ? N * 8 : 0);
     L.Cf64 = take(mixed ? 3 * N * 8 : 0);
+    // Anderson history: m+1 slots of map values and residuals (N FP64 each)
+    const int ma = p.anderson_m;
+    L.AAG = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
+    L.AAf = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
     L.part = take((size_t)std::max<long long>(L.nblk_cells, L.nblk_vec) * 24 * 8);
@@ -510,7 +640,7 @@ Layout layout(long long N, const rad_params_t &p)
 
 // Small device area (doubles) that reductions write and the host reads back.
 enum {
-    SM_RED = 0,     // generic reduction results (<= 16)
+    SM_RED = 0,     // generic reduction results (<= 32)
     SM_DOTS = 32,   // <v_i, w>, i <= kMaxM (+16 slack for chunked writes)
     SM_WW = 120,    // <w, w>
     SM_NRM = 121,   // ||v_{j+1}||^2 after orthogonalisation
@@ -644,6 +774,11 @@ int run_step(Solver &S)
     double resT = 0, best_res = INFINITY;
     int best_at = 0;
     int status = RAD_NOT_CONVERGED;
+    // Anderson acceleration of the Picard map (off when anderson_m = 0)
+    const int aa_m = p.anderson_m;
+    double *AAG = aa_m > 0 ? S.at<double>(S.L.AAG) : nullptr, *AAf = aa_m > 0 ? S.at<double>(S.L.AAf) : nullptr;
+    std::vector<int> aa_hist;  // history slots, most recent first
+    double aa_best = INFINITY;
     const bool trace = trace_enabled();
     int reorth = 0, cycles = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gvec(m + 1), y(m), sv(m + 1);
@@ -661,12 +796,16 @@ int run_step(Solver &S)
             break;
         }
         if (k >= p.max_picard) break;
-        // stall: no new best residual within the last 5 Picard iterations (active-set cycling)
+        // stall: no new best residual within the last 5 Picard iterations (active-set cycling);
+        // with Anderson mixing the residual is not monotone: its history restarts after
+        // max(3, m) iterations without a new best, and the step gives up after 15
         if (res < best_res) {
             best_res = res;
             best_at = k;
-        } else if (k - best_at >= 5) {
+        } else if (k - best_at >= (aa_m > 0 ? 15 : 5)) {
             break;
+        } else if (aa_m > 0 && k - best_at >= std::max(3, aa_m)) {
+            aa_hist.clear();
         }
 
         // ---- Krylov solve of A d = r for the correction, accumulated into X.
@@ -750,17 +889,64 @@ int run_step(Solver &S)
         st.krylov_iters += its;
 
         // ---- exchange: per-cell Newton for T, diagnostics of the iteration
-        S.timed(K_EXCHANGE, Nd * (2 * cb + 16 + 64 + 40),
-                [&] { hipLaunchKernelGGL((k_exchange<CT>), gc, bl, 0, S.st, g, rho, kP, S.Tn, Tc, X, X0, part); });
+        const int aslot = aa_m > 0 ? k % (aa_m + 1) : 0;
+        double *Gk = aa_m > 0 ? AAG + (size_t)aslot * N : nullptr, *fk = aa_m > 0 ? AAf + (size_t)aslot * N : nullptr;
+        S.timed(K_EXCHANGE, Nd * (2 * cb + 16 + 64 + 40 + (aa_m > 0 ? 16 : 0)), [&] {
+            hipLaunchKernelGGL((k_exchange<CT>), gc, bl, 0, S.st, g, rho, kP, S.Tn, Tc, X, X0, part, Gk, fk);
+        });
         S.reduce(S.L.nblk_cells, 8, 8, sm + SM_RED);
         RAD_TRY(S.read(SM_RED, 8));
         const double *e = h + SM_RED;
         resT = e[1] > 0 ? std::sqrt(e[0] / e[1]) : std::sqrt(e[0]);
-        const double cE = e[4] > 0 ? std::sqrt(e[3] / e[4]) : 0.0;
-        const double cF = (e[6] + e[4]) > 0 ? std::sqrt(e[5]) / (std::sqrt(e[6]) + std::sqrt(e[4])) : 0.0;
-        const double cT = e[1] > 0 ? std::sqrt(e[2] / e[1]) : 0.0;
+        const double e1 = e[1], e2 = e[2], e3 = e[3], e4 = e[4], e5 = e[5], e6 = e[6], e7 = e[7];
+        if (aa_m > 0) {
+            // Anderson mixing of the map values: restart the history when the map residual
+            // grows a hundredfold over the best one seen (the mixing is then not helping)
+            const double fn = std::sqrt(e2);
+            if (fn > 1e2 * aa_best) aa_hist.clear();
+            aa_best = std::min(aa_best, fn);
+            int H = (int)aa_hist.size();
+            if (H > 0) {
+                AAHist hh{};
+                for (int i = 0; i < H; ++i) {
+                    hh.f[i] = AAf + (size_t)aa_hist[i] * N;
+                    hh.G[i] = AAG + (size_t)aa_hist[i] * N;
+                }
+                const int nv = H * (H + 1) / 2 + H + 1;
+                S.timed(K_EXCHANGE, Nd * 8 * (H + 1), [&] {
+                    launch_aa_gram<kMaxAnderson>(H, gv, S.st, N, fk, hh, part);
+                });
+                S.reduce(S.L.nblk_vec, nv, nv, sm + SM_RED);
+                RAD_TRY(S.read(SM_RED, nv));
+                double D[kMaxAnderson * kMaxAnderson], b[kMaxAnderson], gam[kMaxAnderson];
+                // the most recent H' <= H entries form the leading block; drop the oldest until it solves
+                int Hs = H;
+                for (; Hs > 0; --Hs) {
+                    int q = 0;
+                    for (int i = 0; i < H; ++i)
+                        for (int j = i; j < H; ++j, ++q)
+                            if (i < Hs && j < Hs) D[i * Hs + j] = D[j * Hs + i] = h[SM_RED + q];
+                    for (int i = 0; i < Hs; ++i) b[i] = h[SM_RED + H * (H + 1) / 2 + i];
+                    if (aa_solve(Hs, D, b, gam)) break;
+                }
+                if (Hs > 0) {
+                    for (int i = 0; i < Hs; ++i) hh.gamma[i] = gam[i];
+                    S.timed(K_EXCHANGE, Nd * (8 * (Hs + 1) + 2 * cb + 32), [&] {
+                        launch_aa_mix<CT, kMaxAnderson>(Hs, gv, S.st, g, Gk, hh, rho, kP, S.Tn, X, Tc, part);
+                    });
+                    S.reduce(S.L.nblk_vec, 2, 2, sm + SM_RED);
+                    RAD_TRY(S.read(SM_RED, 2));
+                    resT = h[SM_RED + 1] > 0 ? std::sqrt(h[SM_RED] / h[SM_RED + 1]) : std::sqrt(h[SM_RED]);
+                }
+            }
+            aa_hist.insert(aa_hist.begin(), aslot);
+            if ((int)aa_hist.size() > aa_m) aa_hist.pop_back();
+        }
+        const double cE = e4 > 0 ? std::sqrt(e3 / e4) : 0.0;
+        const double cF = (e6 + e4) > 0 ? std::sqrt(e5) / (std::sqrt(e6) + std::sqrt(e4)) : 0.0;
+        const double cT = e1 > 0 ? std::sqrt(e2 / e1) : 0.0;
         st.rel_change = std::max(cE, std::max(cF, cT));
-        st.neg_cells = (int)e[7];
+        st.neg_cells = (int)e7;
         st.picard_iters = k + 1;
         if (trace)
             std::fprintf(stderr,

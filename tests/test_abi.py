@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(rad):
 def test_defaults(rad):
     p = rad.params()
     assert (p.c, p.a_R, p.c_v) == (1.0, 1.0, 1.0)
-    assert p.gmres_m == 12 and p.prec == 0 and p.mode == 1 and p.eps_R == 1e-2
+    assert p.gmres_m == 12 and p.prec == 0 and p.mode == 1 and p.eps_R == 1e-2 and p.anderson_m == 0
 
 
 def _step(rad, p, nx=4, ny=4, nz=4, ptr=0x1000, bc="periodic", dt=1.0, dx=1.0, ws=None, wsb=None):
@@ -66,12 +66,19 @@ def test_rad_step_rejects_bad_arguments_on_host(rad, case, msg):
 
 
 @pytest.mark.parametrize("field,val", [("gmres_m", 0), ("gmres_m", 65), ("c", 0.0), ("tol", 0.0), ("prec", 7),
-                                       ("mode", 3), ("coef_dtype", 2), ("max_picard", 0), ("a_R", -1.0)])
+                                       ("mode", 3), ("coef_dtype", 2), ("max_picard", 0), ("a_R", -1.0),
+                                       ("anderson_m", -1), ("anderson_m", 6)])
 def test_rad_step_rejects_bad_params(rad, field, val):
     p = rad.params()
     setattr(p, field, val)
     assert _step(rad, p) == rad.RAD_EINVAL
     assert rad.lib.rad_workspace_bytes(4, 4, 4, ct.byref(p)) == 0
+
+
+def test_anderson_history_takes_workspace(rad):
+    a = rad.lib.rad_workspace_bytes(32, 32, 32, ct.byref(rad.params()))
+    b = rad.lib.rad_workspace_bytes(32, 32, 32, ct.byref(rad.params(anderson_m=3)))
+    assert b - a >= 2 * 4 * 32 ** 3 * 8   # (m + 1) map values and residuals, FP64
 
 
 def test_workspace_grows_with_restart_length_and_precision(rad):
