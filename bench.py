@@ -33,13 +33,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30):
-    """Warm up, restore the initial state, then time `steps` consecutive rad_step calls."""
+def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30, autotune=None):
+    """Warm up, restore the initial state, then time `steps` consecutive rad_step calls.  autotune:
+    None, "tiles" (tune the stencil z-ranges) or "all" (also the restart length), outside the timing."""
     E, F, T = (t.clone() for t in state0)
     rho, kP, kR, f = coefs
     p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol, gmres_m=m)
     p.coef_dtype = 1 if rho.dtype == torch.float32 else 0
     ws = rad.alloc_workspace(rad.workspace_bytes(E.shape, p))
+    tuned = None
+    if autotune:
+        tuned = rad.autotune_step(E, F, T, rho, kP, kR, f, d["dt"], d["dx"], d["bc"], p,
+                                  tune_restart=autotune == "all", workspace=ws)
+        log(f"  [{prec}] autotune: {tuned}")
+        p.gmres_m = tuned["gmres_m"]
     for s in range(warmup):
         st = rad.rad_step(E, F, T, rho, kP, kR, f, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
         log(f"  [{prec}] warmup step {s}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
@@ -64,7 +71,7 @@ def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=
     prof = rad.profile_read() if profile else {}
     rad.profile(False)
     del ws
-    return dict(seconds=t1 - t0, stats=stats, state=(E, F, T), prev=prev, profile=prof)
+    return dict(seconds=t1 - t0, stats=stats, state=(E, F, T), prev=prev, profile=prof, tuned=tuned)
 
 
 def measured_traffic(kernel_class):
@@ -161,7 +168,9 @@ def main():
                          "optical depth 1e-4..1e4, dt = 200 crossings (512^3, 3 steps)")
     ap.add_argument("--batched", action="store_true",
                     help="instead: the batched path on 1024 AMR-like Dirichlet blocks (one graph replay per step)")
-    ap.add_argument("--autotune", action="store_true", help="with --batched: autotune the launch shape first")
+    ap.add_argument("--autotune", nargs="?", const="tiles", choices=("tiles", "all"), default=None,
+                    help="autotune before timing: the stencil z-ranges (tiles) or also the restart length (all); "
+                         "with --batched: the launch shape")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--gmres-m", type=int, default=8,
                     help="GMRES restart length (8 is fastest on this workload: orthogonalisation grows with m "
@@ -201,7 +210,7 @@ def main():
 
     log("mixed path (FP32 Krylov + FP64 residual/refinement/exchange, FP32 coefficient storage):")
     mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile,
-                     args.gmres_m)
+                     args.gmres_m, args.autotune)
     value = N * args.steps / mixed["seconds"]
     out_m = [t.cpu().numpy() for t in mixed["state"]]
 
@@ -223,7 +232,8 @@ def main():
     if not args.no_fp64:
         log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
         c64 = tuple(dev(d[k]) for k in ("rho", "kP", "kR", "f"))
-        fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False, args.gmres_m)
+        fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False, args.gmres_m,
+                        args.autotune)
         del c64
 
     res = {
@@ -241,7 +251,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"mixed-depth medium {n}^3 ({recipe}), periodic, "
                                f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
-                   "cells": N, "gmres_m": args.gmres_m,
+                   "cells": N, "gmres_m": (mixed["tuned"] or {}).get("gmres_m", args.gmres_m),
+                   "autotune": mixed["tuned"],
                    "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
         "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
         "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / args.steps,

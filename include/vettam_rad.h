@@ -112,6 +112,23 @@ int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
              double dt, double dx, const int bc[6], const rad_params_t *p,
              void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
 
+/* Autotune rad_step for this grid, boundary set, precision and coefficient
+ * type on the caller's data (same arguments as rad_step; the state E, F, T_gas
+ * is left as it was on entry).  Times the stencil's z-range per workgroup
+ * (8..128 planes) separately for the Krylov apply and the FP64 residual and,
+ * if tune_restart != 0, one full step for each GMRES restart length in
+ * {6, 8, 10, 12, 16, 24, 32, 48, 64} up to params->gmres_m (the workspace's
+ * size).  The z-ranges are stored in the autotune cache
+ * ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad) and used by every later
+ * rad_step call with the same key; the fastest converged restart length is
+ * returned in *gmres_m as a recommendation (rad_step keeps the caller's).
+ * Outputs may be NULL.  Synchronous. */
+int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
+                      const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
+                      double dt, double dx, const int bc[6], const rad_params_t *p,
+                      void *workspace, size_t ws_bytes, void *stream, int tune_restart,
+                      int *kz_apply, int *kz_residual, int *gmres_m);
+
 /* Nonlinear residual of the backward-Euler system at a state (E, F, T) given
  * the old state (E_n, F_n, T_n): R holds 5 planes [R_E | R_Fx | R_Fy | R_Fz | R_T]
  * (FP64, device).  Stream-ordered, asynchronous. */

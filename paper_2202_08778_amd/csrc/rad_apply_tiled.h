@@ -17,6 +17,7 @@
 #pragma once
 #include "rad_device.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace vr {
@@ -62,18 +63,26 @@ struct TileGeom {
     int tiles_x, tiles_y, tiles_z, kz;
 };
 
-inline TileGeom tile_geom(const Grid &g)
+// kz_req > 0: that z-range (planes per workgroup, clipped to nz).  Otherwise
+// the default rule: the longest range up to kz_cap planes (so the two extra
+// planes a column reads stay a small fraction, while x/y neighbours progress
+// together and their shared halo rows hit in L2) that still gives min_tiles
+// workgroups to fill the chip.  Defaults measured by the autotuner at 256^3 and
+// 512^3: the Krylov apply is fastest at 32 planes, the FP64 residual (one
+// 512-thread workgroup per CU) at 128.
+inline TileGeom tile_geom(const Grid &g, int kz_req = 0, int kz_cap = 32, long long min_tiles = 1024)
 {
     TileGeom t;
     t.tiles_x = (g.nx + kTX - 1) / kTX;
     t.tiles_y = (g.ny + kTY - 1) / kTY;
-    // z-range per workgroup: long enough that the two extra planes read per
-    // column stay a small fraction, at most 64 planes so that x/y neighbours
-    // progress together (their shared halo rows then hit in L2), and at least
-    // 1024 tiles to fill the chip (measured best at 256^3: 32, at 512^3: 64)
+    if (kz_req > 0) {
+        t.kz = std::min(kz_req, g.nz);
+        t.tiles_z = (g.nz + t.kz - 1) / t.kz;
+        return t;
+    }
     const long long cols = (long long)t.tiles_x * t.tiles_y;
     int kz = g.nz;
-    while (kz > 8 && (kz > 64 || cols * ((g.nz + kz - 1) / kz) < 1024)) kz = (kz + 1) / 2;
+    while (kz > 8 && (kz > kz_cap || cols * ((g.nz + kz - 1) / kz) < min_tiles)) kz = (kz + 1) / 2;
     t.kz = kz;
     t.tiles_z = (g.nz + kz - 1) / kz;
     return t;

@@ -27,7 +27,6 @@
 #include <string>
 #include <vector>
 
-#include <sys/stat.h>
 
 using namespace vr;
 
@@ -725,32 +724,12 @@ int launch_direct(rad_plan P, hipStream_t st)
     return RAD_OK;
 }
 
-std::string cache_path()
-{
-    const char *d = std::getenv("VETTAM_RAD_CACHE_DIR");
-    std::string dir;
-    if (d && d[0])
-        dir = d;
-    else if (const char *h = std::getenv("HOME"))
-        dir = std::string(h) + "/.cache/vettam_rad";
-    else
-        return "";
-    // create the directory levels that are missing (no shell involved)
-    for (size_t pos = 1; pos <= dir.size(); ++pos)
-        if (pos == dir.size() || dir[pos] == '/') (void)mkdir(dir.substr(0, pos).c_str(), 0755);
-    return dir + "/autotune.txt";
-}
-
 std::string plan_key(rad_plan P)
 {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    std::string arch = "unknown";
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     int hist[65] = {0};
     for (auto &d : P->desc) hist[d.n]++;
     std::ostringstream os;
-    os << arch << "|cu" << P->cus << "|p" << P->p.prec << "|c" << P->p.coef_dtype << "|m" << P->p.gmres_m << "|";
+    os << "batched|" << device_tag() << "|p" << P->p.prec << "|c" << P->p.coef_dtype << "|m" << P->p.gmres_m << "|";
     for (int k = 1; k <= 64; ++k)
         if (hist[k]) os << k << "x" << hist[k] << ",";
     return os.str();
@@ -758,31 +737,22 @@ std::string plan_key(rad_plan P)
 
 bool cache_lookup(rad_plan P)
 {
-    std::string path = cache_path();
-    if (path.empty()) return false;
-    std::ifstream in(path);
-    std::string line, key = plan_key(P);
-    while (std::getline(in, line)) {
-        const size_t t = line.find('\t');
-        if (t == std::string::npos || line.substr(0, t) != key) continue;
-        int nt, pc, lpt;
-        if (std::sscanf(line.c_str() + t + 1, "%d %d %d", &nt, &pc, &lpt) == 3 && (nt == 256 || nt == 512) && pc >= 1 &&
-            pc <= kMaxSlotsPerCU) {
-            P->nt = nt;
-            P->per_cu = pc;
-            P->lpt = lpt != 0;
-            return true;
-        }
+    std::string v;
+    if (!cache_get(plan_key(P), v)) return false;
+    int nt, pc, lpt;
+    if (std::sscanf(v.c_str(), "%d %d %d", &nt, &pc, &lpt) == 3 && (nt == 256 || nt == 512) && pc >= 1 &&
+        pc <= kMaxSlotsPerCU) {
+        P->nt = nt;
+        P->per_cu = pc;
+        P->lpt = lpt != 0;
+        return true;
     }
     return false;
 }
 
 void cache_store(rad_plan P)
 {
-    std::string path = cache_path();
-    if (path.empty()) return;
-    std::ofstream out(path, std::ios::app);
-    if (out) out << plan_key(P) << "\t" << P->nt << " " << P->per_cu << " " << (P->lpt ? 1 : 0) << "\n";
+    cache_put(plan_key(P), std::to_string(P->nt) + " " + std::to_string(P->per_cu) + " " + (P->lpt ? "1" : "0"));
 }
 
 }  // namespace

@@ -1,12 +1,15 @@
-// rad_host.cpp -- error state, defaults and parameter checks of the C ABI.
+// rad_host.cpp -- error state, defaults, parameter checks, profiler and autotune cache of the C ABI.
 #include "rad_host.h"
 
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <fstream>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 namespace vr {
 
@@ -186,3 +189,61 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->coef_dtype = RAD_F64;
     p->anderson_m = 0;
 }
+
+// ------------------------------------------------------------------ autotune cache
+
+namespace vr {
+
+static std::string cache_file()
+{
+    const char *d = std::getenv("VETTAM_RAD_CACHE_DIR");
+    std::string dir;
+    if (d && d[0])
+        dir = d;
+    else if (const char *h = std::getenv("HOME"))
+        dir = std::string(h) + "/.cache/vettam_rad";
+    else
+        return "";
+    // create the directory levels that are missing (no shell involved)
+    for (size_t pos = 1; pos <= dir.size(); ++pos)
+        if (pos == dir.size() || dir[pos] == '/') (void)mkdir(dir.substr(0, pos).c_str(), 0755);
+    return dir + "/autotune.txt";
+}
+
+bool cache_get(const std::string &key, std::string &value)
+{
+    const std::string path = cache_file();
+    if (path.empty()) return false;
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        const size_t t = line.find('\t');
+        if (t == std::string::npos || line.compare(0, t, key) != 0 || t != key.size()) continue;
+        value = line.substr(t + 1);
+        found = true;
+    }
+    return found;
+}
+
+void cache_put(const std::string &key, const std::string &value)
+{
+    const std::string path = cache_file();
+    if (path.empty()) return;
+    std::ofstream out(path, std::ios::app);
+    if (out) out << key << "\t" << value << "\n";
+}
+
+std::string device_tag()
+{
+    int dev = 0, cus = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    return arch + "|cu" + std::to_string(cus);
+}
+
+}  // namespace vr

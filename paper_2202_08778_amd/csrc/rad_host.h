@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
 
 #include "../../include/vettam_rad.h"
 #include "rad_device.h"
@@ -26,6 +27,14 @@ __host__ __device__ inline size_t align_up(size_t b) { return (b + 255) & ~size_
 int prof_begin(int kid, hipStream_t st);
 void prof_end(int token, hipStream_t st, double bytes);
 void prof_resolve();
+
+// Autotune cache: one "key<TAB>value" line per tuned configuration in
+// $VETTAM_RAD_CACHE_DIR/autotune.txt (else ~/.cache/vettam_rad/autotune.txt).
+// The last line with a key wins.  device_tag() names the GPU (architecture
+// and compute-unit count) for use in keys.
+bool cache_get(const std::string &key, std::string &value);
+void cache_put(const std::string &key, const std::string &value);
+std::string device_tag();
 
 enum {
     K_SETUP = 0, K_RESIDUAL, K_APPLY32, K_APPLY64, K_MULTIDOT32, K_MULTIDOT64, K_ORTH32, K_ORTH64,

@@ -17,6 +17,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 using namespace vr;
@@ -659,6 +662,11 @@ struct Solver {
     double *E, *F, *T;
     double *host;  // pinned staging, SM_TOTAL doubles
     rad_stats_t stats;
+    int kz_apply = 0, kz_res = 0;  // tile z-ranges (0: default rule)
+    // tuning mode: after the setup and the first residual, time these z-ranges
+    // for the apply and the residual instead of stepping
+    const std::vector<int> *tune_kz = nullptr;
+    int tuned_apply = 0, tuned_res = 0;
 
     template <class P>
     P *at(size_t off) { return reinterpret_cast<P *>(ws + off); }
@@ -724,9 +732,9 @@ int run_step(Solver &S)
     const int kOrth = sizeof(KT) == 4 ? K_ORTH32 : K_ORTH64;
     const int kUpd = sizeof(KT) == 4 ? K_UPDATEX32 : K_UPDATEX64;
     const double fb = fA ? kb : cb;   // bytes per stored tensor component read by the apply
-    const TileGeom tg = tile_geom(g);
-    const dim3 gt((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)), bt(tile_threads<AT>()),
-        bt64(tile_threads<double>());
+    TileGeom tg = tile_geom(g, S.kz_apply), tgr = tile_geom(g, S.kz_res, 128, 256);
+    auto tiles = [](const TileGeom &t) { return dim3((unsigned)(t.tiles_x * t.tiles_y * t.tiles_z)); };
+    const dim3 bt(tile_threads<AT>()), bt64(tile_threads<double>());
     AT *Cf = S.at<AT>(S.L.Cf);
     double *Cf64 = mixed ? S.at<double>(S.L.Cf64) : (double *)Cf;
     S.timed(K_SETUP, Nd * (3 * cb + 3 * kb), [&] {
@@ -739,11 +747,11 @@ int run_step(Solver &S)
     auto apply = [&](const KT *x, const double *xs, KT *y) {
         const int tok = prof_begin(kApply, S.st);
         if (fA)
-            hipLaunchKernelGGL((k_apply_tiled<AT, AT, true>), gt, bt, 0, S.st, g, tg, (const AT *)fA, sR,
+            hipLaunchKernelGGL((k_apply_tiled<AT, AT, true>), tiles(tg), bt, 0, S.st, g, tg, (const AT *)fA, sR,
                                (const AT *)nullptr, (const AT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
         else
-            hipLaunchKernelGGL((k_apply_tiled<AT, CT, true>), gt, bt, 0, S.st, g, tg, f, sR, (const CT *)nullptr,
-                               (const CT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
+            hipLaunchKernelGGL((k_apply_tiled<AT, CT, true>), tiles(tg), bt, 0, S.st, g, tg, f, sR,
+                               (const CT *)nullptr, (const CT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
         prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
     };
     // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
@@ -752,10 +760,10 @@ int run_step(Solver &S)
     auto residual = [&]() -> int {
         // streams X, En/Fn/Tn/Ts, sR and face speeds (FP64), f, rho, kP; writes V[0], dE
         S.timed(K_RESIDUAL, Nd * (32 + 48 + 32 + 8 * cb + 5 * kb), [&] {
-            hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT>), gt, bt64, 0, S.st, g, tg, p.mode, S.En, S.Fn, S.Tn,
-                               Tc, rho, kP, f, sR64, Cf64, X, V, dEA, part);
+            hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT>), tiles(tgr), bt64, 0, S.st, g, tgr, p.mode, S.En, S.Fn,
+                               S.Tn, Tc, rho, kP, f, sR64, Cf64, X, V, dEA, part);
         });
-        S.reduce(gt.x, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
+        S.reduce(tiles(tgr).x, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
         RAD_TRY(S.read(SM_RED, 5));
         for (int q = 0; q < 5; ++q) nrm[q] = h[SM_RED + q];
         st.refine_sweeps++;
@@ -782,6 +790,46 @@ int run_step(Solver &S)
     const bool trace = trace_enabled();
     int reorth = 0, cycles = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gvec(m + 1), y(m), sv(m + 1);
+
+    if (S.tune_kz) {
+        // time each candidate z-range: 1 warm-up + 5 applies, 1 warm-up + 3 residuals
+        RAD_TRY(residual());
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best_a = INFINITY, best_r = INFINITY;
+        int rc = RAD_OK;
+        for (int kz : *S.tune_kz) {
+            tg = tile_geom(g, kz);
+            tgr = tg;
+            float ms_a = 0, ms_r = 0;
+            apply(V, sm + SM_S, W);
+            if (hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+            for (int r = 0; r < 5 && rc == RAD_OK; ++r) apply(V, sm + SM_S, W);
+            if (rc == RAD_OK && hipEventRecord(e1, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+            if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "apply trial failed");
+            if (rc == RAD_OK && hipEventElapsedTime(&ms_a, e0, e1) != hipSuccess) rc = fail(RAD_EHIP, "timing failed");
+            if (rc == RAD_OK) rc = residual();
+            if (rc == RAD_OK && hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+            for (int r = 0; r < 3 && rc == RAD_OK; ++r) rc = residual();
+            if (rc == RAD_OK && hipEventRecord(e1, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+            if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "residual trial failed");
+            if (rc == RAD_OK && hipEventElapsedTime(&ms_r, e0, e1) != hipSuccess) rc = fail(RAD_EHIP, "timing failed");
+            if (rc != RAD_OK) break;
+            if (trace) std::fprintf(stderr, "[rad] tune kz=%d: apply %.3f ms, residual %.3f ms\n", kz, ms_a / 5, ms_r / 3);
+            if (ms_a < best_a) {
+                best_a = ms_a;
+                S.tuned_apply = kz;
+            }
+            if (ms_r < best_r) {
+                best_r = ms_r;
+                S.tuned_res = kz;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+    }
 
     for (int k = 0;; ++k) {
         RAD_TRY(residual());
@@ -995,19 +1043,50 @@ extern "C" size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t
     return layout((long long)nx * ny * nz, *p).total;
 }
 
-extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
-                        const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
-                        const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
-                        rad_stats_t *stats)
+namespace {
+
+// autotune cache key of a single-grid configuration
+std::string single_key(int nx, int ny, int nz, const int bc[6], const rad_params_t &p)
 {
-    clear_error();
-    auto t0 = std::chrono::steady_clock::now();
-    if (stats) std::memset(stats, 0, sizeof(*stats));
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "single|%s|%dx%dx%d|p%d|c%d|bc%d%d%d%d%d%d", device_tag().c_str(), nx, ny, nz,
+                  p.prec, p.coef_dtype, bc[0], bc[1], bc[2], bc[3], bc[4], bc[5]);
+    return buf;
+}
+
+// tuned tile z-ranges per key, read from the cache file once per process
+std::mutex g_tile_mu;
+std::map<std::string, std::pair<int, int>> g_tiles;
+
+void tile_lookup(const std::string &key, int &kz_apply, int &kz_res)
+{
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tiles.find(key);
+    if (it == g_tiles.end()) {
+        std::string v;
+        int a = 0, r = 0, m = 0;
+        if (!cache_get(key, v) || std::sscanf(v.c_str(), "%d %d %d", &a, &r, &m) < 2 || a < 1 || r < 1) a = r = 0;
+        it = g_tiles.emplace(key, std::make_pair(a, r)).first;
+    }
+    kz_apply = it->second.first;
+    kz_res = it->second.second;
+}
+
+int dispatch_step(Solver &S)
+{
+    const bool mixed = S.p.prec == RAD_MIXED;
+    if (S.p.coef_dtype == RAD_F64) return mixed ? run_step<double, float>(S) : run_step<double, double>(S);
+    return mixed ? run_step<float, float>(S) : run_step<float, double>(S);
+}
+
+int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6],
+                const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream)
+{
     RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
     if (!E || !F || !T_gas || !rho || !kappa_P || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
     if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace) % 256) return fail(RAD_EINVAL, "workspace must be 256-byte aligned");
-    Solver S;
     S.p = *p;
     S.L = layout((long long)nx * ny * nz, *p);
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
@@ -1027,16 +1106,105 @@ extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_
     S.F = F;
     S.T = T_gas;
     std::memset(&S.stats, 0, sizeof(S.stats));
-    const bool mixed = p->prec == RAD_MIXED;
-    int rc;
-    if (p->coef_dtype == RAD_F64)
-        rc = mixed ? run_step<double, float>(S) : run_step<double, double>(S);
-    else
-        rc = mixed ? run_step<float, float>(S) : run_step<float, double>(S);
+    tile_lookup(single_key(nx, ny, nz, bc, *p), S.kz_apply, S.kz_res);
+    return RAD_OK;
+}
+
+}  // namespace
+
+extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                        const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                        const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
+                        rad_stats_t *stats)
+{
+    clear_error();
+    auto t0 = std::chrono::steady_clock::now();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Solver S;
+    RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
+                        stream));
+    const int rc = dispatch_step(S);
     S.stats.status = rc;
     S.stats.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S.stats;
     return rc;
+}
+
+extern "C" int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                                 const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                                 const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes,
+                                 void *stream, int tune_restart, int *kz_apply, int *kz_residual, int *gmres_m)
+{
+    clear_error();
+    Solver S;
+    RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
+                        stream));
+    // z-range candidates (planes per workgroup), clipped to the grid and deduplicated
+    std::vector<int> cand;
+    for (int kz : {8, 16, 32, 64, 128}) {
+        const int k = std::min(kz, nz);
+        if (std::find(cand.begin(), cand.end(), k) == cand.end()) cand.push_back(k);
+    }
+    S.tune_kz = &cand;
+    RAD_TRY(dispatch_step(S));
+    const int ka = S.tuned_apply, kr = S.tuned_res;
+    int best_m = p->gmres_m;
+    if (tune_restart) {
+        // full steps at each restart length the workspace allows, from the same state
+        const size_t N = (size_t)nx * ny * nz;
+        std::vector<double> save(5 * N);
+        hipStream_t st = (hipStream_t)stream;
+        HIP_TRY(hipMemcpyAsync(save.data(), E, N * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(save.data() + N, F, 3 * N * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(save.data() + 4 * N, T_gas, N * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        auto restore = [&]() -> int {
+            HIP_TRY(hipMemcpyAsync(E, save.data(), N * 8, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(F, save.data() + N, 3 * N * 8, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(T_gas, save.data() + 4 * N, N * 8, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            return RAD_OK;
+        };
+        std::vector<int> ms;
+        for (int m : {6, 8, 10, 12, 16, 24, 32, 48, 64})
+            if (m <= p->gmres_m) ms.push_back(m);
+        if (std::find(ms.begin(), ms.end(), p->gmres_m) == ms.end()) ms.push_back(p->gmres_m);
+        double best_t = INFINITY;
+        for (int m : ms) {
+            RAD_TRY(restore());
+            Solver T;
+            RAD_TRY(init_solver(T, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace,
+                                ws_bytes, stream));
+            T.p.gmres_m = m;  // the layout keeps the caller's (largest) restart length
+            T.kz_apply = ka;
+            T.kz_res = kr;
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = dispatch_step(T);
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (rc < 0) {
+                (void)restore();
+                return rc;
+            }
+            clear_error();
+            if (trace_enabled())
+                std::fprintf(stderr, "[rad] tune m=%d: %.3f s, rc %d, %d Krylov\n", m, sec, rc, T.stats.krylov_iters);
+            if (rc == RAD_OK && sec < best_t) {
+                best_t = sec;
+                best_m = m;
+            }
+        }
+        RAD_TRY(restore());
+    }
+    const std::string key = single_key(nx, ny, nz, bc, *p);
+    cache_put(key, std::to_string(ka) + " " + std::to_string(kr) + " " + std::to_string(best_m));
+    {
+        std::lock_guard<std::mutex> lk(g_tile_mu);
+        g_tiles[key] = std::make_pair(ka, kr);
+    }
+    if (kz_apply) *kz_apply = ka;
+    if (kz_residual) *kz_residual = kr;
+    if (gmres_m) *gmres_m = best_m;
+    return RAD_OK;
 }
 
 extern "C" int rad_residual(int nx, int ny, int nz, const double *E_n, const double *F_n, const double *T_n,

@@ -80,6 +80,9 @@ def _load():
     L.rad_autotune_batched.restype = I
     L.rad_step_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
     L.rad_step_batched.restype = I
+    L.rad_autotune_step.argtypes = [I, I, I, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, I,
+                                    ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
+    L.rad_autotune_step.restype = I
     L.rad_closure.argtypes = [ct.c_longlong, P, P, I, ct.c_double, P, I, P]
     L.rad_closure.restype = I
     L.rad_plan_launch_shape.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
@@ -101,7 +104,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_residual", "rad_face_speeds",
+EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_autotune_step", "rad_residual",
+            "rad_face_speeds",
             "rad_apply", "rad_exchange", "rad_closure", "rad_batched_workspace_bytes", "rad_plan_batched",
             "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_launch_shape",
             "rad_plan_destroy",
@@ -215,6 +219,28 @@ def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace
     d = st.as_dict()
     d["rc"] = rc
     return d
+
+
+def autotune_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, tune_restart=True, workspace=None,
+                  stream=None):
+    """Autotune rad_step on this data (state left unchanged): returns {"kz_apply", "kz_residual", "gmres_m"}.
+    The z-ranges are cached and used by later rad_step calls; gmres_m is a recommendation."""
+    torch = _torch()
+    nz, ny, nx = E.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
+            _ptr(rho, cd, N, "rho"), _ptr(kappa_P, cd, N, "kappa_P"), _ptr(kappa_R, cd, N, "kappa_R"),
+            _ptr(f, cd, 6 * N, "f")]
+    if workspace is None:
+        workspace = alloc_workspace(int(lib.rad_workspace_bytes(nx, ny, nz, ct.byref(p))), E.device)
+    ka, kr, m = ct.c_int(), ct.c_int(), ct.c_int()
+    _check(lib.rad_autotune_step(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
+                                 _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
+                                 _stream(stream), 1 if tune_restart else 0, ct.byref(ka), ct.byref(kr), ct.byref(m)))
+    return {"kz_apply": ka.value, "kz_residual": kr.value, "gmres_m": m.value}
 
 
 def rad_residual(En, Fn, Tn, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, R=None, stream=None):

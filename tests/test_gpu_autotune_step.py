@@ -1,0 +1,53 @@
+"""Single-grid autotuner: tile z-range per kernel and GMRES restart length timed on the caller's data,
+cached per configuration, state left unchanged; later steps with the tuned tiles match the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_08778_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def rad(torch):
+    from paper_2202_08778_amd import rad as r
+    return r
+
+
+def test_autotune_step_caches_tiles_and_keeps_state(torch, rad, tmp_path, monkeypatch):
+    monkeypatch.setenv("VETTAM_RAD_CACHE_DIR", str(tmp_path))
+    d = W.mixed_depth(shape=(40, 20, 24), seed=17, steps=1)
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    coef = [g(d[k]) for k in ("rho", "kP", "kR", "f")]
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], gmres_m=16, tol=1e-12)
+    out = rad.autotune_step(E, F, T, *coef, d["dt"], d["dx"], d["bc"], p, tune_restart=True)
+    print("autotune", out, flush=True)
+    assert out["kz_apply"] in (8, 16, 32, 40) and out["kz_residual"] in (8, 16, 32, 40)
+    assert out["gmres_m"] in (6, 8, 10, 12, 16)
+    for t, a in zip((E, F, T), (d["E"], d["F"], d["T"])):
+        assert np.array_equal(t.cpu().numpy(), a)
+    lines = open(os.path.join(str(tmp_path), "autotune.txt")).read().splitlines()
+    assert any(l.startswith("single|") and "|24x20x40|" in l for l in lines)
+    # a step with the tuned tiles (read back from the cache) and restart length matches the oracle
+    p.gmres_m = out["gmres_m"]
+    p.tol = 1e-13
+    st = rad.rad_step(E, F, T, *coef, d["dt"], d["dx"], d["bc"], p)
+    P = oracle.Problem(d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"], c=d["c"], aR=d["aR"],
+                       cv=d["cv"])
+    Eo, Fo, To, _ = P.step(d["E"], d["F"], d["T"], tol=1e-14)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    errs = (rel(E.cpu().numpy(), Eo), rel(F.cpu().numpy(), Fo), rel(T.cpu().numpy(), To))
+    print("  step after autotune:", st["krylov_iters"], "Krylov; rel errors", errs, flush=True)
+    assert max(errs) <= 1e-10
