@@ -735,9 +735,8 @@ int run_step(Solver &S)
     Grid &g = S.g;
     const rad_params_t &p = S.p;
     const long long N = g.N, n4 = 4 * N;
-    // gv: the capped grid of the multi-dot (its per-block partial sums are reduced in one
-    // pass); gf: one 4-element group per thread, for the streaming passes with at most one
-    // partial per block (read-and-write streams run ~10% faster at full occupancy)
+    // gf: one 4-element group per thread for the Krylov streaming passes (their per-block
+    // partial sums go through the two-stage reduction); gv: a capped grid for the rest
     const dim3 gc((unsigned)S.L.nblk_cells), gv((unsigned)S.L.nblk_vec), gf((unsigned)S.L.nblk_cells), bl(kBlock);
     const CT *rho = (const CT *)S.rho, *kP = (const CT *)S.kP, *kR = (const CT *)S.kR, *f = (const CT *)S.f;
     double *X = S.at<double>(S.L.X), *X0 = S.at<double>(S.L.X0), *Tc = S.at<double>(S.L.Tc);
@@ -808,8 +807,8 @@ int run_step(Solver &S)
         for (int i0 = 0; i0 < cnt; i0 += 16) {
             const int c = std::min(16, cnt - i0);
             S.timed(kDot, 4 * Nd * kb * (c + 1),
-                    [&] { launch_multidot<KT, 16>(c, gv, S.st, V, stride, i0, w, n4, part); });
-            S.reduce(S.L.nblk_vec, c + 1, c, sm + SM_DOTS + i0, sm + SM_WW);
+                    [&] { launch_multidot<KT, 16>(c, gf, S.st, V, stride, i0, w, n4, part); });
+            S.reduce(S.L.nblk_cells, c + 1, c, sm + SM_DOTS + i0, sm + SM_WW);
         }
     };
 
