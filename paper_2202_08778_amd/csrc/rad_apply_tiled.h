@@ -23,19 +23,19 @@
 namespace vr {
 
 constexpr int kTX = 64;  // tile width (x), one wave per row
-constexpr int kTY = 8;   // tile height (y)
-constexpr int kLX = kTX + 2, kLY = kTY + 2;
-constexpr int kHalo = 2 * kTX + 2 * kTY;
+constexpr int kLX = kTX + 2;
 
 // thread rows of the tile, cells per thread along y and planes in flight
 // (prefetch depth), by arithmetic type: FP64 records take twice the registers
 template <class AT>
 struct TileShape {
     static constexpr int TYT = 4, CPT = 2, DEPTH = 2;
+    static constexpr int TY = TYT * CPT, LY = TY + 2, HALO = 2 * kTX + 2 * TY;
 };
 template <>
 struct TileShape<double> {
     static constexpr int TYT = 8, CPT = 1, DEPTH = 1;
+    static constexpr int TY = TYT * CPT, LY = TY + 2, HALO = 2 * kTX + 2 * TY;
 };
 template <class AT>
 constexpr int tile_threads()
@@ -70,11 +70,13 @@ struct TileGeom {
 // workgroups to fill the chip.  Defaults measured by the autotuner at 256^3 and
 // 512^3: the Krylov apply is fastest at 32 planes, the FP64 residual (one
 // 512-thread workgroup per CU) at 128.
+template <class AT>
 inline TileGeom tile_geom(const Grid &g, int kz_req = 0, int kz_cap = 32, long long min_tiles = 1024)
 {
+    constexpr int TY = TileShape<AT>::TY;
     TileGeom t;
     t.tiles_x = (g.nx + kTX - 1) / kTX;
-    t.tiles_y = (g.ny + kTY - 1) / kTY;
+    t.tiles_y = (g.ny + TY - 1) / TY;
     if (kz_req > 0) {
         t.kz = std::min(kz_req, g.nz);
         t.tiles_z = (g.nz + t.kz - 1) / t.kz;
@@ -125,9 +127,10 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
                                            const AT *__restrict__ x, AT s, AT sF,
-                                           AT (&lds)[2][Rec<PRE>::NL][kLY][kLX], LEX lex, EPI epi)
+                                           AT (&lds)[2][Rec<PRE>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi)
 {
     constexpr int TYT = TileShape<AT>::TYT, CPT = TileShape<AT>::CPT;
+    constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
     constexpr int NC = PRE ? 3 : 0;
     constexpr int IX = Rec<PRE>::IX, IF = Rec<PRE>::IF, IS = Rec<PRE>::IS, IC = Rec<PRE>::IC, NL = Rec<PRE>::NL;
 
@@ -394,7 +397,7 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
                   AT *__restrict__ y, AT xF, AT yF)
 {
-    __shared__ AT lds[2][Rec<PRE>::NL][kLY][kLX];
+    __shared__ AT lds[2][Rec<PRE>::NL][TileShape<AT>::LY][kLX];
     const long long N = g.N;
     const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
     const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;

@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(tile_threads<double>())
                      const double *__restrict__ sR64, const double *__restrict__ Cf64, const double *__restrict__ X,
                      KT *__restrict__ out, DT *__restrict__ dEA, double *partials)
 {
-    __shared__ double lds[2][Rec<true>::NL][kLY][kLX];
+    __shared__ double lds[2][Rec<true>::NL][TileShape<double>::LY][kLX];
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
     const double invc = 1.0 / g.c, nu = g.nu, half = 0.5 * g.nu, aR = g.aR, cdt = g.cdt, cv = g.cv;
@@ -765,7 +765,7 @@ int run_step(Solver &S)
     const int kOrth = sizeof(KT) == 4 ? K_ORTH32 : K_ORTH64;
     const int kUpd = sizeof(KT) == 4 ? K_UPDATEX32 : K_UPDATEX64;
     const double fb = fA ? kb : cb;   // bytes per stored tensor component read by the apply
-    TileGeom tg = tile_geom(g, S.kz_apply), tgr = tile_geom(g, S.kz_res, 128, 256);
+    TileGeom tg = tile_geom<AT>(g, S.kz_apply), tgr = tile_geom<double>(g, S.kz_res, 128, 256);
     auto tiles = [](const TileGeom &t) { return dim3((unsigned)(t.tiles_x * t.tiles_y * t.tiles_z)); };
     const dim3 bt(tile_threads<AT>()), bt64(tile_threads<double>());
     AT *Cf = S.at<AT>(S.L.Cf);
@@ -833,8 +833,8 @@ int run_step(Solver &S)
         float best_a = INFINITY, best_r = INFINITY;
         int rc = RAD_OK;
         for (int kz : *S.tune_kz) {
-            tg = tile_geom(g, kz);
-            tgr = tg;
+            tg = tile_geom<AT>(g, kz);
+            tgr = tile_geom<double>(g, kz);
             float ms_a = 0, ms_r = 0;
             apply(V, sm + SM_S, W);
             if (hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
@@ -1059,7 +1059,7 @@ template <class AT, class CT>
 void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, const void *rho, const void *kR,
                        const void *f, double c, hipStream_t st)
 {
-    const TileGeom tg = tile_geom(g);
+    const TileGeom tg = tile_geom<AT>(g);
     hipLaunchKernelGGL((k_apply_tiled<AT, CT, false>), dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)),
                        dim3(tile_threads<AT>()), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
                        (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
