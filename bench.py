@@ -289,6 +289,11 @@ def main():
                            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if n == 256 else None,
                            "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
                            "avg_launch_us": 1000.0 * e["ms"] / e["launches"], "launches": e["launches"]}
+        # the whole step: every kernel's algorithmic bytes over the step's wall time
+        tot_b = sum(v["bytes"] for v in prof.values())
+        res["step_roofline"] = {"achieved": tot_b / mixed["seconds"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": tot_b / mixed["seconds"] / 1e9 / HBM_PEAK_GBS,
+                                "note": "sum of algorithmic bytes of all kernels / wall time of the timed steps"}
         res["kernel_time_share"] = {k: v["ms"] / (mixed["seconds"] * 1e3) for k, v in
                                     sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
         res["kernel_gbs"] = {k: v["bytes"] / (v["ms"] * 1e-3) / 1e9 for k, v in prof.items() if v["ms"] > 0}
