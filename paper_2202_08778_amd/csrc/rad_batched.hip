@@ -49,7 +49,7 @@ struct BatchArgs {
 
 // per-slot scratch layout for a block of up to nmax^3 cells
 struct SlotLayout {
-    size_t X, X0, Tc, sR, dE, V, W, total;
+    size_t X, X0, Tc, sR, dE, Cs, V, W, total;
 };
 
 __host__ __device__ SlotLayout slot_layout(int nmax, int m, size_t kb)
@@ -67,6 +67,7 @@ __host__ __device__ SlotLayout slot_layout(int nmax, int m, size_t kb)
     L.Tc = take(N * 8);
     L.sR = take(N * kb);
     L.dE = take(N * kb);
+    L.Cs = take(6 * N * kb);  // corrected speeds of the six faces of every interior cell
     L.V = take((size_t)(m + 1) * 4 * N * kb);
     L.W = take(4 * N * kb);
     L.total = o;
@@ -138,6 +139,36 @@ __device__ __forceinline__ void transport_blk(T nu, T tk, LD ld, FL fl, SR sr, T
     div[3] = nu * dF[2];
 }
 
+// transport_blk with the face speeds given: cs(d, side) for face (d, side)
+template <class T, class LD, class FL, class CS>
+__device__ __forceinline__ void transport_blk_pre(T nu, LD ld, FL fl, CS cs, T div[4], T &sumC)
+{
+    const T Ec = ld(0, 0, 0, 0);
+    const T Fc[3] = {ld(1, 0, 0, 0), ld(2, 0, 0, 0), ld(3, 0, 0, 0)};
+    T dE = 0, dF[3] = {0, 0, 0};
+    sumC = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T fcr[3] = {fl(tens_row(d, 0), 0, 0, 0), fl(tens_row(d, 1), 0, 0, 0), fl(tens_row(d, 2), 0, 0, 0)};
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int o = side ? 1 : -1;
+            const int di = d == 0 ? o : 0, dj = d == 1 ? o : 0, dk = d == 2 ? o : 0;
+            const T En = ld(0, di, dj, dk);
+            const T Fn[3] = {ld(1, di, dj, dk), ld(2, di, dj, dk), ld(3, di, dj, dk)};
+            const T fnr[3] = {fl(tens_row(d, 0), di, dj, dk), fl(tens_row(d, 1), di, dj, dk),
+                              fl(tens_row(d, 2), di, dj, dk)};
+            const T C = cs(d, side);
+            sumC += C;
+            face_flux_acc<T>(d, side, C, Ec, Fc, fcr, En, Fn, fnr, dE, dF);
+        }
+    }
+    div[0] = nu * dE;
+    div[1] = nu * dF[0];
+    div[2] = nu * dF[1];
+    div[3] = nu * dF[2];
+}
+
 __device__ __forceinline__ void cell_of(int c, int n, int &i, int &j, int &k)
 {
     const int q = c / n;
@@ -165,7 +196,9 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
     for (;;) {
         if (tid == 0) sh_b = atomicAdd(a.queue, 1);
         __syncthreads();
-        const int qi = sh_b;
+        // the same value in every lane: say so, so that block-derived sizes and
+        // pointers live in scalar registers
+        const int qi = __builtin_amdgcn_readfirstlane(sh_b);
         __syncthreads();
         if (qi >= a.nblocks) break;
         const int bid = a.order[qi];
@@ -185,6 +218,7 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
         SlotLayout L = slot_layout(n, m, sizeof(KT));
         double *X = (double *)(slot + L.X), *X0 = (double *)(slot + L.X0), *Tc = (double *)(slot + L.Tc);
         KT *sR = (KT *)(slot + L.sR), *dEv = (KT *)(slot + L.dE), *V = (KT *)(slot + L.V), *Wv = (KT *)(slot + L.W);
+        KT *Cs = (KT *)(slot + L.Cs);
 
         // ---- setup: state, sR, data check
         double bad[1] = {0};
@@ -203,6 +237,25 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
             X[c] = X0[c] = a.E[p];
             for (int q = 0; q < 3; ++q) X[(1 + q) * Nb + c] = X0[(1 + q) * Nb + c] = a.F[q * AR + p] * invc;
             Tc[c] = a.T[p];
+        }
+        // corrected face speeds, once per block solve: FP64 from the stored coefficients
+        // (ghost neighbours carry their own rho, kappa_R, f), rounded to the Krylov precision
+        for (int c = tid; c < Nb; c += NT) {
+            int i, j, k;
+            cell_of(c, n, i, j, k);
+            auto sr64 = [&](int di, int dj, int dk) -> double {
+                const long long p = B.p(i + di, j + dj, k + dk);
+                return B.cdt * (double)rho[p] * (double)kR[p];
+            };
+            const double sRc = sr64(0, 0, 0);
+            for (int d = 0; d < 3; ++d)
+                for (int side = 0; side < 2; ++side) {
+                    const int o = side ? 1 : -1;
+                    const int di = d == 0 ? o : 0, dj = d == 1 ? o : 0, dk = d == 2 ? o : 0;
+                    const double fc = (double)f[d * AR + B.p(i, j, k)];
+                    const double fn = (double)f[d * AR + B.p(i + di, j + dj, k + dk)];
+                    Cs[(2 * d + side) * Nb + c] = (KT)face_speed<double>(fc, fn, sRc, sr64(di, dj, dk), B.tau_k);
+                }
         }
         wg_sum<NT, 1>(bad, red);
         rad_stats_t st;
@@ -292,13 +345,9 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                 auto fl = [&](int t, int di, int dj, int dk) -> KT {
                     return (KT)f[t * AR + B.p(i + di, j + dj, k + dk)];
                 };
-                auto sr = [&](int di, int dj, int dk) -> KT {
-                    if (inside(di, dj, dk)) return sR[c + di + n * (dj + n * dk)];
-                    const long long p = B.p(i + di, j + dj, k + dk);
-                    return (KT)(B.cdt * (double)rho[p] * (double)kR[p]);
-                };
+                auto cs = [&](int d, int side) -> KT { return Cs[(2 * d + side) * Nb + c]; };
                 KT div[4], sumC;
-                transport_blk<KT>((KT)B.nu, (KT)B.tau_k, ld, fl, sr, div, sumC);
+                transport_blk_pre<KT>((KT)B.nu, ld, fl, cs, div, sumC);
                 const KT sRc = sR[c], dEc = dEv[c], half = KT(0.5) * (KT)B.nu;
                 y[c] = (dEc * ld(0, 0, 0, 0) + div[0]) / (dEc + half * sumC);
                 const KT DF = KT(1) + sRc + half * sumC;

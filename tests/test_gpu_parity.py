@@ -219,3 +219,30 @@ def test_multi_step_mixed_depth_128_properties(torch, rad):
             res = P.scaled_residual(En, Fn, Tn, E.cpu().numpy(), F.cpu().numpy(), T.cpu().numpy())
             _say("  oracle scaled residual", res)
             assert res[3] <= 1.5e-10
+
+
+def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad):
+    """The 256^3 precision workload in the bench's configuration (FP32-exact inputs, m = 8): one mixed
+    step and one FP64 step from the same state agree within 1e-8 per field, and the mixed output meets
+    the oracle's residual definition at the requested tolerance (an implicit step has no per-cell output
+    the oracle could compute alone; its residual is the per-cell check)."""
+    _say("full size 256^3")
+    d = W.mixed_depth_256(n=256, steps=1)
+    P = _oracle_problem(d)
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        cd = torch.float32 if prec == "mixed" else torch.float64
+        E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+        p = _params(rad, d, prec=prec, tol=1e-10, gmres_m=8, coef_dtype=1 if prec == "mixed" else 0)
+        st = rad.rad_step(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd), d["dt"],
+                          d["dx"], d["bc"], p)
+        _say(f"  {prec}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, res {st['scaled_residual']:.2e}")
+        outs[prec] = (E.cpu().numpy(), F.cpu().numpy(), T.cpu().numpy())
+        del E, F, T
+    errs = [_relerr(a, b) for a, b in zip(outs["mixed"], outs["fp64"])]
+    _say("  mixed vs FP64 relerr E F T", ["%.1e" % e for e in errs])
+    assert max(errs) <= MIXED_TOL
+    res = P.scaled_residual(d["E"], d["F"], d["T"], *outs["mixed"])
+    _say("  oracle scaled residual of the mixed step", res)
+    assert res[3] <= 1.5e-10
