@@ -286,7 +286,8 @@ def main():
         e = prof[dom]
         gbs = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if n == 256 else None,
+                           "frac": gbs / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(dom) if (n == 256 and not scale) else None,
                            "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
                            "avg_launch_us": 1000.0 * e["ms"] / e["launches"], "launches": e["launches"]}
         # the whole step: every kernel's algorithmic bytes over the step's wall time

@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -813,10 +814,10 @@ extern "C" size_t rad_batched_workspace_bytes(int nblocks, const rad_block_desc_
     return ws_layout(nblocks, G.nmax, *p).total;
 }
 
-extern "C" int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p, void *workspace,
-                                size_t ws_bytes, void *stream, rad_plan *out)
+namespace {
+int plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p, void *workspace, size_t ws_bytes,
+                 void *stream, rad_plan *out)
 {
-    clear_error();
     if (!out) return fail(RAD_EINVAL, "out is NULL");
     *out = nullptr;
     RAD_TRY(check_params(p));
@@ -856,6 +857,19 @@ extern "C" int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const
     }
     *out = P;
     return RAD_OK;
+}
+}  // namespace
+
+extern "C" int rad_plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *p, void *workspace,
+                                size_t ws_bytes, void *stream, rad_plan *out)
+{
+    clear_error();
+    if (out) *out = nullptr;
+    try {  // the plan object and its descriptor copy live in host memory
+        return plan_batched(nblocks, desc, p, workspace, ws_bytes, stream, out);
+    } catch (const std::bad_alloc &) {
+        return fail(RAD_ENOMEM, "host memory for the plan");
+    }
 }
 
 extern "C" int rad_step_batched(rad_plan P, double *E, double *F, double *T_gas, const void *rho, const void *kappa_P,

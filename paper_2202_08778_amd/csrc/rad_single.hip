@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -1156,19 +1157,24 @@ extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_
     Solver S;
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
                         stream));
-    const int rc = dispatch_step(S);
+    int rc;
+    try {  // small host vectors of the GMRES least-squares problem
+        rc = dispatch_step(S);
+    } catch (const std::bad_alloc &) {
+        rc = fail(RAD_ENOMEM, "host memory");
+    }
     S.stats.status = rc;
     S.stats.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S.stats;
     return rc;
 }
 
-extern "C" int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
-                                 const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
-                                 const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes,
-                                 void *stream, int tune_restart, int *kz_apply, int *kz_residual, int *gmres_m)
+namespace {
+int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho, const void *kappa_P,
+                  const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6], const rad_params_t *p,
+                  void *workspace, size_t ws_bytes, void *stream, int tune_restart, int *kz_apply, int *kz_residual,
+                  int *gmres_m)
 {
-    clear_error();
     Solver S;
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
                         stream));
@@ -1238,6 +1244,21 @@ extern "C" int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, d
     if (kz_residual) *kz_residual = kr;
     if (gmres_m) *gmres_m = best_m;
     return RAD_OK;
+}
+}  // namespace
+
+extern "C" int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                                 const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                                 const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes,
+                                 void *stream, int tune_restart, int *kz_apply, int *kz_residual, int *gmres_m)
+{
+    clear_error();
+    try {  // the host copy of the state is the one large host allocation
+        return autotune_step(nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
+                             stream, tune_restart, kz_apply, kz_residual, gmres_m);
+    } catch (const std::bad_alloc &) {
+        return fail(RAD_ENOMEM, "host memory for the autotuner's copy of the state");
+    }
 }
 
 extern "C" int rad_residual(int nx, int ny, int nz, const double *E_n, const double *F_n, const double *T_n,
