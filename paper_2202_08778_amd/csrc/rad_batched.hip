@@ -13,6 +13,7 @@
 // HIP graph rebuilt only when the plan changes; each step updates the kernel
 // node's arguments and replays it.
 #include "rad_host.h"
+#include "rad_apply_tiled.h"
 
 #include <hip/hip_runtime.h>
 
@@ -178,6 +179,90 @@ __device__ __forceinline__ void cell_of(int c, int n, int &i, int &j, int &k)
     j = q - k * n;
 }
 
+// Plane-marching form of the block apply (FP32, n <= 32), kept out of line so
+// that it has its own register allocation: the thread owns plane positions
+// q = tid, tid + NT; planes stream through three LDS slots (plane p in slot
+// p % 3), the next-but-one plane is fetched into registers while the current
+// one is computed, so each x and f value is read from memory once per apply and
+// the lateral and vertical neighbours come from LDS.  Neighbours outside the
+// block carry a zero correction (the ghosts are fixed data), so their tensor
+// multiplies zero.  spl: 3 x 10 x 1024 floats of LDS.
+template <class CT, int NT>
+__device__ __noinline__ void apply_planes(Blk B, int n, int Nb, long long AR, const CT *__restrict__ f,
+                                          const float *__restrict__ x, float s, const float *__restrict__ Cs,
+                                          const float *__restrict__ sR, const float *__restrict__ dEv,
+                                          float *__restrict__ y, float *spl_)
+{
+    using KT = float;
+    auto spl = reinterpret_cast<float(*)[10][32 * 32]>(spl_);
+    constexpr int QP = (32 * 32 + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int n2 = n * n;
+    const KT nu = (KT)B.nu, half = KT(0.5) * (KT)B.nu;
+    KT R[QP][10];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int u = 0; u < QP; ++u) {
+            const int q = tid + u * NT;
+            if (q < n2) {
+                const int c = q + n2 * k;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) R[u][t] = s * x[t * Nb + c];
+                const long long p = B.p(q % n, q / n, k);
+#pragma unroll
+                for (int t = 0; t < 6; ++t) R[u][4 + t] = (KT)f[t * AR + p];
+            }
+        }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int u = 0; u < QP; ++u) {
+            const int q = tid + u * NT;
+            if (q < n2)
+#pragma unroll
+                for (int t = 0; t < 10; ++t) spl[slot][t][q] = R[u][t];
+        }
+    };
+    fetch(0);
+    store(0);
+    if (n > 1) {
+        fetch(1);
+        store(1);
+    }
+    lds_barrier();
+    for (int k = 0; k < n; ++k) {
+        if (k + 2 < n) fetch(k + 2);
+        const int a = k % 3, lo = (k + 2) % 3, hi = (k + 1) % 3;
+#pragma unroll 1
+        for (int u = 0; u < QP; ++u) {
+            const int q = tid + u * NT;
+            if (q >= n2) continue;
+            const int i = q % n, j = q / n, c = q + n2 * k;
+            auto ld = [&](int t, int di, int dj, int dk) -> KT {
+                if (dk) return (unsigned)(k + dk) < (unsigned)n ? spl[dk > 0 ? hi : lo][t][q] : KT(0);
+                if ((unsigned)(i + di) >= (unsigned)n || (unsigned)(j + dj) >= (unsigned)n) return KT(0);
+                return spl[a][t][q + di + n * dj];
+            };
+            auto fl = [&](int t, int di, int dj, int dk) -> KT {
+                if (dk) return (unsigned)(k + dk) < (unsigned)n ? spl[dk > 0 ? hi : lo][4 + t][q] : spl[a][4 + t][q];
+                if ((unsigned)(i + di) >= (unsigned)n || (unsigned)(j + dj) >= (unsigned)n) return spl[a][4 + t][q];
+                return spl[a][4 + t][q + di + n * dj];
+            };
+            auto cs = [&](int d, int side) -> KT { return Cs[(2 * d + side) * Nb + c]; };
+            KT div[4], sumC;
+            transport_blk_pre<KT>(nu, ld, fl, cs, div, sumC);
+            const KT sRc = sR[c], dEc = dEv[c];
+            y[c] = (dEc * ld(0, 0, 0, 0) + div[0]) / (dEc + half * sumC);
+            const KT DF = KT(1) + sRc + half * sumC;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) y[(1 + t) * Nb + c] = ((KT(1) + sRc) * ld(1 + t, 0, 0, 0) + div[1 + t]) / DF;
+        }
+        lds_barrier();
+        if (k + 2 < n) store((k + 2) % 3);
+        lds_barrier();
+    }
+}
+
 template <class CT, class KT, int NT>
 __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
 {
@@ -187,6 +272,9 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
     __shared__ double sh_dots[kMaxM + DC], sh_s[kMaxM + 2], sh_a[kMaxM + 1], sh_y[kMaxM];
     __shared__ double sh_H[(kMaxM + 1) * kMaxM], sh_cs[kMaxM], sh_sn[kMaxM], sh_g[kMaxM + 1];
     __shared__ int sh_flag, sh_b;
+    // planes k-1, k, k+1 of the marching apply (FP32 blocks up to 32^3): x (4) and f (6)
+    constexpr int PL = sizeof(KT) == 4 ? 32 * 32 : 1;
+    __shared__ KT spl[3][10][PL];
 
     const CT *rho = (const CT *)a.rho, *kP = (const CT *)a.kP, *kR = (const CT *)a.kR, *f = (const CT *)a.f;
     const long long AR = a.arena;
@@ -333,6 +421,12 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
 
         // w = D^-1 A (s x): linear operator, ghost part of the correction is zero
         auto apply = [&](const KT *x, KT s, KT *y) {
+            if constexpr (sizeof(KT) == 4) {
+                if (n <= 32) {
+                    apply_planes<CT, NT>(B, n, Nb, AR, f, x, s, Cs, sR, dEv, y, &spl[0][0][0]);
+                    return;
+                }
+            }
             for (int c = tid; c < Nb; c += NT) {
                 int i, j, k;
                 cell_of(c, n, i, j, k);
