@@ -51,7 +51,7 @@ struct BatchArgs {
 
 // per-slot scratch layout for a block of up to nmax^3 cells
 struct SlotLayout {
-    size_t X, X0, Tc, sR, dE, Cs, V, W, total;
+    size_t X, X0, Tc, sR, dE, Cs, Cs64, V, W, total;
 };
 
 __host__ __device__ SlotLayout slot_layout(int nmax, int m, size_t kb)
@@ -70,6 +70,7 @@ __host__ __device__ SlotLayout slot_layout(int nmax, int m, size_t kb)
     L.sR = take(N * kb);
     L.dE = take(N * kb);
     L.Cs = take(6 * N * kb);  // corrected speeds of the six faces of every interior cell
+    L.Cs64 = take(kb == 8 ? 0 : 6 * N * 8);  // the same in FP64 for the residual (FP32 Krylov only)
     L.V = take((size_t)(m + 1) * 4 * N * kb);
     L.W = take(4 * N * kb);
     L.total = o;
@@ -109,39 +110,9 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double *red)
     __syncthreads();
 }
 
-// Transport part at interior cell (i,j,k) of a block; neighbours outside the
-// interior are the first ghost layer.  Loaders take offsets (di, dj, dk).
-template <class T, class LD, class FL, class SR>
-__device__ __forceinline__ void transport_blk(T nu, T tk, LD ld, FL fl, SR sr, T div[4], T &sumC)
-{
-    const T Ec = ld(0, 0, 0, 0);
-    const T Fc[3] = {ld(1, 0, 0, 0), ld(2, 0, 0, 0), ld(3, 0, 0, 0)};
-    const T sRc = sr(0, 0, 0);
-    T dE = 0, dF[3] = {0, 0, 0};
-    sumC = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T fcr[3] = {fl(tens_row(d, 0), 0, 0, 0), fl(tens_row(d, 1), 0, 0, 0), fl(tens_row(d, 2), 0, 0, 0)};
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int o = side ? 1 : -1;
-            const int di = d == 0 ? o : 0, dj = d == 1 ? o : 0, dk = d == 2 ? o : 0;
-            const T En = ld(0, di, dj, dk);
-            const T Fn[3] = {ld(1, di, dj, dk), ld(2, di, dj, dk), ld(3, di, dj, dk)};
-            const T fnr[3] = {fl(tens_row(d, 0), di, dj, dk), fl(tens_row(d, 1), di, dj, dk),
-                              fl(tens_row(d, 2), di, dj, dk)};
-            const T C = face_speed<T>(fcr[d], fnr[d], sRc, sr(di, dj, dk), tk);
-            sumC += C;
-            face_flux_acc<T>(d, side, C, Ec, Fc, fcr, En, Fn, fnr, dE, dF);
-        }
-    }
-    div[0] = nu * dE;
-    div[1] = nu * dF[0];
-    div[2] = nu * dF[1];
-    div[3] = nu * dF[2];
-}
-
-// transport_blk with the face speeds given: cs(d, side) for face (d, side)
+// Transport part at interior cell (i,j,k) of a block, with the corrected face
+// speeds given (cs(d, side) for face (d, side)); neighbours outside the interior
+// are the first ghost layer.  Loaders take offsets (di, dj, dk).
 template <class T, class LD, class FL, class CS>
 __device__ __forceinline__ void transport_blk_pre(T nu, LD ld, FL fl, CS cs, T div[4], T &sumC)
 {
@@ -308,6 +279,7 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
         double *X = (double *)(slot + L.X), *X0 = (double *)(slot + L.X0), *Tc = (double *)(slot + L.Tc);
         KT *sR = (KT *)(slot + L.sR), *dEv = (KT *)(slot + L.dE), *V = (KT *)(slot + L.V), *Wv = (KT *)(slot + L.W);
         KT *Cs = (KT *)(slot + L.Cs);
+        double *Cs64 = sizeof(KT) == 8 ? (double *)Cs : (double *)(slot + L.Cs64);
 
         // ---- setup: state, sR, data check
         double bad[1] = {0};
@@ -343,7 +315,9 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                     const int di = d == 0 ? o : 0, dj = d == 1 ? o : 0, dk = d == 2 ? o : 0;
                     const double fc = (double)f[d * AR + B.p(i, j, k)];
                     const double fn = (double)f[d * AR + B.p(i + di, j + dj, k + dk)];
-                    Cs[(2 * d + side) * Nb + c] = (KT)face_speed<double>(fc, fn, sRc, sr64(di, dj, dk), B.tau_k);
+                    const double C = face_speed<double>(fc, fn, sRc, sr64(di, dj, dk), B.tau_k);
+                    Cs[(2 * d + side) * Nb + c] = (KT)C;
+                    Cs64[(2 * d + side) * Nb + c] = C;
                 }
         }
         wg_sum<NT, 1>(bad, red);
@@ -372,15 +346,13 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                 auto fl = [&](int t, int di, int dj, int dk) -> double {
                     return (double)f[t * AR + B.p(i + di, j + dj, k + dk)];
                 };
-                auto sr = [&](int di, int dj, int dk) -> double {
-                    const long long p = B.p(i + di, j + dj, k + dk);
-                    return B.cdt * (double)rho[p] * (double)kR[p];
-                };
+                auto cs = [&](int d, int side) -> double { return Cs64[(2 * d + side) * Nb + c]; };
                 double div[4], sumC;
-                transport_blk<double>(B.nu, B.tau_k, ld, fl, sr, div, sumC);
+                transport_blk_pre<double>(B.nu, ld, fl, cs, div, sumC);
                 const long long p = B.p(i, j, k);
                 const double r_ = (double)rho[p];
-                const double sP = B.cdt * r_ * (double)kP[p], sRc = sr(0, 0, 0), alpha = r_ * a.cv, aR = a.aR;
+                const double sP = B.cdt * r_ * (double)kP[p], sRc = B.cdt * r_ * (double)kR[p], alpha = r_ * a.cv,
+                             aR = a.aR;
                 const double Ts = Tc[c], T3 = Ts * Ts * Ts, T4 = T3 * Ts;
                 double dE, bE;
                 if (a.mode == 0) {
