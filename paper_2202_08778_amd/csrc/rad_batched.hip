@@ -482,12 +482,13 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                         for (int e = 4 * tid; e < n4; e += 4 * NT) {
                             double we[4];
                             Quad<KT>::load(Wv + e, we);
-                            double vv[DC][4];
+                            KT vv[DC][4];
 #pragma unroll
-                            for (int q = 0; q < DC; ++q) Quad<KT>::load(vq[q] + e, vv[q]);
+                            for (int q = 0; q < DC; ++q) Quad<KT>::load_raw(vq[q] + e, vv[q]);
 #pragma unroll
                             for (int q = 0; q < DC; ++q)
-                                acc[q] += vv[q][0] * we[0] + vv[q][1] * we[1] + vv[q][2] * we[2] + vv[q][3] * we[3];
+                                acc[q] += (double)vv[q][0] * we[0] + (double)vv[q][1] * we[1] + (double)vv[q][2] * we[2] +
+                                          (double)vv[q][3] * we[3];
                             acc[DC] += we[0] * we[0] + we[1] * we[1] + we[2] * we[2] + we[3] * we[3];
                         }
                         wg_sum<NT, DC + 1>(acc, red);
@@ -500,24 +501,21 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                     __syncthreads();
                     // v_{j+1} = w - sum_i s_i^2 d_i V_i
                     double nn[1] = {0};
+                    // basis vectors in chunks of DC with indices past j clamped to j and a zero
+                    // coefficient, so every load of a chunk is issued at once
                     for (int e = 4 * tid; e < n4; e += 4 * NT) {
                         double val[4];
                         Quad<KT>::load(Wv + e, val);
-                        int i = 0;
-                        for (; i + 4 <= j + 1; i += 4) {
-                            double a4[4][4];
+                        for (int i0 = 0; i0 <= j; i0 += DC) {
+                            KT a8[DC][4];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) Quad<KT>::load(V + (long long)(i + u) * n4 + e, a4[u]);
+                            for (int u = 0; u < DC; ++u) Quad<KT>::load_raw(V + (long long)min(i0 + u, j) * n4 + e, a8[u]);
 #pragma unroll
-                            for (int u = 0; u < 4; ++u)
+                            for (int u = 0; u < DC; ++u) {
+                                const double cu = i0 + u <= j ? sh_a[i0 + u] : 0.0;
 #pragma unroll
-                                for (int k = 0; k < 4; ++k) val[k] -= sh_a[i + u] * a4[u][k];
-                        }
-                        for (; i <= j; ++i) {
-                            double a1[4];
-                            Quad<KT>::load(V + (long long)i * n4 + e, a1);
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) val[k] -= sh_a[i] * a1[k];
+                                for (int k = 0; k < 4; ++k) val[k] -= cu * (double)a8[u][k];
+                            }
                         }
                         double r[4];
                         Quad<KT>::store(vn + e, val, r);

@@ -195,6 +195,11 @@ template <class KT>
 struct Quad;
 template <>
 struct Quad<float> {
+    static __device__ __forceinline__ void load_raw(const float *p, float (&v)[4])
+    {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
     static __device__ __forceinline__ void load(const float *p, double (&v)[4])
     {
         const float4 q = *reinterpret_cast<const float4 *>(p);
@@ -210,6 +215,7 @@ struct Quad<float> {
 };
 template <>
 struct Quad<double> {
+    static __device__ __forceinline__ void load_raw(const double *p, double (&v)[4]) { load(p, v); }
     static __device__ __forceinline__ void load(const double *p, double (&v)[4])
     {
         const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
