@@ -1,0 +1,353 @@
+"""Two-level composite grid: plain FP64 oracle of the implicit radiation step on a
+coarse grid with one box refined by a factor 2.
+
+TEST INFRASTRUCTURE ONLY: only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module.  It shares no code with
+the GPU library; it reuses only the uniform oracle's per-cell quartic.
+
+What it computes (Sec. 2.3.3, eq. wavespeedtau and eq. interface_flux; App. A2):
+the backward-Euler system of the uniform oracle, written on the composite grid
+made of the uncovered cells of a coarse grid (width H) and the cells of the
+refined box (width H/2).
+
+* Every face carries one HLLE flux of the piecewise-constant states on its two
+  sides.  Between two cells of one level the optical depth of the wave-speed
+  correction is the mean of the cells' values.  Where the level changes it is
+  the upstream cell's: tau_L for the right-going speed C^R, tau_R for the
+  left-going speed C^L, each cell's tau taken with its own width.  With
+  C^L != C^R the flux is the general HLL form
+      Phi = (C^R Phi(U_L) + C^L Phi(U_R) - C^L C^R (U_R - U_L)) / (C^L + C^R).
+* A fine cell's neighbour across a level jump is the coarse cell itself
+  (piecewise-constant ghost, the first-order reading).
+* A coarse face covered by fine cells carries, for the coarse cell, the mean of
+  the four fine face fluxes (each fine face has a quarter of its area): the
+  fine-face fluxes enter the coarse cell with weight c dt / (4 H) and the fine
+  cells with c dt / h_f, so the scheme conserves E and F by construction.
+* Covered coarse cells take no part in the transport: their rows are the
+  isolated-cell equations, and on output they hold the mean of their eight
+  children (restriction).  Boundary faces of the domain are periodic or
+  zero-gradient outflow, as on the uniform grid.
+
+Readings (where the paper is silent): f at a level-jump face is the larger of the
+two cells' f_dd, as at every other face; the restriction of T is the plain mean.
+
+The nonlinear system is solved by the linearised outer iteration (Newton on the
+T-eliminated system, or the paper's lagged Picard form) with each linear system
+solved directly (SuperLU), then the per-cell quartic of eq. PicardTemp.
+
+Array conventions: per level, a scalar field has shape (nz, ny, nx) (x fastest),
+F has shape (3, ...), f has shape (6, ...) in the order xx, yy, zz, xy, xz, yz.
+The fine level's extents are 2 (hi - lo) of the refined box [lo, hi) (coarse
+cells, per axis x, y, z).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import exchange_T
+
+_TENS = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (1, 0): 3, (0, 2): 4, (2, 0): 4, (1, 2): 5, (2, 1): 5}
+
+
+def _bc_list(bc):
+    if isinstance(bc, str):
+        bc = [bc] * 6
+    bc = list(bc)
+    if len(bc) != 6 or any(b not in ("periodic", "outflow") for b in bc):
+        raise ValueError("bc: 'periodic' or 'outflow' per face")
+    for a in range(3):
+        if (bc[2 * a] == "periodic") != (bc[2 * a + 1] == "periodic"):
+            raise ValueError("periodic faces must come in pairs")
+    return bc
+
+
+def correction(tau):
+    """sqrt((1 - exp(-tau)) / tau) with its limits 1 at tau = 0 and 0 at tau = inf."""
+    tau = np.asarray(tau, dtype=np.float64)
+    out = np.ones_like(tau)
+    pos = tau > 0
+    fin = pos & np.isfinite(tau)
+    out[pos & ~np.isfinite(tau)] = 0.0
+    out[fin] = np.sqrt(-np.expm1(-tau[fin]) / tau[fin])
+    return out
+
+
+def cell_tau(sigma, h, fdd):
+    """(10 h sigma)^2 / (2 f_dd); 0 without opacity, +inf for f_dd = 0 with opacity (eq. taucorrect)."""
+    sigma, h, fdd = np.broadcast_arrays(np.asarray(sigma, np.float64), np.asarray(h, np.float64),
+                                        np.asarray(fdd, np.float64))
+    tau = np.zeros(sigma.shape)
+    has = sigma != 0
+    zero_f = has & (fdd == 0)
+    ok = has & ~zero_f
+    tau[zero_f] = np.inf
+    tau[ok] = (10.0 * h[ok] * sigma[ok]) ** 2 / (2.0 * fdd[ok])
+    return tau
+
+
+class TwoLevel:
+    """Composite grid, constants and coefficient fields of one implicit step."""
+
+    def __init__(self, coarse_shape, lo, hi, rho, kP, kR, f, dt, dx, bc="periodic", c=1.0, aR=1.0, cv=1.0,
+                 jump_tau="upstream"):
+        """coarse_shape = (nx, ny, nz); [lo, hi) the refined box in coarse cells (x, y, z).
+        rho, kP, kR, f: (coarse, fine) pairs of arrays.  dx: coarse cell width.
+        jump_tau: 'upstream' (eq. wavespeedtau) or 'average' (the variant App. A2 rejects)."""
+        nx, ny, nz = (int(v) for v in coarse_shape)
+        self.nc = (nx, ny, nz)
+        self.lo, self.hi = tuple(int(v) for v in lo), tuple(int(v) for v in hi)
+        self.span = []
+        for d in range(3):
+            n, a, b = self.nc[d], self.lo[d], self.hi[d]
+            if a == 0 and b == n:
+                self.span.append(True)
+            elif 1 <= a < b <= n - 1:
+                self.span.append(False)
+            else:
+                raise ValueError("the refined box must span an axis or stay one coarse cell inside it")
+        self.nf = tuple(2 * (self.hi[d] - self.lo[d]) for d in range(3))
+        self.Nc, self.Nf = nx * ny * nz, int(np.prod(self.nf))
+        self.N = self.Nc + self.Nf
+        self.bc = _bc_list(bc)
+        self.c, self.aR, self.cv, self.dt, self.dx = float(c), float(aR), float(cv), float(dt), float(dx)
+        self.hl = (self.dx, 0.5 * self.dx)
+        self.nul = (self.c * self.dt / self.hl[0], self.c * self.dt / self.hl[1])
+        if jump_tau not in ("upstream", "average"):
+            raise ValueError("jump_tau")
+        self.jump_tau = jump_tau
+
+        cat = lambda pair, k: np.concatenate([np.asarray(pair[0], np.float64).reshape(k, -1),
+                                              np.asarray(pair[1], np.float64).reshape(k, -1)], axis=1)
+        self.rho = cat(rho, 1)[0]
+        self.kP = cat(kP, 1)[0]
+        self.kR = cat(kR, 1)[0]
+        self.f = cat(f, 6)
+        self.level = np.r_[np.zeros(self.Nc, np.int64), np.ones(self.Nf, np.int64)]
+        self.h_cell = np.where(self.level == 0, self.hl[0], self.hl[1])
+        self.nu_cell = np.where(self.level == 0, self.nul[0], self.nul[1])
+        K, J, I = np.indices((nz, ny, nx)).reshape(3, -1)
+        self.covered = np.zeros(self.N, bool)
+        self.covered[:self.Nc] = ((I >= self.lo[0]) & (I < self.hi[0]) & (J >= self.lo[1]) & (J < self.hi[1]) &
+                                  (K >= self.lo[2]) & (K < self.hi[2]))
+        self.sP = self.c * self.dt * self.rho * self.kP
+        self.sR = self.c * self.dt * self.rho * self.kR
+        self.alpha = self.rho * self.cv
+        self._faces()
+
+    # ------------------------------------------------------------- geometry
+    def cid(self, i, j, k):
+        nx, ny, _ = self.nc
+        return i + nx * (j + ny * k)
+
+    def fid(self, i, j, k):
+        a, b, _ = self.nf
+        return self.Nc + i + a * (j + b * k)
+
+    def _faces(self):
+        """Faces as arrays: left cell, right cell, axis, weights into the left and right
+        divergences, and whether the level changes; plus zero-gradient boundary faces
+        (cell, axis, side sign, weight)."""
+        L, R, D, WL, WR, JMP = [], [], [], [], [], []
+        BA, BD, BS, BW = [], [], [], []
+        for lev in (0, 1):
+            n = self.nc if lev == 0 else self.nf
+            ids = self.cid if lev == 0 else self.fid
+            nu = self.nul[lev]
+            K, J, I = np.indices((n[2], n[1], n[0])).reshape(3, -1)
+            P = [I, J, K]
+            for d in range(3):
+                q = P[d]
+                domain_axis = lev == 0 or self.span[d]
+                # same-level pairs (a, a + e_d), wrapping on periodic axes of the domain
+                inner = q + 1 < n[d]
+                nb = [p.copy() for p in P]
+                nb[d] = np.where(inner, q + 1, 0)
+                pair = inner | (domain_axis & (self.bc[2 * d] == "periodic") & (q + 1 == n[d]))
+                a = ids(I[pair], J[pair], K[pair])
+                b = ids(nb[0][pair], nb[1][pair], nb[2][pair])
+                if lev == 0:
+                    keep = ~self.covered[a] & ~self.covered[b]
+                    a, b = a[keep], b[keep]
+                L.append(a); R.append(b); D.append(np.full(a.size, d)); WL.append(np.full(a.size, nu))
+                WR.append(np.full(a.size, nu)); JMP.append(np.zeros(a.size, bool))
+                if domain_axis and self.bc[2 * d] == "outflow":
+                    for side, at in ((0, q == 0), (1, q == n[d] - 1)):
+                        cells = ids(I[at], J[at], K[at])
+                        if lev == 0:
+                            cells = cells[~self.covered[cells]]
+                        BA.append(cells); BD.append(np.full(cells.size, d)); BS.append(np.full(cells.size, 2 * side - 1.0))
+                        BW.append(np.full(cells.size, nu))
+                if lev == 1 and not self.span[d]:
+                    # level jumps: the fine cell's neighbour is the coarse cell next to its parent
+                    for side, at in ((0, q == 0), (1, q == n[d] - 1)):
+                        par = [self.lo[e] + P[e][at] // 2 for e in range(3)]
+                        par[d] = np.full(par[d].shape, self.lo[d] - 1 if side == 0 else self.hi[d])
+                        fine = ids(I[at], J[at], K[at])
+                        coarse = self.cid(*par)
+                        lft, rgt = (coarse, fine) if side == 0 else (fine, coarse)
+                        wc, wf = self.nul[0] / 4.0, self.nul[1]
+                        L.append(lft); R.append(rgt); D.append(np.full(fine.size, d))
+                        WL.append(np.full(fine.size, wc if side == 0 else wf))
+                        WR.append(np.full(fine.size, wf if side == 0 else wc))
+                        JMP.append(np.ones(fine.size, bool))
+        cc = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt)
+        self.fL, self.fR, self.fD = cc(L, np.int64), cc(R, np.int64), cc(D, np.int64)
+        self.fWL, self.fWR, self.fJ = cc(WL, np.float64), cc(WR, np.float64), cc(JMP, bool)
+        self.bA, self.bD, self.bS, self.bW = cc(BA, np.int64), cc(BD, np.int64), cc(BS, np.float64), cc(BW, np.float64)
+
+    def face_speeds(self):
+        """(C^L, C^R) of every face, divided by c."""
+        L, R, D = self.fL, self.fR, self.fD
+        sig = self.rho * self.kR
+        fL, fR = self.f[D, L], self.f[D, R]
+        tL = cell_tau(sig[L], self.h_cell[L], fL)
+        tR = cell_tau(sig[R], self.h_cell[R], fR)
+        root = np.sqrt(np.maximum(fL, fR))
+        mean = correction(0.5 * (tL + tR))
+        CL = root * mean
+        CR = root * mean
+        if self.jump_tau == "upstream":
+            j = self.fJ
+            CR = np.where(j, root * correction(tL), CR)   # right-going wave: tau of the left (upstream) cell
+            CL = np.where(j, root * correction(tR), CL)   # left-going wave: tau of the right cell
+        return CL, CR
+
+    # ------------------------------------------------------------- operator
+    def matrix(self, dE):
+        """Sparse A of the linear system at E diagonal dE, unknowns u[q N + cell] with
+        q = 0: E, 1..3: F/c.  Rows: dE E + div PhiE, (1 + sR) F/c + div PhiF/c."""
+        N = self.N
+        rows, cols, vals = [], [], []
+
+        def put(r, c_, v):
+            rows.append(r); cols.append(c_); vals.append(v)
+
+        ar = np.arange(N)
+        put(ar, ar, np.asarray(dE, np.float64))
+        for q in range(1, 4):
+            put(q * N + ar, q * N + ar, 1.0 + self.sR)
+        CL, CR = self.face_speeds()
+        S = CL + CR
+        safe = np.where(S > 0, S, 1.0)
+        aL = np.where(S > 0, CR / safe, 0.5)   # weight of Phi(U_L)
+        aR = np.where(S > 0, CL / safe, 0.5)   # weight of Phi(U_R)
+        g = np.where(S > 0, CL * CR / safe, 0.0)
+        L, R, D = self.fL, self.fR, self.fD
+        for cell, w in ((L, self.fWL), (R, -self.fWR)):
+            # E row: Phi^E = aL Ft_d,L + aR Ft_d,R - g (E_R - E_L)
+            put(cell, (1 + D) * N + L, w * aL)
+            put(cell, (1 + D) * N + R, w * aR)
+            put(cell, L, w * g)
+            put(cell, R, -w * g)
+            for j in range(3):
+                t = np.array([_TENS[(int(d), j)] for d in range(3)])[D]
+                # F_j row: Phi^Fj = aL f_dj,L E_L + aR f_dj,R E_R - g (Ft_j,R - Ft_j,L)
+                put((1 + j) * N + cell, L, w * aL * self.f[t, L])
+                put((1 + j) * N + cell, R, w * aR * self.f[t, R])
+                put((1 + j) * N + cell, (1 + j) * N + L, w * g)
+                put((1 + j) * N + cell, (1 + j) * N + R, -w * g)
+        # zero-gradient boundary faces: the ghost is the cell itself, the flux its physical flux
+        A_, Bd, sw = self.bA, self.bD, self.bS * self.bW
+        put(A_, (1 + Bd) * N + A_, sw)
+        for j in range(3):
+            t = np.array([_TENS[(int(d), j)] for d in range(3)])[Bd]
+            put((1 + j) * N + A_, A_, sw * self.f[t, A_])
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(4 * N, 4 * N))
+
+    def apply(self, x, dE):
+        """y = A x for x of shape (4, N) (E, F/c per composite cell)."""
+        return (self.matrix(dE) @ np.asarray(x, np.float64).reshape(-1)).reshape(4, self.N)
+
+    # ------------------------------------------------------------- state I/O
+    def pack(self, coarse, fine, k=1):
+        return np.concatenate([np.asarray(coarse, np.float64).reshape(k, -1),
+                               np.asarray(fine, np.float64).reshape(k, -1)], axis=1)
+
+    def unpack(self, a, k=1):
+        nx, ny, nz = self.nc
+        a = np.asarray(a).reshape(k, self.N)
+        cs = (k, nz, ny, nx) if k > 1 else (nz, ny, nx)
+        fs = (k,) + self.nf[::-1] if k > 1 else self.nf[::-1]
+        return a[:, :self.Nc].reshape(cs).copy(), a[:, self.Nc:].reshape(fs).copy()
+
+    def restrict(self, a):
+        """Covered coarse cells of a (k, N) composite array := mean of their eight children."""
+        nx, ny, nz = self.nc
+        lo, hi = self.lo, self.hi
+        for q in range(a.shape[0]):
+            fine = a[q, self.Nc:].reshape(self.nf[::-1])
+            m = fine.reshape(self.nf[2] // 2, 2, self.nf[1] // 2, 2, self.nf[0] // 2, 2).mean(axis=(1, 3, 5))
+            c = a[q, :self.Nc].reshape(nz, ny, nx)
+            c[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = m
+        return a
+
+    def leaf_volume(self):
+        """Cell volumes of the composite (0 for covered coarse cells)."""
+        v = self.h_cell ** 3
+        v[self.covered] = 0.0
+        return v
+
+    # ------------------------------------------------------------- nonlinear step
+    def residual(self, En, Ftn, Tn, E, Ft, T):
+        """Nonlinear residual (R_E, R_F/c x3, R_T) of the backward-Euler system at (E, F/c, T)."""
+        A = self.matrix(1.0 + self.sP)
+        u = np.concatenate([E, Ft.reshape(-1)])
+        Au = (A @ u).reshape(4, self.N)
+        R = np.empty((5, self.N))
+        R[0] = Au[0] - (En + self.sP * self.aR * T ** 4)
+        R[1:4] = Au[1:4] - Ftn
+        R[4] = self.alpha * (T - Tn) + self.sP * (self.aR * T ** 4 - E)
+        return R, A.diagonal().reshape(4, self.N)
+
+    def scaled_residual(self, En, Ftn, Tn, E, Ft, T):
+        R, W = self.residual(En, Ftn, Tn, E, Ft, T)
+        nE, nF, nT = np.linalg.norm(E), np.linalg.norm(Ft), np.linalg.norm(T)
+        rE = np.linalg.norm(R[0] / W[0]) / max(nE, 1e-300)
+        rF = np.linalg.norm(R[1:4] / W[1:4]) / max(nF + nE, 1e-300)
+        WT = self.alpha + 4.0 * self.sP * self.aR * T ** 3
+        WT = np.where(WT > 0, WT, 1.0)
+        rT = np.linalg.norm(R[4] / WT) / max(nT, 1e-300)
+        return max(rE, rF, rT)
+
+    def step(self, E, F, T, tol=1e-13, mode="linearised", max_picard=100):
+        """One implicit step.  E, F, T: (coarse, fine) pairs.  Returns ((Ec, Ef), (Fc, Ff), (Tc, Tf), stats)."""
+        En = self.pack(*E)[0]
+        Ftn = self.pack(*F, k=3) / self.c
+        Tn = self.pack(*T)[0]
+        N = self.N
+        Ts = Tn.copy()
+        E_, Ft_, T_ = En.copy(), Ftn.copy(), Tn.copy()
+        prev, res, it, conv = np.inf, np.inf, 0, 0
+        for it in range(1, max_picard + 1):
+            T3 = Ts ** 3
+            if mode == "lagged":
+                dE = 1.0 + self.sP
+                bE = En + self.sP * self.aR * Ts ** 4
+            else:
+                den = self.alpha + 4.0 * self.sP * self.aR * T3
+                eta = np.where(den > 0, 4.0 * self.sP * self.aR * T3 / np.where(den > 0, den, 1.0), 0.0)
+                dE = 1.0 + self.sP * (1.0 - eta)
+                bE = En + eta * self.alpha * Tn - 3.0 * (1.0 - eta) * self.sP * self.aR * Ts ** 4
+            A = self.matrix(dE).tocsc()
+            u = spla.spsolve(A, np.concatenate([bE, Ftn.reshape(-1)]))
+            E_, Ft_ = u[:N].copy(), u[N:].reshape(3, N).copy()
+            T_ = np.array([exchange_T(self.alpha[i], Tn[i], self.sP[i], self.aR, E_[i])[0] for i in range(N)])
+            Ts = T_
+            res = self.scaled_residual(En, Ftn, Tn, E_, Ft_, T_)
+            if res <= tol:
+                conv = 1
+                break
+            if res >= prev and prev < 1e-10:
+                conv = 2
+                break
+            prev = min(prev, res)
+        out = np.vstack([E_[None], Ft_ * self.c, T_[None]])
+        self.restrict(out)
+        Ec, Ef = self.unpack(out[0])
+        Fc, Ff = self.unpack(out[1:4], k=3)
+        Tc, Tf = self.unpack(out[4])
+        if conv == 0:
+            raise RuntimeError(f"composite oracle did not converge: residual {res:.3e} after {it} iterations")
+        return (Ec, Ef), (Fc, Ff), (Tc, Tf), {"picard_iters": it, "scaled_residual": res, "converged": conv}

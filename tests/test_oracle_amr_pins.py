@@ -1,0 +1,307 @@
+"""Pins of the two-level composite oracle (oracle/amr.py) against what the paper and the
+mathematics fix, independent of its own arithmetic:
+
+* conservation: on a periodic composite grid the scheme conserves sum vol (E + alpha T)
+  and sum vol ((1 + sR) F^{n+1} - F^n) = 0 to round-off (Sec. 2.3.3, eq. interface_flux:
+  conservation by construction);
+* streaming: with no opacity and f = diag(1, 0, 0), fields that vary along x only reduce
+  the scheme to implicit upwinding of E +- F/c on a line of cells of two widths, whose
+  cyclic recurrence is solved here in closed form (pins the HLL weights at level jumps,
+  the per-level factor c dt / h and the mean over the four fine faces);
+* uniform state: a uniform medium and state are preserved across level jumps, each cell
+  following the one-cell closed form (root by bisection, not the oracle's Newton);
+* a refined box covering the whole domain reduces to the uniform oracle on the fine grid;
+* App. A2: for the weak-equilibrium diffusion pulse with a level jump on the pulse's flank,
+  the upstream optical depth at the jump gives a flux much closer to the uniform fine grid
+  than the arithmetic mean (which the paper reports as oscillating).
+A set of planted mistakes checks that each of them fails at least one pin.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import oracle
+from oracle.amr import TwoLevel
+
+
+def _fields(rng, shape, kappa=10.0, aniso=0.05, Fscale=0.1):
+    s = shape[::-1]
+    rho = np.exp(0.5 * rng.standard_normal(s))
+    f = np.zeros((6,) + s)
+    f[:3] = 1.0 / 3.0
+    P = rng.standard_normal((6,) + s)
+    f += aniso * P * np.array([1, 1, 1, 0.5, 0.5, 0.5])[:, None, None, None]
+    E = 1 + 0.1 * rng.standard_normal(s)
+    T = 1 + 0.1 * rng.standard_normal(s)
+    F = Fscale * rng.standard_normal((3,) + s)
+    return rho, kappa * np.ones(s), f, E, F, T
+
+
+def _fine_shape(lo, hi):
+    return tuple(2 * (b - a) for a, b in zip(lo, hi))
+
+
+# ------------------------------------------------------------------ pins (metric functions)
+
+def conservation_defect(cls=TwoLevel, seed=0):
+    rng = np.random.default_rng(seed)
+    nc, lo, hi = (6, 5, 4), (2, 1, 1), (4, 4, 3)
+    c, fi = _fields(rng, nc), _fields(rng, _fine_shape(lo, hi))
+    pb = cls(nc, lo, hi, (c[0], fi[0]), (c[1], fi[1]), (c[1], fi[1]), (c[2], fi[2]), dt=0.5, dx=1 / 6,
+             bc="periodic", c=1.0)
+    E, F, T, _ = pb.step((c[3], fi[3]), (c[4], fi[4]), (c[5], fi[5]))
+    v = pb.leaf_volume()
+    tot = lambda E_, T_: np.sum(v * (pb.pack(*E_)[0] + pb.alpha * pb.pack(*T_)[0]))
+    e0 = tot((c[3], fi[3]), (c[5], fi[5]))
+    de = abs(tot(E, T) - e0) / abs(e0)
+    Fn, F1 = pb.pack(c[4], fi[4], 3), pb.pack(*F, k=3)
+    dF = np.max(np.abs(np.sum(v * (1 + pb.sR) * F1, axis=1) - np.sum(v * Fn, axis=1)) /
+                np.sum(v * np.abs(Fn), axis=1))
+    return max(de, dF)
+
+
+def _upwind_cyclic(w0, nu, right=True):
+    """Implicit upwind on a periodic line of cells with their own nu: (1 + nu_i) w_i - nu_i w_up = w0_i."""
+    if not right:
+        return _upwind_cyclic(w0[::-1], nu[::-1], True)[::-1]
+    p, q = w0 / (1 + nu), nu / (1 + nu)
+    a, b = 0.0, 1.0
+    for i in range(len(w0)):
+        a, b = p[i] + q[i] * a, q[i] * b
+    w = np.empty_like(w0)
+    prev = a / (1 - b)
+    for i in range(len(w0)):
+        prev = p[i] + q[i] * prev
+        w[i] = prev
+    return w
+
+
+def streaming_error(cls=TwoLevel, seed=1):
+    rng = np.random.default_rng(seed)
+    nx, i0, i1, c_light, dt, dx = 12, 3, 8, 1.5, 0.3, 0.2
+    nfx = 2 * (i1 - i0)
+    Ec, Ef = 1 + 0.3 * rng.random(nx), 1 + 0.3 * rng.random(nfx)
+    Fc, Ff = c_light * 0.5 * rng.standard_normal(nx), c_light * 0.5 * rng.standard_normal(nfx)
+    sc, sf = (1, 1, nx), (2, 2, nfx)
+    zc, zf = np.zeros(sc), np.zeros(sf)
+    fc, ff = np.zeros((6,) + sc), np.zeros((6,) + sf)
+    fc[0], ff[0] = 1.0, 1.0
+    pb = cls((nx, 1, 1), (i0, 0, 0), (i1, 1, 1), (zc + 1, zf + 1), (zc, zf), (zc, zf), (fc, ff), dt=dt, dx=dx,
+             bc="periodic", c=c_light)
+    F0 = (np.zeros((3,) + sc), np.zeros((3,) + sf))
+    F0[0][0] = Fc
+    F0[1][0] = Ff
+    E, F, T, _ = pb.step((zc + Ec, zf + Ef), F0, (zc + 1, zf + 1))
+    # the line of leaf cells along x and their factors c dt / h
+    seqE = np.r_[Ec[:i0], Ef, Ec[i1:]]
+    seqF = np.r_[Fc[:i0], Ff, Fc[i1:]] / c_light
+    nu = np.r_[np.full(i0, c_light * dt / dx), np.full(nfx, 2 * c_light * dt / dx), np.full(nx - i1, c_light * dt / dx)]
+    wp = _upwind_cyclic(seqE + seqF, nu, True)
+    wm = _upwind_cyclic(seqE - seqF, nu, False)
+    Ex, Fx = 0.5 * (wp + wm), 0.5 * (wp - wm) * c_light
+    err = 0.0
+    for out_c, out_f, ref in ((E[0][0, 0], E[1], Ex), (F[0][0, 0, 0], F[1][0], Fx)):
+        got = np.r_[out_c[:i0], out_f[0, 0], out_c[i1:]]
+        err = max(err, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        for j in range(2):   # the fine level stays uniform across y and z
+            for k in range(2):
+                err = max(err, np.max(np.abs(out_f[k, j] - out_f[0, 0])) / np.max(np.abs(ref)))
+    return err
+
+
+def uniform_error(cls=TwoLevel, bc="periodic"):
+    nc, lo, hi = (5, 4, 6), (1, 1, 2), (3, 3, 5)
+    nf = _fine_shape(lo, hi)
+    rho, kP, kR, cv, aR, c_light, dt, dx = 1.3, 2.0, 3.5, 0.7, 1.1, 1.0, 0.8, 0.25
+    fv = np.array([0.5, 0.3, 0.2, 0.05, -0.03, 0.02])
+    En, Fv, Tn = 1.7, np.array([0.2, -0.1, 0.05]), 1.2
+    mk = lambda s, v: np.full(s[::-1], v)
+    mkf = lambda s: np.broadcast_to(fv[:, None, None, None], (6,) + s[::-1]).copy()
+    mkF = lambda s: np.broadcast_to(Fv[:, None, None, None], (3,) + s[::-1]).copy()
+    pb = cls(nc, lo, hi, (mk(nc, rho), mk(nf, rho)), (mk(nc, kP), mk(nf, kP)), (mk(nc, kR), mk(nf, kR)),
+             (mkf(nc), mkf(nf)), dt=dt, dx=dx, bc=bc, c=c_light, aR=aR, cv=cv)
+    E, F, T, _ = pb.step((mk(nc, En), mk(nf, En)), (mkF(nc), mkF(nf)), (mk(nc, Tn), mk(nf, Tn)))
+    sP, sR, alpha = c_light * dt * rho * kP, c_light * dt * rho * kR, rho * cv
+    Tx = brentq(lambda t: alpha * (t - Tn) + sP / (1 + sP) * (aR * t ** 4 - En), 0.0, 10.0, xtol=1e-15, rtol=1e-15)
+    Ex = (En + sP * aR * Tx ** 4) / (1 + sP)
+    Fx = Fv / (1 + sR)
+    err = 0.0
+    for lev in (0, 1):
+        err = max(err, np.max(np.abs(E[lev] - Ex)) / Ex, np.max(np.abs(T[lev] - Tx)) / Tx)
+        for q in range(3):
+            err = max(err, np.max(np.abs(F[lev][q] - Fx[q])) / np.max(np.abs(Fx)))
+    return err
+
+
+def full_cover_error(cls=TwoLevel):
+    rng = np.random.default_rng(3)
+    nc = (3, 2, 2)
+    nf = (6, 4, 4)
+    c, fi = _fields(rng, nc), _fields(rng, nf)
+    dt, dx = 0.4, 0.25
+    pb = cls(nc, (0, 0, 0), nc, (c[0], fi[0]), (c[1], fi[1]), (c[1], fi[1]), (c[2], fi[2]), dt=dt, dx=dx,
+             bc=("outflow", "outflow", "periodic", "periodic", "outflow", "outflow"))
+    E, F, T, _ = pb.step((c[3], fi[3]), (c[4], fi[4]), (c[5], fi[5]))
+    uni = oracle.Problem(fi[0], fi[1], fi[1], fi[2], dt=dt, dx=dx / 2,
+                         bc=("outflow", "outflow", "periodic", "periodic", "outflow", "outflow"))
+    Eu, Fu, Tu, _ = uni.step(fi[3], fi[4], fi[5], tol=1e-14)
+    err = max(np.max(np.abs(E[1] - Eu)) / np.max(np.abs(Eu)), np.max(np.abs(F[1] - Fu)) / np.max(np.abs(Fu)),
+              np.max(np.abs(T[1] - Tu)) / np.max(np.abs(Tu)))
+    # covered coarse cells hold the mean of their children
+    m = Eu.reshape(2, 2, 2, 2, 3, 2).mean(axis=(1, 3, 5))
+    return max(err, np.max(np.abs(E[0] - m)) / np.max(np.abs(m)))
+
+
+# weak-equilibrium diffusion pulse of the radiating-pulse test (sigma h ~ 0.4 on the coarse
+# grid), refined on x < 0.04 so that the level jump sits on the pulse's flank
+_A2 = dict(nx=128, L=1.28, sig=40.0, mu=20.0, i0=1, i1=68, steps=20)
+
+
+def _pulse(x):
+    D = 1.0 / (3.0 * _A2["sig"])
+    E = np.exp(-_A2["mu"] ** 2 * x ** 2)
+    return E, D * 2 * _A2["mu"] ** 2 * x * E
+
+
+def a2_interface_error(cls=TwoLevel, jump_tau="upstream"):
+    nx, L, sig, i0, i1 = _A2["nx"], _A2["L"], _A2["sig"], _A2["i0"], _A2["i1"]
+    h = L / nx
+    xc = -L / 2 + (np.arange(nx) + 0.5) * h
+    nfx = 2 * (i1 - i0)
+    xf = xc[i0] - h / 4 + np.arange(nfx) * h / 2
+    sc, sf = (1, 1, nx), (2, 2, nfx)
+    oc, of = np.ones(sc), np.ones(sf)
+    fc, ff = np.zeros((6,) + sc), np.zeros((6,) + sf)
+    fc[:3], ff[:3] = 1 / 3, 1 / 3
+    pb = cls((nx, 1, 1), (i0, 0, 0), (i1, 1, 1), (oc, of), (0 * oc, 0 * of), (sig * oc, sig * of), (fc, ff),
+             dt=h / 2, dx=h, bc="outflow", jump_tau=jump_tau)
+    (Ec, Fc), (Ef, Ff) = _pulse(xc), _pulse(xf)
+    E = (Ec * oc, Ef * of)
+    F = (np.zeros((3,) + sc), np.zeros((3,) + sf))
+    F[0][0], F[1][0] = Fc * oc, Ff * of
+    T = (oc.copy(), of.copy())
+    for _ in range(_A2["steps"]):
+        E, F, T, _ = pb.step(E, F, T)
+    # uniform grid at the fine resolution (the uniform oracle)
+    n = 2 * nx
+    xu = -L / 2 + (np.arange(n) + 0.5) * h / 2
+    one = np.ones((1, 1, n))
+    fu = np.zeros((6, 1, 1, n))
+    fu[:3] = 1 / 3
+    uni = oracle.Problem(one, 0 * one, sig * one, fu, dt=h / 2, dx=h / 2, bc="outflow")
+    Eu, Fu = _pulse(xu)
+    Eu, FuA, Tu = Eu.reshape(1, 1, n), np.zeros((3, 1, 1, n)), one.copy()
+    FuA[0, 0, 0] = Fu
+    for _ in range(_A2["steps"]):
+        Eu, FuA, Tu, _ = uni.step(Eu, FuA, Tu)
+    Fu = FuA[0, 0, 0]
+    err_f = np.abs(F[1][0, 0, 0] - Fu[2 * i0:2 * i1])[-6:]
+    err_c = np.abs(F[0][0, 0, 0] - Fu.reshape(nx, 2).mean(1))[i1:i1 + 4]
+    return max(err_f.max(), err_c.max()) / np.max(np.abs(Fu))
+
+
+# ------------------------------------------------------------------ the pins
+
+def test_composite_conserves_energy_and_momentum():
+    assert conservation_defect() < 1e-13
+
+
+def test_streaming_matches_nonuniform_upwind_closed_form():
+    assert streaming_error() < 1e-13
+
+
+@pytest.mark.parametrize("bc", ["periodic", "outflow"])
+def test_uniform_state_follows_one_cell_closed_form(bc):
+    assert uniform_error(bc=bc) < 1e-13
+
+
+def test_full_cover_reduces_to_uniform_fine_grid():
+    assert full_cover_error() < 1e-11
+
+
+def test_upstream_tau_beats_average_at_level_jump():
+    up = a2_interface_error(jump_tau="upstream")
+    avg = a2_interface_error(jump_tau="average")
+    # relative to max |F|: upstream stays within 2 % of the uniform fine grid, the mean is > 3x worse
+    assert up < 2e-2
+    assert avg > 3 * up
+
+
+# ------------------------------------------------------------------ planted mistakes
+
+class _CoarseWeightHalf(TwoLevel):   # 2D area ratio instead of the 3D one
+    def _faces(self):
+        super()._faces()
+        coarse_L = self.fJ & (self.level[self.fL] == 0)
+        coarse_R = self.fJ & (self.level[self.fR] == 0)
+        self.fWL = np.where(coarse_L, 2 * self.fWL, self.fWL)
+        self.fWR = np.where(coarse_R, 2 * self.fWR, self.fWR)
+
+
+class _FineWeightCoarse(TwoLevel):   # fine cells divided by the coarse width
+    def _faces(self):
+        super()._faces()
+        fine_L = self.fJ & (self.level[self.fL] == 1)
+        fine_R = self.fJ & (self.level[self.fR] == 1)
+        self.fWL = np.where(fine_L, 0.5 * self.fWL, self.fWL)
+        self.fWR = np.where(fine_R, 0.5 * self.fWR, self.fWR)
+
+
+class _SwapUpstream(TwoLevel):       # downstream optical depth at level jumps
+    def face_speeds(self):
+        CL, CR = super().face_speeds()
+        return np.where(self.fJ, CR, CL), np.where(self.fJ, CL, CR)
+
+
+class _JumpOrientation(TwoLevel):    # left and right cells of level-jump faces exchanged
+    def _faces(self):
+        super()._faces()
+        L, R = self.fL.copy(), self.fR.copy()
+        WL, WR = self.fWL.copy(), self.fWR.copy()
+        self.fL, self.fR = np.where(self.fJ, R, L), np.where(self.fJ, L, R)
+        self.fWL, self.fWR = np.where(self.fJ, WR, WL), np.where(self.fJ, WL, WR)
+
+
+class _FineTauCoarseWidth(TwoLevel):  # every cell's tau taken with the coarse width
+    def face_speeds(self):
+        saved = self.h_cell
+        self.h_cell = np.full(self.N, self.hl[0])
+        try:
+            return super().face_speeds()
+        finally:
+            self.h_cell = saved
+
+
+class _ParentOffByOne(TwoLevel):     # fine cell coupled to the coarse cell one further out
+    def _faces(self):
+        super()._faces()
+        nx = self.nc[0]
+        shift = np.where(self.fJ & (self.fD == 0) & (self.level[self.fL] == 0), -1, 0)
+        shift2 = np.where(self.fJ & (self.fD == 0) & (self.level[self.fR] == 0), 1, 0)
+        self.fL = self.fL + shift
+        self.fR = self.fR + shift2
+        assert nx > 2
+
+
+MUTANTS = [_CoarseWeightHalf, _FineWeightCoarse, _SwapUpstream, _JumpOrientation, _FineTauCoarseWidth,
+           _ParentOffByOne]
+
+
+@pytest.mark.parametrize("cls", MUTANTS, ids=lambda c: c.__name__.strip("_"))
+def test_planted_mistake_fails_a_pin(cls):
+    ref_a2 = a2_interface_error()
+    checks = [
+        lambda: conservation_defect(cls) > 1e-10,
+        lambda: streaming_error(cls) > 1e-10,
+        lambda: uniform_error(cls) > 1e-10,
+        lambda: a2_interface_error(cls) > 2 * ref_a2,
+    ]
+    failed = []
+    for chk in checks:
+        try:
+            failed.append(bool(chk()))
+        except (RuntimeError, ValueError, np.linalg.LinAlgError, FloatingPointError):
+            failed.append(True)   # a mutant that no longer converges also fails its pin
+        if failed[-1]:
+            break
+    assert any(failed), cls.__name__
