@@ -112,6 +112,46 @@ int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
              double dt, double dx, const int bc[6], const rad_params_t *p,
              void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
 
+/* ---------------------------------------------------- two-level AMR grid
+ * A coarse grid (nx, ny, nz) of cell width dx with one box [lo, hi) of its
+ * cells (per axis x, y, z) refined by a factor 2 (Sec. 2.3.3, eq. wavespeedtau
+ * and eq. interface_flux; App. A2).  Along each axis the box either spans the
+ * whole extent (lo = 0, hi = n: no level jump there, the fine level takes the
+ * domain's boundary condition) or stays at least one coarse cell inside it
+ * (1 <= lo < hi <= n - 1).  The fine level has extents 2 (hi - lo).
+ *
+ * Every per-cell array holds the coarse level's cells, all nx ny nz of them
+ * (covered ones included), followed by the fine level's: each level is a
+ * complete single-grid array set of its own extents (x fastest), so F is
+ * [Fx|Fy|Fz of the coarse level | Fx|Fy|Fz of the fine level] and f_ij the
+ * six coarse planes followed by the six fine ones.
+ *
+ * The step solves the composite backward-Euler system: at a face where the
+ * level changes the HLLE speeds take the upstream cell's optical depth (each
+ * cell's with its own width), the fine cells' neighbour is the coarse cell,
+ * and the coarse cell receives the mean of the four fine face fluxes, so E and
+ * F are conserved by construction.  Covered coarse cells are no part of the
+ * transport; on return they hold the mean of their eight children (E, F and
+ * T).  Boundaries of the domain: periodic (in pairs) or outflow. */
+typedef struct {
+    int nx, ny, nz;     /* coarse extents */
+    int lo[3], hi[3];   /* refined box in coarse cells, [lo, hi) per axis x, y, z */
+} rad_amr2_t;
+
+/* Workspace bytes of rad_step_amr2 (0 if the geometry or params are invalid). */
+size_t rad_workspace_bytes_amr2(const rad_amr2_t *geom, const rad_params_t *p);
+
+/* One implicit step on the two-level grid; arguments as rad_step, with the
+ * geometry in geom, dx the coarse cell width and the arrays in the two-level
+ * layout above (device pointers owned by the caller; E, F, T_gas updated in
+ * place).  Errors: RAD_EINVAL for an invalid geometry (a box that neither
+ * spans an axis nor stays inside it, more than 2^31 cells in all), the
+ * conditions of rad_step otherwise.  The autotune cache is not consulted. */
+int rad_step_amr2(const rad_amr2_t *geom, double *E, double *F, double *T_gas,
+                  const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
+                  double dt, double dx, const int bc[6], const rad_params_t *p,
+                  void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
+
 /* Autotune rad_step for this grid, boundary set, precision and coefficient
  * type on the caller's data (same arguments as rad_step; the state E, F, T_gas
  * is left as it was on entry).  Times the stencil's z-range per workgroup

@@ -308,7 +308,10 @@ class TwoLevel:
         rF = np.linalg.norm(R[1:4] / W[1:4]) / max(nF + nE, 1e-300)
         WT = self.alpha + 4.0 * self.sP * self.aR * T ** 3
         WT = np.where(WT > 0, WT, 1.0)
-        rT = np.linalg.norm(R[4] / WT) / max(nT, 1e-300)
+        # T >= 0 is the physical range: where the quartic has no non-negative root (R_T > 0 at
+        # T = 0) the bound is active and the exchange row counts as satisfied
+        RT = np.where((T == 0.0) & (R[4] > 0.0), 0.0, R[4])
+        rT = np.linalg.norm(RT / WT) / max(nT, 1e-300)
         return max(rE, rF, rT)
 
     def step(self, E, F, T, tol=1e-13, mode="linearised", max_picard=100):

@@ -16,6 +16,7 @@
 // operator apply and the FP64 residual of one Picard iteration share the sweep.
 #pragma once
 #include "rad_device.h"
+#include "rad_amr.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -390,12 +391,14 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // y = D^-1 A (s x) (PRE: Jacobi-scaled Krylov operator, dE the E diagonal of
 // the Picard iteration) or y = A x with flux rescaling xF/yF (!PRE: the
 // physical operator of one Picard iteration with E diagonal dE).
-template <class AT, class ST, bool PRE>
+// AMR: one level of the two-level composite grid -- covered coarse cells keep
+// only their local terms, jump cells add their level-jump corrections.
+template <class AT, class ST, bool PRE, bool AMR = false>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
-                  AT *__restrict__ y, AT xF, AT yF)
+                  AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{})
 {
     __shared__ AT lds[2][Rec<PRE>::NL][TileShape<AT>::LY][kLX];
     const long long N = g.N;
@@ -408,9 +411,24 @@ __global__ void __launch_bounds__(tile_threads<AT>())
         const AT dEc = e[0];
         AT yE = dEc * S.Ec + nu * S.dEs, yFq[3];
         for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + S.sc) * S.Fc[q] + nu * S.dF[q];
+        AT dtr = half * S.sumC_nb;   // transport part of the Jacobi diagonal
+        if constexpr (AMR) {
+            const int jj = (int)(o / (unsigned)g.nx), ii = (int)(o - (unsigned)jj * (unsigned)g.nx);
+            const int role = amr_role(al, ii, jj, k);
+            if (role == AMR_COVERED) {
+                yE = dEc * S.Ec;
+                for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + S.sc) * S.Fc[q];
+                dtr = AT(0);
+            } else if (role == AMR_JUMP) {
+                const long long c = pb + o;
+                yE += (AT)al.corr[c];
+                for (int q = 0; q < 3; ++q) yFq[q] += (AT)al.corr[(1 + q) * N + c];
+                dtr += (AT)al.corr[4 * N + c];
+            }
+        }
         if constexpr (PRE) {
-            yE *= AT(1) / (dEc + half * S.sumC_nb);
-            const AT iDF = AT(1) / (AT(1) + S.sc + half * S.sumC_nb);
+            yE *= AT(1) / (dEc + dtr);
+            const AT iDF = AT(1) / (AT(1) + S.sc + dtr);
             for (int q = 0; q < 3; ++q) yFq[q] *= iDF;
         }
         if (active) {

@@ -64,7 +64,7 @@ int check_params(const rad_params_t *p)
 static const char *const kNames[K_NCLASS] = {
     "setup", "residual_fp64", "apply_fp32", "apply_fp64", "multidot_fp32", "multidot_fp64", "orth_update_fp32",
     "orth_update_fp64", "update_x_fp32", "update_x_fp64", "exchange_fp64", "commit", "reduce", "batched_persistent",
-    "closure"};
+    "closure", "amr_jump"};
 
 struct Pending {
     hipEvent_t a, b;

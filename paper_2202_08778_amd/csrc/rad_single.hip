@@ -11,6 +11,7 @@
 // only keeps the (m+1) x m Hessenberg matrix and decides when to stop.
 #include "rad_host.h"
 #include "rad_apply_tiled.h"
+#include "rad_amr.h"
 
 #include <algorithm>
 #include <chrono>
@@ -21,6 +22,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace vr;
@@ -144,13 +146,15 @@ __global__ void __launch_bounds__(kBlock)
 // The RES_KRYLOV residual of k_residual as a tile sweep: FP64 state, stored
 // coefficients, and the face speeds and sR precomputed in FP64 once per step
 // (the same values k_residual derives per face).  Partial sums per tile.
-template <class CT, class KT, class DT>
+// AMR: one level of the two-level composite grid (covered coarse cells keep
+// their local terms only, jump cells add their level-jump corrections).
+template <class CT, class KT, class DT, bool AMR = false>
 __global__ void __launch_bounds__(tile_threads<double>())
     k_residual_tiled(Grid g, TileGeom tg, int picard_mode, const double *__restrict__ En,
                      const double *__restrict__ Fn, const double *__restrict__ Tn, const double *__restrict__ Ts,
                      const CT *__restrict__ rho, const CT *__restrict__ kP, const CT *__restrict__ f,
                      const double *__restrict__ sR64, const double *__restrict__ Cf64, const double *__restrict__ X,
-                     KT *__restrict__ out, DT *__restrict__ dEA, double *partials)
+                     KT *__restrict__ out, DT *__restrict__ dEA, double *partials, AmrLv al = AmrLv{})
 {
     __shared__ double lds[2][Rec<true>::NL][TileShape<double>::LY][kLX];
     const long long N = g.N;
@@ -182,13 +186,28 @@ __global__ void __launch_bounds__(tile_threads<double>())
             bE = e[0] + eta * alpha * e[4] - 3.0 * (1.0 - eta) * sP * aR * T4;
         }
         const double E = S.Ec;
-        const double rE = bE - (dE * E + nu * S.dEs);
-        const double DE = dE + half * S.sumC_nb, DF = 1.0 + sR + half * S.sumC_nb;
+        double divE = nu * S.dEs, divF[3] = {nu * S.dF[0], nu * S.dF[1], nu * S.dF[2]};
+        double dtr = half * S.sumC_nb;   // transport part of the Jacobi diagonal
+        if constexpr (AMR) {
+            const int jj = (int)(o / (unsigned)g.nx), ii = (int)(o - (unsigned)jj * (unsigned)g.nx);
+            const int role = amr_role(al, ii, jj, k);
+            if (role == AMR_COVERED) {
+                divE = divF[0] = divF[1] = divF[2] = 0.0;
+                dtr = 0.0;
+            } else if (role == AMR_JUMP) {
+                const long long c = pb + o;
+                divE += al.corr[c];
+                for (int q = 0; q < 3; ++q) divF[q] += al.corr[(1 + q) * N + c];
+                dtr += al.corr[4 * N + c];
+            }
+        }
+        const double rE = bE - (dE * E + divE);
+        const double DE = dE + dtr, DF = 1.0 + sR + dtr;
         const double WE = 1.0 + sP + half * S.sumC_all, WF = 1.0 + sR + half * S.sumC_all;
         const double zE = rE / DE;
         double zF[3], zz = zE * zE, wf = 0, fn = 0;
         for (int q = 0; q < 3; ++q) {
-            const double rF = e[1 + q] * invc - ((1.0 + sR) * S.Fc[q] + nu * S.dF[q]);
+            const double rF = e[1 + q] * invc - ((1.0 + sR) * S.Fc[q] + divF[q]);
             zF[q] = rF / DF;
             zz += zF[q] * zF[q];
             wf += (rF / WF) * (rF / WF);
@@ -619,14 +638,23 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, V, W, part, small, total;
+    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, V, W, part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
 
 long long vec_blocks(long long n) { return std::min<long long>((n / 4 + kBlock - 1) / kBlock, 2048); }
 
-Layout layout(long long N, const rad_params_t &p)
+// Upper bound on the workgroups of a tile sweep over an nx x ny x nz grid (tiles of
+// 64 x 4 or more cells; z-ranges of all nz <= 8 planes, else at least 4): partial-sum rows.
+long long tile_bound(int nx, int ny, int nz)
+{
+    return (long long)((nx + 63) / 64) * ((ny + 3) / 4) * (nz <= 8 ? 1 : (nz + 3) / 4);
+}
+
+// part_rows: partial-sum rows the sweeps of every level need (tile_bound summed);
+// amr: room for the level-jump corrections (5 FP64 planes over the composite grid).
+Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false)
 {
     Layout L;
     const bool mixed = p.prec == RAD_MIXED;
@@ -655,9 +683,11 @@ Layout layout(long long N, const rad_params_t &p)
     const int ma = p.anderson_m;
     L.AAG = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
     L.AAf = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
+    L.AMRC = take(amr ? 5 * N * 8 : 0);
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
-    L.part = take((size_t)std::max<long long>(L.nblk_cells, L.nblk_vec) * 24 * 8);
+    // per-cell kernels of a two-level grid use one more (partial) block than the cell count gives
+    L.part = take((size_t)std::max(std::max<long long>(L.nblk_cells + 2, L.nblk_vec), part_rows) * 24 * 8);
     L.small = take(512 * 8);
     L.total = o;
     return L;
@@ -674,7 +704,17 @@ enum {
 };
 
 struct Solver {
-    Grid g;
+    Grid g;        // the single grid, or the coarse level
+    // levels: one uniform grid, or the coarse and fine levels of a two-level
+    // composite grid stored one after the other (level l starts at cell c0[l]
+    // of every per-cell array; each level is a complete single-grid array set)
+    int nlev = 1;
+    Grid gl[2];
+    long long c0[2] = {0, 0};
+    bool amr = false;
+    Amr A{};
+    long long nshell = 0, ncoarse = 0;  // threads of the level-jump kernel
+    long long Ntot = 0;                 // cells of all levels
     rad_params_t p;
     hipStream_t st;
     char *ws;
@@ -735,10 +775,11 @@ int run_step(Solver &S)
     using AT = KT;
     Grid &g = S.g;
     const rad_params_t &p = S.p;
-    const long long N = g.N, n4 = 4 * N;
+    const long long N = S.Ntot, n4 = 4 * N;
+    const int NL = S.nlev;
     // gf: one 4-element group per thread for the Krylov streaming passes (their per-block
     // partial sums go through the two-stage reduction); gv: a capped grid for the rest
-    const dim3 gc((unsigned)S.L.nblk_cells), gv((unsigned)S.L.nblk_vec), gf((unsigned)S.L.nblk_cells), bl(kBlock);
+    const dim3 gv((unsigned)S.L.nblk_vec), gf((unsigned)S.L.nblk_cells), bl(kBlock);
     const CT *rho = (const CT *)S.rho, *kP = (const CT *)S.kP, *kR = (const CT *)S.kR, *f = (const CT *)S.f;
     double *X = S.at<double>(S.L.X), *X0 = S.at<double>(S.L.X0), *Tc = S.at<double>(S.L.Tc);
     AT *sR = S.at<AT>(S.L.sR), *dEA = S.at<AT>(S.L.dEA);
@@ -752,11 +793,19 @@ int run_step(Solver &S)
     const bool mixed = sizeof(KT) == 4;
     double *sR64 = mixed ? S.at<double>(S.L.sR64) : (double *)sR;
     const double cb = sizeof(CT), kb = sizeof(KT), Nd = (double)N;
+    // per-cell kernels run once per level; their partial sums are stacked level after level
+    auto cell_grid = [&](int l) { return dim3((unsigned)((S.gl[l].N + kBlock - 1) / kBlock)); };
+    long long rows = 0;
     S.timed(K_SETUP, Nd * (9 * cb + 40 + kb + (mixed ? 8 : 0) + (fA ? 6 * kb : 0) + 72), [&] {
-        hipLaunchKernelGGL((k_setup<CT, AT>), gc, bl, 0, S.st, g, rho, kP, kR, f, sR, mixed ? sR64 : nullptr, fA,
-                           S.En, S.Fn, S.Tn, X, X0, Tc, part);
+        for (int l = 0; l < NL; ++l) {
+            const long long o = S.c0[l];
+            hipLaunchKernelGGL((k_setup<CT, AT>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kP + o, kR + o,
+                               f + 6 * o, sR + o, mixed ? sR64 + o : nullptr, fA ? fA + 6 * o : nullptr, S.En + o,
+                               S.Fn + 3 * o, S.Tn + o, X + 4 * o, X0 + 4 * o, Tc + o, part + rows);
+            rows += cell_grid(l).x;
+        }
     });
-    S.reduce(S.L.nblk_cells, 1, 1, sm + SM_RED);
+    S.reduce(rows, 1, 1, sm + SM_RED);
     RAD_TRY(S.read(SM_RED, 1));
     st.bad_cells = (int)h[SM_RED];
     if (st.bad_cells > 0) return fail(RAD_EDATA, "%d cells with invalid rho/kappa/f data", st.bad_cells);
@@ -766,38 +815,99 @@ int run_step(Solver &S)
     const int kOrth = sizeof(KT) == 4 ? K_ORTH32 : K_ORTH64;
     const int kUpd = sizeof(KT) == 4 ? K_UPDATEX32 : K_UPDATEX64;
     const double fb = fA ? kb : cb;   // bytes per stored tensor component read by the apply
-    TileGeom tg = tile_geom<AT>(g, S.kz_apply), tgr = tile_geom<double>(g, S.kz_res, 128, 256);
+    TileGeom tg[2], tgr[2];
+    for (int l = 0; l < NL; ++l) {
+        tg[l] = tile_geom<AT>(S.gl[l], S.kz_apply);
+        tgr[l] = tile_geom<double>(S.gl[l], S.kz_res, 128, 256);
+    }
     auto tiles = [](const TileGeom &t) { return dim3((unsigned)(t.tiles_x * t.tiles_y * t.tiles_z)); };
     const dim3 bt(tile_threads<AT>()), bt64(tile_threads<double>());
     AT *Cf = S.at<AT>(S.L.Cf);
     double *Cf64 = mixed ? S.at<double>(S.L.Cf64) : (double *)Cf;
     S.timed(K_SETUP, Nd * (3 * cb + 3 * kb), [&] {
-        hipLaunchKernelGGL((k_face_coef<CT, AT>), gc, bl, 0, S.st, g, rho, kR, f, Cf);
+        for (int l = 0; l < NL; ++l) {
+            const long long o = S.c0[l];
+            hipLaunchKernelGGL((k_face_coef<CT, AT>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kR + o, f + 6 * o,
+                               Cf + 3 * o);
+        }
     });
     if (mixed)
         S.timed(K_SETUP, Nd * (3 * cb + 3 * 8), [&] {
-            hipLaunchKernelGGL((k_face_coef<CT, double>), gc, bl, 0, S.st, g, rho, kR, f, Cf64);
+            for (int l = 0; l < NL; ++l) {
+                const long long o = S.c0[l];
+                hipLaunchKernelGGL((k_face_coef<CT, double>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kR + o,
+                                   f + 6 * o, Cf64 + 3 * o);
+            }
         });
+    // two-level grid: level-jump corrections of the operand x (scaled by *xs), read by the sweeps' epilogues
+    double *corr = S.amr ? S.at<double>(S.L.AMRC) : nullptr;
+    auto level_view = [&](int l) {
+        AmrLv v;
+        v.a = S.A;
+        v.lev = l;
+        v.corr = corr ? corr + 5 * S.c0[l] : nullptr;
+        return v;
+    };
+    auto jump = [&](auto x, const double *xs, auto Cc) {
+        using XT = std::remove_const_t<std::remove_pointer_t<decltype(x)>>;
+        using FT = std::remove_const_t<std::remove_pointer_t<decltype(Cc)>>;
+        const long long nt = S.nshell + S.ncoarse;
+        S.timed(K_AMR, (double)nt * 10 * 8 * sizeof(XT), [&] {
+            hipLaunchKernelGGL((k_amr_jump<XT, CT, FT>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, S.st, S.A,
+                               S.gl[0], S.gl[1], S.nshell, S.ncoarse, (const XT *)x, xs, f, (const double *)sR64,
+                               (const FT *)Cc, corr);
+        });
+    };
     auto apply = [&](const KT *x, const double *xs, KT *y) {
+        if (S.amr) jump(x, xs, (const AT *)Cf);
         const int tok = prof_begin(kApply, S.st);
-        if (fA)
-            hipLaunchKernelGGL((k_apply_tiled<AT, AT, true>), tiles(tg), bt, 0, S.st, g, tg, (const AT *)fA, sR,
-                               (const AT *)nullptr, (const AT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
-        else
-            hipLaunchKernelGGL((k_apply_tiled<AT, CT, true>), tiles(tg), bt, 0, S.st, g, tg, f, sR,
-                               (const CT *)nullptr, (const CT *)nullptr, (const AT *)Cf, dEA, x, xs, y, AT(1), AT(1));
+        for (int l = 0; l < NL; ++l) {
+            const long long o = S.c0[l];
+            auto go = [&](auto amr_c) {
+                constexpr bool AM = decltype(amr_c)::value;
+                if (fA)
+                    hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM>), tiles(tg[l]), bt, 0, S.st, S.gl[l], tg[l],
+                                       (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr, (const AT *)nullptr,
+                                       (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
+                                       level_view(l));
+                else
+                    hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM>), tiles(tg[l]), bt, 0, S.st, S.gl[l], tg[l],
+                                       f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
+                                       (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
+                                       level_view(l));
+            };
+            if (S.amr)
+                go(std::true_type{});
+            else
+                go(std::false_type{});
+        }
         prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
     };
     // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
     // its norm's inverse becomes the scale s_0 of V[0].
     double nrm[5];
     auto residual = [&]() -> int {
+        if (S.amr) jump((const double *)X, (const double *)nullptr, (const double *)Cf64);
         // streams X, En/Fn/Tn/Ts, sR and face speeds (FP64), f, rho, kP; writes V[0], dE
+        long long rrows = 0;
         S.timed(K_RESIDUAL, Nd * (32 + 48 + 32 + 8 * cb + 5 * kb), [&] {
-            hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT>), tiles(tgr), bt64, 0, S.st, g, tgr, p.mode, S.En, S.Fn,
-                               S.Tn, Tc, rho, kP, f, sR64, Cf64, X, V, dEA, part);
+            for (int l = 0; l < NL; ++l) {
+                const long long o = S.c0[l];
+                auto go = [&](auto amr_c) {
+                    constexpr bool AM = decltype(amr_c)::value;
+                    hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT, AM>), tiles(tgr[l]), bt64, 0, S.st, S.gl[l],
+                                       tgr[l], p.mode, S.En + o, S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o,
+                                       f + 6 * o, sR64 + o, Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o,
+                                       part + rrows * 5, level_view(l));
+                };
+                if (S.amr)
+                    go(std::true_type{});
+                else
+                    go(std::false_type{});
+                rrows += tiles(tgr[l]).x;
+            }
         });
-        S.reduce(tiles(tgr).x, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
+        S.reduce(rrows, 5, 5, sm + SM_RED, nullptr, 4, sm + SM_S);
         RAD_TRY(S.read(SM_RED, 5));
         for (int q = 0; q < 5; ++q) nrm[q] = h[SM_RED + q];
         st.refine_sweeps++;
@@ -834,8 +944,8 @@ int run_step(Solver &S)
         float best_a = INFINITY, best_r = INFINITY;
         int rc = RAD_OK;
         for (int kz : *S.tune_kz) {
-            tg = tile_geom<AT>(g, kz);
-            tgr = tile_geom<double>(g, kz);
+            tg[0] = tile_geom<AT>(g, kz);
+            tgr[0] = tile_geom<double>(g, kz);
             float ms_a = 0, ms_r = 0;
             apply(V, sm + SM_S, W);
             if (hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
@@ -973,10 +1083,17 @@ int run_step(Solver &S)
         // ---- exchange: per-cell Newton for T, diagnostics of the iteration
         const int aslot = aa_m > 0 ? k % (aa_m + 1) : 0;
         double *Gk = aa_m > 0 ? AAG + (size_t)aslot * N : nullptr, *fk = aa_m > 0 ? AAf + (size_t)aslot * N : nullptr;
+        long long xrows = 0;
         S.timed(K_EXCHANGE, Nd * (2 * cb + 16 + 64 + 40 + (aa_m > 0 ? 16 : 0)), [&] {
-            hipLaunchKernelGGL((k_exchange<CT>), gc, bl, 0, S.st, g, rho, kP, S.Tn, Tc, X, X0, part, Gk, fk);
+            for (int l = 0; l < NL; ++l) {
+                const long long o = S.c0[l];
+                hipLaunchKernelGGL((k_exchange<CT>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kP + o, S.Tn + o,
+                                   Tc + o, X + 4 * o, X0 + 4 * o, part + xrows * 8, Gk ? Gk + o : nullptr,
+                                   fk ? fk + o : nullptr);
+                xrows += cell_grid(l).x;
+            }
         });
-        S.reduce(S.L.nblk_cells, 8, 8, sm + SM_RED);
+        S.reduce(xrows, 8, 8, sm + SM_RED);
         RAD_TRY(S.read(SM_RED, 8));
         const double *e = h + SM_RED;
         resT = e[1] > 0 ? std::sqrt(e[0] / e[1]) : std::sqrt(e[0]);
@@ -1014,9 +1131,18 @@ int run_step(Solver &S)
                 if (Hs > 0) {
                     for (int i = 0; i < Hs; ++i) hh.gamma[i] = gam[i];
                     S.timed(K_EXCHANGE, Nd * (8 * (Hs + 1) + 2 * cb + 32), [&] {
-                        launch_aa_mix<CT, kMaxAnderson>(Hs, gv, S.st, g, Gk, hh, rho, kP, S.Tn, X, Tc, part);
+                        for (int l = 0; l < NL; ++l) {
+                            const long long o = S.c0[l];
+                            AAHist hl = hh;
+                            for (int i = 0; i < Hs; ++i) {
+                                hl.f[i] = hh.f[i] + o;
+                                hl.G[i] = hh.G[i] + o;
+                            }
+                            launch_aa_mix<CT, kMaxAnderson>(Hs, gv, S.st, S.gl[l], Gk + o, hl, rho + o, kP + o,
+                                                            S.Tn + o, X + 4 * o, Tc + o, part + (long long)l * gv.x * 2);
+                        }
                     });
-                    S.reduce(S.L.nblk_vec, 2, 2, sm + SM_RED);
+                    S.reduce((long long)NL * gv.x, 2, 2, sm + SM_RED);
                     RAD_TRY(S.read(SM_RED, 2));
                     resT = h[SM_RED + 1] > 0 ? std::sqrt(h[SM_RED] / h[SM_RED + 1]) : std::sqrt(h[SM_RED]);
                 }
@@ -1037,7 +1163,18 @@ int run_step(Solver &S)
                          k, res, st.res_E, st.res_F, resT, its, st.krylov_iters, cycles, reorth, st.rel_change,
                          st.neg_cells);
     }
-    S.timed(K_COMMIT, Nd * 80, [&] { hipLaunchKernelGGL(k_commit, gc, bl, 0, S.st, N, g.c, X, Tc, S.E, S.F, S.T); });
+    S.timed(K_COMMIT, Nd * 80, [&] {
+        for (int l = 0; l < NL; ++l) {
+            const long long o = S.c0[l];
+            hipLaunchKernelGGL(k_commit, cell_grid(l), bl, 0, S.st, S.gl[l].N, g.c, X + 4 * o, Tc + o, S.E + o,
+                               S.F + 3 * o, S.T + o);
+        }
+        if (S.amr) {
+            const long long nb = (long long)(S.A.hi[0] - S.A.lo[0]) * (S.A.hi[1] - S.A.lo[1]) * (S.A.hi[2] - S.A.lo[2]);
+            hipLaunchKernelGGL(k_amr_restrict, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S.st, S.A, S.E, S.F,
+                               S.T);
+        }
+    });
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(S.st));
     prof_resolve();
@@ -1074,7 +1211,7 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
 extern "C" size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t *p)
 {
     if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
-    return layout((long long)nx * ny * nz, *p).total;
+    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz)).total;
 }
 
 namespace {
@@ -1122,11 +1259,14 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace) % 256) return fail(RAD_EINVAL, "workspace must be 256-byte aligned");
     S.p = *p;
-    S.L = layout((long long)nx * ny * nz, *p);
+    S.L = layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz));
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
     S.host = pinned_staging();
     if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
     S.g = make_grid(nx, ny, nz, bc, dt, dx, *p);
+    S.nlev = 1;
+    S.gl[0] = S.g;
+    S.Ntot = S.g.N;
     S.st = (hipStream_t)stream;
     S.ws = (char *)workspace;
     S.rho = rho;
@@ -1159,6 +1299,111 @@ extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_
                         stream));
     int rc;
     try {  // small host vectors of the GMRES least-squares problem
+        rc = dispatch_step(S);
+    } catch (const std::bad_alloc &) {
+        rc = fail(RAD_ENOMEM, "host memory");
+    }
+    S.stats.status = rc;
+    S.stats.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S.stats;
+    return rc;
+}
+
+namespace {
+
+// Geometry of a two-level grid: its levels' grids, the box and the level-jump thread counts.
+int amr_setup(const rad_amr2_t *geom, const int bc[6], double dt, double dx, const rad_params_t *p, Solver &S)
+{
+    if (!geom) return fail(RAD_EINVAL, "geometry is NULL");
+    const int nc[3] = {geom->nx, geom->ny, geom->nz};
+    RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, false));
+    Amr &A = S.A;
+    int fbc[6];
+    for (int d = 0; d < 3; ++d) {
+        const int lo = geom->lo[d], hi = geom->hi[d];
+        const bool span = lo == 0 && hi == nc[d];
+        if (!span && !(1 <= lo && lo < hi && hi <= nc[d] - 1))
+            return fail(RAD_EINVAL, "refined box must span axis %d or stay one coarse cell inside it", d);
+        A.lo[d] = lo;
+        A.hi[d] = hi;
+        A.nc[d] = nc[d];
+        A.nf[d] = 2 * (hi - lo);
+        A.jump[d] = span ? 0 : 1;
+        fbc[2 * d] = span ? bc[2 * d] : RAD_BC_OUTFLOW;
+        fbc[2 * d + 1] = span ? bc[2 * d + 1] : RAD_BC_OUTFLOW;
+    }
+    if ((long long)A.nf[0] * A.nf[1] > (1LL << 27)) return fail(RAD_EINVAL, "fine level nx * ny larger than 2^27");
+    A.Nc = (long long)nc[0] * nc[1] * nc[2];
+    A.Nf = (long long)A.nf[0] * A.nf[1] * A.nf[2];
+    if (A.Nc + A.Nf > (1LL << 31)) return fail(RAD_EINVAL, "two-level grid larger than 2^31 cells");
+    S.nlev = 2;
+    S.amr = true;
+    S.gl[0] = make_grid(nc[0], nc[1], nc[2], bc, dt, dx, *p);
+    S.gl[1] = make_grid(A.nf[0], A.nf[1], A.nf[2], fbc, dt, 0.5 * dx, *p);
+    S.g = S.gl[0];
+    S.c0[0] = 0;
+    S.c0[1] = A.Nc;
+    S.Ntot = A.Nc + A.Nf;
+    const long long a = A.nf[0], b = A.nf[1], c = A.nf[2];
+    S.nshell = 2 * b * c + 2 * (a - 2) * c + 2 * (a - 2) * (b - 2);
+    S.ncoarse = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+        if (A.jump[d]) S.ncoarse += 2LL * (A.hi[e1] - A.lo[e1]) * (A.hi[e2] - A.lo[e2]);
+    }
+    return RAD_OK;
+}
+
+Layout amr_layout(const Solver &S, const rad_params_t &p)
+{
+    const Amr &A = S.A;
+    return layout(S.Ntot, p, tile_bound(A.nc[0], A.nc[1], A.nc[2]) + tile_bound(A.nf[0], A.nf[1], A.nf[2]), true);
+}
+
+}  // namespace
+
+extern "C" size_t rad_workspace_bytes_amr2(const rad_amr2_t *geom, const rad_params_t *p)
+{
+    Solver S;
+    const int bc[6] = {RAD_BC_PERIODIC, RAD_BC_PERIODIC, RAD_BC_PERIODIC, RAD_BC_PERIODIC, RAD_BC_PERIODIC,
+                       RAD_BC_PERIODIC};
+    if (!p || amr_setup(geom, bc, 1.0, 1.0, p, S) != RAD_OK) {
+        clear_error();
+        return 0;
+    }
+    return amr_layout(S, *p).total;
+}
+
+extern "C" int rad_step_amr2(const rad_amr2_t *geom, double *E, double *F, double *T_gas, const void *rho,
+                             const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                             const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
+                             rad_stats_t *stats)
+{
+    clear_error();
+    auto t0 = std::chrono::steady_clock::now();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Solver S;
+    RAD_TRY(amr_setup(geom, bc, dt, dx, p, S));
+    if (!E || !F || !T_gas || !rho || !kappa_P || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
+    if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace) % 256) return fail(RAD_EINVAL, "workspace must be 256-byte aligned");
+    S.p = *p;
+    S.L = amr_layout(S, *p);
+    if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
+    S.host = pinned_staging();
+    if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
+    S.st = (hipStream_t)stream;
+    S.ws = (char *)workspace;
+    S.rho = rho;
+    S.kP = kappa_P;
+    S.kR = kappa_R;
+    S.f = f_ij;
+    S.En = S.E = E;
+    S.Fn = S.F = F;
+    S.Tn = S.T = T_gas;
+    std::memset(&S.stats, 0, sizeof(S.stats));
+    int rc;
+    try {
         rc = dispatch_step(S);
     } catch (const std::bad_alloc &) {
         rc = fail(RAD_ENOMEM, "host memory");

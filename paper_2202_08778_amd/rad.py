@@ -43,6 +43,10 @@ class BlockDesc(ct.Structure):
                 ("off", ct.c_longlong)]
 
 
+class Amr2(ct.Structure):
+    _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int), ("lo", ct.c_int * 3), ("hi", ct.c_int * 3)]
+
+
 class RadError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"rad error {code}: {msg}")
@@ -62,6 +66,10 @@ def _load():
     L.rad_workspace_bytes.restype = SZ
     L.rad_step.argtypes = [I, I, I, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
     L.rad_step.restype = I
+    L.rad_workspace_bytes_amr2.argtypes = [ct.POINTER(Amr2), PP]
+    L.rad_workspace_bytes_amr2.restype = SZ
+    L.rad_step_amr2.argtypes = [ct.POINTER(Amr2), P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
+    L.rad_step_amr2.restype = I
     L.rad_residual.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, D, D, IA6, PP, P, P]
     L.rad_residual.restype = I
     L.rad_face_speeds.argtypes = [I, I, I, P, P, P, D, IA6, PP, P, P]
@@ -104,7 +112,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_autotune_step", "rad_residual",
+EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_workspace_bytes_amr2", "rad_step_amr2",
+            "rad_autotune_step", "rad_residual",
             "rad_face_speeds",
             "rad_apply", "rad_exchange", "rad_closure", "rad_batched_workspace_bytes", "rad_plan_batched",
             "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_launch_shape",
@@ -214,6 +223,66 @@ def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace
     rc = lib.rad_step(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
                       _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
                       _stream(stream), ct.byref(st))
+    if check:
+        _check(rc)
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def amr_geometry(coarse_shape, lo, hi) -> Amr2:
+    """rad_amr2_t of a coarse grid (nx, ny, nz) with the box [lo, hi) (coarse cells, x, y, z) refined by 2."""
+    g = Amr2()
+    g.nx, g.ny, g.nz = (int(v) for v in coarse_shape)
+    for d in range(3):
+        g.lo[d], g.hi[d] = int(lo[d]), int(hi[d])
+    return g
+
+
+def amr_pack(coarse, fine, comps=1):
+    """Two-level layout of one field: the coarse level's planes, then the fine level's (flat, contiguous)."""
+    torch = _torch()
+    assert coarse.numel() % comps == 0 and fine.numel() % comps == 0
+    return torch.cat([coarse.reshape(-1), fine.reshape(-1)]).contiguous()
+
+
+def amr_unpack(flat, geom: Amr2, comps=1):
+    """(coarse, fine) views of a two-level array: shapes (comps,) + (nz, ny, nx) and (comps,) + fine extents."""
+    nc = (geom.nz, geom.ny, geom.nx)
+    nf = tuple(2 * (geom.hi[d] - geom.lo[d]) for d in (2, 1, 0))
+    Nc = nc[0] * nc[1] * nc[2]
+    lead = (comps,) if comps > 1 else ()
+    return flat[:comps * Nc].reshape(lead + nc), flat[comps * Nc:].reshape(lead + nf)
+
+
+def workspace_bytes_amr2(geom: Amr2, p: Params) -> int:
+    return int(lib.rad_workspace_bytes_amr2(ct.byref(geom), ct.byref(p)))
+
+
+def rad_step_amr2(geom: Amr2, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace=None,
+                  stream=None, check=True):
+    """One implicit step on a two-level grid, in place on flat device tensors in the two-level
+    layout (amr_pack): E, T (N), F (3N) float64; rho, kappa_P, kappa_R (N), f (6N) of one float dtype,
+    N = coarse cells + fine cells.  dx: the coarse cell width.  Returns the stats dict."""
+    torch = _torch()
+    N = geom.nx * geom.ny * geom.nz + 8 * (geom.hi[0] - geom.lo[0]) * (geom.hi[1] - geom.lo[1]) * \
+        (geom.hi[2] - geom.lo[2])
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
+            _ptr(rho, cd, N, "rho"), _ptr(kappa_P, cd, N, "kappa_P"), _ptr(kappa_R, cd, N, "kappa_R"),
+            _ptr(f, cd, 6 * N, "f")]
+    if workspace is None:
+        need = workspace_bytes_amr2(geom, p)
+        if need == 0:   # invalid geometry or params: let the library name the reason
+            _check(lib.rad_step_amr2(ct.byref(geom), *args, float(dt), float(dx), bc_array(bc), ct.byref(p), None, 0,
+                                     None, None))
+        workspace = alloc_workspace(need, E.device)
+    st = Stats()
+    rc = lib.rad_step_amr2(ct.byref(geom), *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
+                           _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
+                           _stream(stream), ct.byref(st))
     if check:
         _check(rc)
     d = st.as_dict()

@@ -238,3 +238,47 @@ def thermal_coupling(rho, n=16, T0=100.0, Er0=7.567e-13, sigma_P=1.0, gamma=5.0 
                 rho=np.full(shape, rho), kP=np.full(shape, sigma_P / rho), kR=np.full(shape, sigma_P / rho),
                 f=f, dx=h, bc=("outflow", "periodic", "periodic"), c=C_LIGHT, aR=A_RAD, cv=cv,
                 t_therm=1.0 / (sigma_P * C_LIGHT), name=f"thermal_rho{rho:g}")
+
+
+def two_level(nc=(32, 32, 32), lo=(8, 8, 8), hi=(24, 24, 24), seed=6, sigma_rho=1.0, lg_tau=(-2.0, 2.0),
+              dt_cross=20.0, bc="periodic", fp32_exact=False):
+    """Two-level composite grid: the mixed-depth medium on a coarse grid (width h = 1/nx) with the
+    box [lo, hi) (coarse cells, x, y, z) refined by 2.  Fine cells inherit their parent's opacity
+    and tensor with sub-cell variation (density times a lognormal factor of sigma 0.3, tensor the
+    mean of the parent's and a fresh random SPD unit-trace one); E is the Gaussian source (peak
+    1e3, sigma 4 coarse cells) on an equilibrium background sampled at every cell centre, T = 0.1,
+    F = 0, dt = dt_cross h / c.  Arrays are returned per level as (coarse, fine) pairs."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = nc
+    sc = (nz, ny, nx)
+    nf = tuple(2 * (b - a) for a, b in zip(lo, hi))
+    sf = (nf[2], nf[1], nf[0])
+    h = 1.0 / nx
+    rho_c, kap_c = _mixed_depth(rng, sc, sigma_rho, lg_tau[0], lg_tau[1], h)
+    f_c = random_spd_unit_trace(rng, sc)
+    box = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    inj = lambda a: a.repeat(2, axis=-1).repeat(2, axis=-2).repeat(2, axis=-3)
+    rho_f = inj(rho_c[box]) * np.exp(0.3 * rng.standard_normal(sf))
+    kap_f = inj(kap_c[box])
+    f_f = 0.5 * (inj(f_c[(slice(None),) + box]) + random_spd_unit_trace(rng, sf))
+
+    def centres(n, a, w):
+        return (a + (np.arange(n) + 0.5) * w) - 0.5
+
+    def source(shape_xyz, org, w, T):
+        x, y, z = (centres(shape_xyz[d], org[d], w) for d in range(3))
+        r2 = z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2
+        s = 4.0 * h
+        return T ** 4 + 1e3 * np.exp(-r2 / (2.0 * s * s))
+
+    T_c, T_f = np.full(sc, 0.1), np.full(sf, 0.1)
+    E_c = source(nc, (0.0, 0.0, 0.0), h, T_c)
+    E_f = source(nf, tuple(lo[d] * h for d in range(3)), 0.5 * h, T_f)
+    d = dict(nc=tuple(nc), lo=tuple(lo), hi=tuple(hi), E=(E_c, E_f), F=(np.zeros((3,) + sc), np.zeros((3,) + sf)),
+             T=(T_c, T_f), rho=(rho_c, rho_f), kP=(kap_c.copy(), kap_f.copy()), kR=(kap_c, kap_f), f=(f_c, f_f),
+             dt=dt_cross * h, dx=h, bc=bc, c=1.0, aR=1.0, cv=1.0,
+             name=f"two_level_{bc}_{nx}x{ny}x{nz}_box{'-'.join(map(str, lo))}_{'-'.join(map(str, hi))}")
+    if fp32_exact:
+        for k in ("E", "F", "T", "rho", "kP", "kR", "f"):
+            d[k] = tuple(_f32(a) for a in d[k])
+    return d

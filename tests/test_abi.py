@@ -24,7 +24,7 @@ def _declared():
 
 def test_library_exports_every_declared_symbol(rad):
     names = _declared()
-    assert len(names) >= 13
+    assert len(names) >= 15
     for n in names:
         assert hasattr(rad.lib, n), n
         assert n in rad.EXPORTED, n
@@ -111,3 +111,23 @@ def test_other_entry_points_validate(rad):
                                      None, 1, None, None, None) == rad.RAD_EINVAL
     assert rad.lib.rad_autotune_step(0, 4, 4, 8, 8, 8, 8, 8, 8, 8, 1.0, 1.0, bc, ct.byref(p), 0x1000, 1 << 30,
                                      None, 1, None, None, None) == rad.RAD_EINVAL
+
+
+def test_amr2_geometry_is_validated_on_host(rad):
+    p = rad.params()
+    ws = lambda g: rad.lib.rad_workspace_bytes_amr2(ct.byref(g), ct.byref(p))
+    ok = rad.amr_geometry((8, 8, 8), (2, 2, 2), (6, 7, 6))
+    assert ws(ok) > rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(p))
+    assert ws(rad.amr_geometry((8, 8, 8), (0, 0, 0), (8, 8, 8))) > 0   # box spanning every axis
+    for lo, hi in [((0, 2, 2), (6, 6, 6)), ((2, 2, 2), (8, 6, 6)), ((3, 2, 2), (3, 6, 6)), ((2, 2, 2), (6, 6, 9)),
+                   ((-1, 2, 2), (6, 6, 6))]:
+        g = rad.amr_geometry((8, 8, 8), lo, hi)
+        assert ws(g) == 0, (lo, hi)
+        st = rad.Stats()
+        P = 0x1000
+        rc = rad.lib.rad_step_amr2(ct.byref(g), P, P, P, P, P, P, P, 1.0, 1.0, rad.bc_array("periodic"), ct.byref(p),
+                                   0x10000, 1 << 30, None, ct.byref(st))
+        assert rc == rad.RAD_EINVAL and "refined box" in rad.last_error(), (lo, hi, rad.last_error())
+    # an invalid params struct is caught before the geometry is used
+    bad = rad.params(gmres_m=0)
+    assert rad.lib.rad_workspace_bytes_amr2(ct.byref(ok), ct.byref(bad)) == 0
