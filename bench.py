@@ -157,15 +157,126 @@ def bench_batched(args, torch, np, rad, W):
     print(json.dumps(res), flush=True)
 
 
+def amr_cpu_baseline(tol):
+    """The composite oracle on a bounded two-level sample of the same recipe, one step, on the host cores."""
+    from oracle.amr import TwoLevel
+    from paper_2202_08778_amd import workloads as W
+    d = W.two_level((10, 10, 10), (3, 3, 3), (7, 7, 7), seed=6, fp32_exact=True)
+    pb = TwoLevel(d["nc"], d["lo"], d["hi"], d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"])
+    t0 = time.perf_counter()
+    _, _, _, st = pb.step(d["E"], d["F"], d["T"], tol=tol)
+    sec = time.perf_counter() - t0
+    leaf = pb.N - int(pb.covered.sum())
+    return {"value": leaf / sec, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"two-level recipe, coarse 10^3 with the box 3..7 refined (fine 8^3, {leaf} leaf cells), 1 step, "
+                      f"tol {tol:g}: {sec:.1f} s, {st['picard_iters']} Newton iterations with sparse direct solves "
+                      f"(numpy/scipy, one thread for the solves)"}
+
+
+def bench_amr(args, torch, np, rad, W):
+    """The two-level AMR grid: coarse n^3 with the central box [n/4, 3n/4)^3 refined by 2 (fine n^3), the
+    two-level recipe (lognormal density, optical depth 1e-2..1e2 per coarse cell, dt = 20 coarse crossings),
+    mixed precision, consecutive steps from the same initial state after the warm-up."""
+    from oracle.amr import TwoLevel
+    n = args.n or 256
+    q = n // 4
+    log(f"generating the two-level workload: coarse {n}^3, box [{q},{3 * q})^3 refined ...")
+    d = W.two_level((n, n, n), (q, q, q), (3 * q, 3 * q, 3 * q), seed=6, fp32_exact=True)
+    geom = rad.amr_geometry(d["nc"], d["lo"], d["hi"])
+    dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
+    pk = lambda k, dt=torch.float64: rad.amr_pack(dev(d[k][0], dt), dev(d[k][1], dt))
+    state0 = [pk("E"), pk("F"), pk("T")]
+    coefs = [pk(k, torch.float32) for k in ("rho", "kP", "kR", "f")]
+    Nc, Nf = n ** 3, (2 * q) ** 3 * 8
+    leaf = Nc - (2 * q) ** 3 + Nf
+    p = rad.params(prec="mixed", tol=args.tol, gmres_m=args.gmres_m, coef_dtype=1)
+    ws = rad.alloc_workspace(rad.workspace_bytes_amr2(geom, p))
+    E, F, T = (t.clone() for t in state0)
+    for s in range(args.warmup):
+        st = rad.rad_step_amr2(geom, E, F, T, *coefs, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
+        log(f"  [amr] warmup step {s}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
+            f"{st['t_total_ms']:.0f} ms, res {st['scaled_residual']:.2e}")
+    for dst, src in zip((E, F, T), state0):
+        dst.copy_(src)
+    rad.profile(not args.no_profile)
+    rad.profile_reset()
+    stats, prev = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        if s == args.steps - 1:
+            prev = [t.cpu().numpy() for t in (E, F, T)]
+        st = rad.rad_step_amr2(geom, E, F, T, *coefs, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
+        stats.append(st)
+        log(f"  [amr] step {s}: rc {st['rc']}, {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
+            f"{st['t_total_ms']:.0f} ms, res {st['scaled_residual']:.2e}")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    prof = rad.profile_read() if not args.no_profile else {}
+    rad.profile(False)
+    res = {"metric": "two-level AMR implicit VET rad-step cell-updates/s (leaf cells, mixed precision)",
+           "value": leaf * args.steps / sec, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1000.0 * sec / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"two-level grid: coarse {n}^3 periodic with the box [{q},{3 * q})^3 refined by 2 "
+                                  f"(fine {2 * q * 2}^3), lognormal sigma 1, optical depth 1e-2..1e2 per coarse cell, "
+                                  f"dt = 20 coarse crossings, FP32-exact inputs, {args.steps} steps, tol {args.tol:g}",
+                      "leaf_cells": leaf, "stored_cells": Nc + Nf, "gmres_m": p.gmres_m},
+           "krylov_iters_per_step": sum(s_["krylov_iters"] for s_ in stats) / args.steps,
+           "picard_iters_per_step": sum(s_["picard_iters"] for s_ in stats) / args.steps,
+           "converged_steps": sum(1 for s_ in stats if s_["rc"] == 0),
+           "final_scaled_residual": stats[-1]["scaled_residual"]}
+    if prof:
+        dom = max(prof, key=lambda k: prof[k]["ms"])
+        e = prof[dom]
+        gbs = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+        res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
+                           "avg_launch_us": 1000.0 * e["ms"] / e["launches"], "launches": e["launches"]}
+        tot_b = sum(v["bytes"] for v in prof.values())
+        res["step_roofline"] = {"achieved": tot_b / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": tot_b / sec / 1e9 / HBM_PEAK_GBS}
+        res["kernel_time_share"] = {k: v["ms"] / (sec * 1e3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+        res["kernel_gbs"] = {k: v["bytes"] / (v["ms"] * 1e-3) / 1e9 for k, v in prof.items() if v["ms"] > 0}
+    if not args.no_oracle_check:
+        log("composite oracle: residual of the last step on sampled leaf cells (jump cells included) ...")
+        pb = TwoLevel(d["nc"], d["lo"], d["hi"], d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"])
+        out = [t.cpu().numpy() for t in (E, F, T)]
+        rng = np.random.default_rng(0)
+        N = pb.N
+        # covered coarse cells are no part of the composite system: on output they hold the mean of their children
+        leaves = np.nonzero(~pb.covered)[0]
+        jumps = np.unique(np.concatenate([pb.fL[pb.fJ], pb.fR[pb.fJ]]))
+        cells = np.unique(np.concatenate([rng.choice(leaves, 4096, replace=False),
+                                          rng.choice(jumps, min(1024, jumps.size), replace=False)]))
+        Fp = np.concatenate([prev[1][:3 * Nc].reshape(3, Nc), prev[1][3 * Nc:].reshape(3, Nf)], axis=1) / d["c"]
+        Fo = np.concatenate([out[1][:3 * Nc].reshape(3, Nc), out[1][3 * Nc:].reshape(3, Nf)], axis=1) / d["c"]
+        R, Wt = pb.residual_at(cells, prev[0], Fp, prev[2], out[0], Fo, out[2])
+        c = cells
+        RT = np.where((out[2][c] == 0) & (R[4] > 0), 0.0, R[4])
+        WT = pb.alpha[c] + 4 * pb.sP[c] * pb.aR * out[2][c] ** 3
+        nE, nF, nT = np.linalg.norm(out[0][c]), np.linalg.norm(Fo[:, c]), np.linalg.norm(out[2][c])
+        res["oracle_scaled_residual_sampled"] = {
+            "E": float(np.linalg.norm(R[0] / Wt[0]) / nE), "F": float(np.linalg.norm(R[1:4] / Wt[1:4]) / (nF + nE)),
+            "T": float(np.linalg.norm(RT / WT) / nT), "cells": int(c.size), "jump_cells": int(np.isin(c, jumps).sum())}
+        del pb
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline (two-level sample) ...")
+        res["cpu_baseline"] = amr_cpu_baseline(args.tol)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None, help="grid edge (default 256; 512 for --workload scale)")
-    ap.add_argument("--workload", choices=("precision", "scale"), default="precision",
+    ap.add_argument("--workload", choices=("precision", "scale", "amr"), default="precision",
                     help="precision: mixed-depth 256^3 recipe (the metric's workload); scale: lognormal sigma 2, "
-                         "optical depth 1e-4..1e4, dt = 200 crossings (512^3, 3 steps)")
+                         "optical depth 1e-4..1e4, dt = 200 crossings (512^3, 3 steps); amr: two-level grid, "
+                         "coarse 256^3 with the central half-box refined")
     ap.add_argument("--batched", action="store_true",
                     help="instead: the batched path on 1024 AMR-like Dirichlet blocks (one graph replay per step)")
     ap.add_argument("--autotune", nargs="?", const="tiles", choices=("tiles", "all"), default=None,
@@ -197,6 +308,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batched:
         return bench_batched(args, torch, np, rad, W)
+    if args.workload == "amr":
+        return bench_amr(args, torch, np, rad, W)
     scale = args.workload == "scale"
     n = args.n or (512 if scale else 256)
     log(f"generating the {args.workload} workload at {n}^3 ...")

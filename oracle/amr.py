@@ -197,9 +197,10 @@ class TwoLevel:
         self.fWL, self.fWR, self.fJ = cc(WL, np.float64), cc(WR, np.float64), cc(JMP, bool)
         self.bA, self.bD, self.bS, self.bW = cc(BA, np.int64), cc(BD, np.int64), cc(BS, np.float64), cc(BW, np.float64)
 
-    def face_speeds(self):
-        """(C^L, C^R) of every face, divided by c."""
-        L, R, D = self.fL, self.fR, self.fD
+    def face_speeds(self, sel=None):
+        """(C^L, C^R) of every face (or of the faces sel), divided by c."""
+        sel = slice(None) if sel is None else sel
+        L, R, D, J = self.fL[sel], self.fR[sel], self.fD[sel], self.fJ[sel]
         sig = self.rho * self.kR
         fL, fR = self.f[D, L], self.f[D, R]
         tL = cell_tau(sig[L], self.h_cell[L], fL)
@@ -209,9 +210,8 @@ class TwoLevel:
         CL = root * mean
         CR = root * mean
         if self.jump_tau == "upstream":
-            j = self.fJ
-            CR = np.where(j, root * correction(tL), CR)   # right-going wave: tau of the left (upstream) cell
-            CL = np.where(j, root * correction(tR), CL)   # left-going wave: tau of the right cell
+            CR = np.where(J, root * correction(tL), CR)   # right-going wave: tau of the left (upstream) cell
+            CL = np.where(J, root * correction(tR), CL)   # left-going wave: tau of the right cell
         return CL, CR
 
     # ------------------------------------------------------------- operator
@@ -300,6 +300,45 @@ class TwoLevel:
         R[1:4] = Au[1:4] - Ftn
         R[4] = self.alpha * (T - Tn) + self.sP * (self.aR * T ** 4 - E)
         return R, A.diagonal().reshape(4, self.N)
+
+    def residual_at(self, cells, En, Ftn, Tn, E, Ft, T):
+        """Nonlinear residual rows (5, len(cells)) and their diagonal weights (4, len(cells)) at the
+        given composite cells, from the faces that touch them only (same fluxes as matrix())."""
+        cells = np.asarray(cells, np.int64)
+        pos = np.full(self.N, -1, np.int64)
+        pos[cells] = np.arange(cells.size)
+        sel = np.nonzero((pos[self.fL] >= 0) | (pos[self.fR] >= 0))[0]
+        CL, CR = self.face_speeds(sel)
+        S = CL + CR
+        safe = np.where(S > 0, S, 1.0)
+        aL, aR = np.where(S > 0, CR / safe, 0.5), np.where(S > 0, CL / safe, 0.5)
+        g = np.where(S > 0, CL * CR / safe, 0.0)
+        L, R, D = self.fL[sel], self.fR[sel], self.fD[sel]
+        div = np.zeros((4, cells.size))
+        W = np.zeros((4, cells.size))
+        phi = [aL * Ft[D, L] + aR * Ft[D, R] - g * (E[R] - E[L])]
+        for j in range(3):
+            t = np.array([_TENS[(int(d), j)] for d in range(3)])[D]
+            phi.append(aL * self.f[t, L] * E[L] + aR * self.f[t, R] * E[R] - g * (Ft[j, R] - Ft[j, L]))
+        for cell, w in ((L, self.fWL[sel]), (R, -self.fWR[sel])):
+            m = pos[cell] >= 0
+            for q in range(4):
+                np.add.at(div[q], pos[cell[m]], w[m] * phi[q][m])
+                np.add.at(W[q], pos[cell[m]], np.abs(w[m]) * g[m])
+        b = np.nonzero(pos[self.bA] >= 0)[0]
+        A_, Bd, sw = self.bA[b], self.bD[b], self.bS[b] * self.bW[b]
+        np.add.at(div[0], pos[A_], sw * Ft[Bd, A_])
+        for j in range(3):
+            t = np.array([_TENS[(int(d), j)] for d in range(3)])[Bd]
+            np.add.at(div[1 + j], pos[A_], sw * self.f[t, A_] * E[A_])
+        c = cells
+        R_ = np.empty((5, c.size))
+        R_[0] = (1.0 + self.sP[c]) * E[c] + div[0] - (En[c] + self.sP[c] * self.aR * T[c] ** 4)
+        R_[1:4] = (1.0 + self.sR[c]) * Ft[:, c] + div[1:4] - Ftn[:, c]
+        R_[4] = self.alpha[c] * (T[c] - Tn[c]) + self.sP[c] * (self.aR * T[c] ** 4 - E[c])
+        W[0] += 1.0 + self.sP[c]
+        W[1:4] += 1.0 + self.sR[c]
+        return R_, W
 
     def scaled_residual(self, En, Ftn, Tn, E, Ft, T):
         R, W = self.residual(En, Ftn, Tn, E, Ft, T)

@@ -305,3 +305,22 @@ def test_planted_mistake_fails_a_pin(cls):
         if failed[-1]:
             break
     assert any(failed), cls.__name__
+
+
+def test_sampled_residual_rows_equal_full_residual():
+    """residual_at (the rows a large grid is checked on) is the full residual restricted to those rows."""
+    rng = np.random.default_rng(9)
+    nc, lo, hi = (7, 6, 5), (2, 1, 0), (5, 4, 5)
+    c, fi = _fields(rng, nc), _fields(rng, _fine_shape(lo, hi))
+    pb = TwoLevel(nc, lo, hi, (c[0], fi[0]), (c[1], fi[1]), (c[1], fi[1]), (c[2], fi[2]), dt=0.7, dx=1 / 7,
+                  bc=("outflow", "outflow", "periodic", "periodic", "periodic", "periodic"))
+    st = [pb.pack(c[k], fi[k], 3 if k == 4 else 1) for k in (3, 4, 5)]
+    En, Ftn, Tn = st[0][0], st[1], st[2][0]
+    E = En * (1 + 0.05 * rng.standard_normal(pb.N))
+    Ft = Ftn + 0.05 * rng.standard_normal((3, pb.N))
+    T = Tn * (1 + 0.05 * rng.standard_normal(pb.N))
+    full, W = pb.residual(En, Ftn, Tn, E, Ft, T)
+    cells = rng.choice(pb.N, size=150, replace=False)
+    part, Wp = pb.residual_at(cells, En, Ftn, Tn, E, Ft, T)
+    assert np.max(np.abs(part - full[:, cells])) <= 1e-13 * np.max(np.abs(full))
+    assert np.max(np.abs(Wp - W[:, cells])) <= 1e-13 * np.max(np.abs(W))
