@@ -18,6 +18,8 @@
 
 #include "rad_device.h"
 
+#include <type_traits>
+
 namespace vr {
 
 // Refined box [lo, hi) in coarse cells; an axis that the box spans entirely
@@ -31,11 +33,12 @@ struct Amr {
 
 // Per-level view handed to a sweep: lev 0 coarse, 1 fine; corr points at this
 // level's block of the correction array (5 planes of the level's cell count:
-// the four transport corrections, then the change of the Jacobi diagonal).
+// the four transport corrections, then the change of the Jacobi diagonal), in
+// the sweep's arithmetic precision.
 struct AmrLv {
     Amr a;
     int lev;
-    const double *corr;
+    const void *corr;
 };
 
 enum { AMR_PLAIN = 0, AMR_COVERED = 1, AMR_JUMP = 2 };
@@ -104,11 +107,11 @@ namespace {
 // of either level block (E, Ft planes; FT the Krylov or the FP64 precision)
 // scaled by *xs when given; Cc the coarse level's stored low-face speeds of
 // the sweep whose coarse-coarse flux across a covered face is replaced.
-template <class XT, class CT, class FT>
+template <class XT, class CT, class FT, class OT>
 __global__ void __launch_bounds__(256)
     k_amr_jump(Amr a, Grid gc, Grid gf, long long nshell, long long ncoarse, const XT *__restrict__ x,
                const double *__restrict__ xs, const CT *__restrict__ f, const double *__restrict__ sR,
-               const FT *__restrict__ Cc, double *__restrict__ corr)
+               const FT *__restrict__ Cc, OT *__restrict__ corr)
 {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= nshell + ncoarse) return;
@@ -178,9 +181,9 @@ __global__ void __launch_bounds__(256)
             for (int q = 0; q < 4; ++q) acc[q] += sg * (phi[q] - self[q]);
         }
         if (any) {
-            double *cr = corr + 5 * Nc;
+            OT *cr = corr + 5 * Nc;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) cr[q * Nf + cf] = acc[q];
+            for (int q = 0; q < 5; ++q) cr[q * Nf + cf] = (OT)acc[q];
         }
         return;
     }
@@ -196,48 +199,59 @@ __global__ void __launch_bounds__(256)
         r -= 2 * layer;
     }
     if (d == 3) return;
-    const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
-    const bool box_above = r < layer;  // the coarse cell sits below the box (its high face is covered)
-    const long long q = box_above ? r : r - layer;
-    const int w1 = a.hi[e1] - a.lo[e1];
-    int pc[3];
-    pc[e1] = a.lo[e1] + (int)(q % w1);
-    pc[e2] = a.lo[e2] + (int)(q / w1);
-    pc[d] = box_above ? a.lo[d] - 1 : a.hi[d];
-    int pk[3] = {pc[0], pc[1], pc[2]};
-    pk[d] = box_above ? a.lo[d] : a.hi[d] - 1;   // the covered neighbour
-    const long long cc = cidx(pc[0], pc[1], pc[2]), ck = cidx(pk[0], pk[1], pk[2]);
-    JCell uc, uk;
-    load(xc, fc, sRc, Nc, cc, d, gc.tau_k, uc);
-    load(xc, fc, sRc, Nc, ck, d, gc.tau_k, uk);
-    double mean[4] = {0, 0, 0, 0}, gmean = 0;
-    for (int m = 0; m < 4; ++m) {
-        int p[3];
-        p[e1] = 2 * (pc[e1] - a.lo[e1]) + (m & 1);
-        p[e2] = 2 * (pc[e2] - a.lo[e2]) + (m >> 1);
-        p[d] = box_above ? 0 : a.nf[d] - 1;
-        JCell uf;
-        load(xf, ff, sRf, Nf, fidx(p[0], p[1], p[2]), d, gf.tau_k, uf);
-        double phi[4], gd;
-        if (box_above)
-            jump_flux(d, uc, uf, phi, gd);
-        else
-            jump_flux(d, uf, uc, phi, gd);
+    // one body per axis, so that every index below is a compile-time constant (no stack arrays)
+    auto coarse = [&](auto axis) {
+        constexpr int D = decltype(axis)::value, e1 = D == 0 ? 1 : 0, e2 = D == 2 ? 1 : 2;
+        const bool box_above = r < layer;  // the coarse cell sits below the box (its high face is covered)
+        const long long q = box_above ? r : r - layer;
+        const int w1 = a.hi[e1] - a.lo[e1];
+        int pc[3];
+        pc[e1] = a.lo[e1] + (int)(q % w1);
+        pc[e2] = a.lo[e2] + (int)(q / w1);
+        pc[D] = box_above ? a.lo[D] - 1 : a.hi[D];
+        int pk[3] = {pc[0], pc[1], pc[2]};
+        pk[D] = box_above ? a.lo[D] : a.hi[D] - 1;   // the covered neighbour
+        const long long cc = cidx(pc[0], pc[1], pc[2]), ck = cidx(pk[0], pk[1], pk[2]);
+        JCell uc, uk;
+        load(xc, fc, sRc, Nc, cc, D, gc.tau_k, uc);
+        load(xc, fc, sRc, Nc, ck, D, gc.tau_k, uk);
+        double mean[4] = {0, 0, 0, 0}, gmean = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) mean[k] += 0.25 * phi[k];
-        gmean += 0.25 * gd;
-    }
-    // the coarse sweep's flux across the covered face: uniform HLLE with its stored speed
-    const JCell &L = box_above ? uc : uk, &R = box_above ? uk : uc;
-    const double Cu = (double)Cc[d * Nc + (box_above ? ck : cc)];
-    double phic[4];
-    phic[0] = 0.5 * (L.F[d] + R.F[d]) - 0.5 * Cu * (R.E - L.E);
+        for (int m = 0; m < 4; ++m) {
+            int p[3];
+            p[e1] = 2 * (pc[e1] - a.lo[e1]) + (m & 1);
+            p[e2] = 2 * (pc[e2] - a.lo[e2]) + (m >> 1);
+            p[D] = box_above ? 0 : a.nf[D] - 1;
+            JCell uf;
+            load(xf, ff, sRf, Nf, fidx(p[0], p[1], p[2]), D, gf.tau_k, uf);
+            double phi[4], gd;
+            if (box_above)
+                jump_flux(D, uc, uf, phi, gd);
+            else
+                jump_flux(D, uf, uc, phi, gd);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) phic[1 + k] = 0.5 * (L.fr[k] * L.E + R.fr[k] * R.E) - 0.5 * Cu * (R.F[k] - L.F[k]);
-    const double sg = box_above ? gc.nu : -gc.nu;
+            for (int k = 0; k < 4; ++k) mean[k] += 0.25 * phi[k];
+            gmean += 0.25 * gd;
+        }
+        // the coarse sweep's flux across the covered face: uniform HLLE with its stored speed
+        const JCell &L = box_above ? uc : uk, &R = box_above ? uk : uc;
+        const double Cu = (double)Cc[D * Nc + (box_above ? ck : cc)];
+        double phic[4];
+        phic[0] = 0.5 * (L.F[D] + R.F[D]) - 0.5 * Cu * (R.E - L.E);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) corr[k * Nc + cc] = sg * (mean[k] - phic[k]);
-    corr[4 * Nc + cc] = gc.nu * (gmean - 0.5 * Cu);
+        for (int k = 0; k < 3; ++k)
+            phic[1 + k] = 0.5 * (L.fr[k] * L.E + R.fr[k] * R.E) - 0.5 * Cu * (R.F[k] - L.F[k]);
+        const double sg = box_above ? gc.nu : -gc.nu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) corr[k * Nc + cc] = (OT)(sg * (mean[k] - phic[k]));
+        corr[4 * Nc + cc] = (OT)(gc.nu * (gmean - 0.5 * Cu));
+    };
+    if (d == 0)
+        coarse(std::integral_constant<int, 0>{});
+    else if (d == 1)
+        coarse(std::integral_constant<int, 1>{});
+    else
+        coarse(std::integral_constant<int, 2>{});
 }
 
 // Covered coarse cells := mean of their eight children (E, F, T), after the commit.

@@ -120,8 +120,8 @@ struct CellSums {
 
 // The sweep.  PRE: sR and the low-face speeds Cf (divided by c, planes x|y|z)
 // are precomputed; otherwise both are derived from rho, kR and f per face.
-// lex(pb, o, e) loads the NE per-cell extras of the epilogue (plane base pb,
-// in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell.
+// lex(k, pb, o, e) loads the NE per-cell extras of the epilogue (plane k, its
+// base pb, in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell.
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
 template <class AT, class ST, bool PRE, bool CALL, int NE, class LEX, class EPI>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
@@ -351,7 +351,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         for (int c = 0; c < CPT; ++c) put(b, ly + TYT * c + 1, lx + 1, S[c]);
         if (hly >= 0) put(b, hly, hlx, H);
         if constexpr (NE > 0)
-            for (int c = 0; c < CPT; ++c) lex(plane * k, off[c], ex[c]);
+            for (int c = 0; c < CPT; ++c) lex(k, plane * k, off[c], ex[c]);
         if constexpr (decltype(LOAD)::value) {
             const int kp = mapz(k + 1 + DEPTH);
             for (int c = 0; c < CPT; ++c) load_full(kp, off[c], S[c]);
@@ -392,7 +392,10 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // the Picard iteration) or y = A x with flux rescaling xF/yF (!PRE: the
 // physical operator of one Picard iteration with E diagonal dE).
 // AMR: one level of the two-level composite grid -- covered coarse cells keep
-// only their local terms, jump cells add their level-jump corrections.
+// only their local terms, jump cells add their level-jump corrections (5
+// planes of the apply precision: transport of E and Ft, then the change of the
+// Jacobi diagonal), loaded with the epilogue's other extras ahead of the
+// plane's prefetch so that waiting for them leaves the prefetch in flight.
 template <class AT, class ST, bool PRE, bool AMR = false>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
@@ -404,8 +407,22 @@ __global__ void __launch_bounds__(tile_threads<AT>())
     const long long N = g.N;
     const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
     const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
-    auto lex = [&](long long pb, unsigned o, AT(&e)[1]) __attribute__((always_inline)) { e[0] = ld_off(dE + pb, o); };
-    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[1])
+    constexpr int NEX = AMR ? 6 : 1;
+    const AT *corr = (const AT *)al.corr;
+    auto lex = [&](int k, long long pb, unsigned o, AT(&e)[NEX]) __attribute__((always_inline)) {
+        e[0] = ld_off(dE + pb, o);
+        if constexpr (AMR) {
+            const int jj = (int)(o / (unsigned)g.nx), ii = (int)(o - (unsigned)jj * (unsigned)g.nx);
+            if (amr_role(al, ii, jj, k) == AMR_JUMP) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) e[1 + q] = corr[q * N + pb + o];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) e[1 + q] = AT(0);
+            }
+        }
+    };
+    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[NEX])
                    __attribute__((always_inline)) {
         const long long pb = (long long)g.nx * g.ny * k;
         const AT dEc = e[0];
@@ -419,11 +436,10 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                 yE = dEc * S.Ec;
                 for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + S.sc) * S.Fc[q];
                 dtr = AT(0);
-            } else if (role == AMR_JUMP) {
-                const long long c = pb + o;
-                yE += (AT)al.corr[c];
-                for (int q = 0; q < 3; ++q) yFq[q] += (AT)al.corr[(1 + q) * N + c];
-                dtr += (AT)al.corr[4 * N + c];
+            } else {   // zero except at jump cells
+                yE += e[1];
+                for (int q = 0; q < 3; ++q) yFq[q] += e[2 + q];
+                dtr += e[5];
             }
         }
         if constexpr (PRE) {
@@ -436,7 +452,7 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, o, yFq[q] * yF);
         }
     };
-    tile_sweep<AT, ST, PRE, false, 1>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi);
+    tile_sweep<AT, ST, PRE, false, NEX>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(tile_threads<double>())
     const long long plane = (long long)g.nx * g.ny;
     const double invc = 1.0 / g.c, nu = g.nu, half = 0.5 * g.nu, aR = g.aR, cdt = g.cdt, cv = g.cv;
     double acc[5] = {0, 0, 0, 0, 0};
-    auto lex = [&](long long pb, unsigned o, double(&e)[8]) __attribute__((always_inline)) {
+    auto lex = [&](int, long long pb, unsigned o, double(&e)[8]) __attribute__((always_inline)) {
         e[0] = ld_off(En + pb, o);
         for (int q = 0; q < 3; ++q) e[1 + q] = ld_off(Fn + q * N + pb, o);
         e[4] = ld_off(Tn + pb, o);
@@ -196,9 +196,10 @@ __global__ void __launch_bounds__(tile_threads<double>())
                 dtr = 0.0;
             } else if (role == AMR_JUMP) {
                 const long long c = pb + o;
-                divE += al.corr[c];
-                for (int q = 0; q < 3; ++q) divF[q] += al.corr[(1 + q) * N + c];
-                dtr += al.corr[4 * N + c];
+                const double *corr = (const double *)al.corr;
+                divE += corr[c];
+                for (int q = 0; q < 3; ++q) divF[q] += corr[(1 + q) * N + c];
+                dtr += corr[4 * N + c];
             }
         }
         const double rE = bE - (dE * E + divE);
@@ -638,7 +639,7 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, V, W, part, small, total;
+    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, V, W, part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
@@ -653,7 +654,8 @@ long long tile_bound(int nx, int ny, int nz)
 }
 
 // part_rows: partial-sum rows the sweeps of every level need (tile_bound summed);
-// amr: room for the level-jump corrections (5 FP64 planes over the composite grid).
+// amr: room for the level-jump corrections (5 planes over the composite grid, FP64 for the
+// residual and in the Krylov precision for the apply).
 Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false)
 {
     Layout L;
@@ -684,6 +686,7 @@ Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr 
     L.AAG = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
     L.AAf = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
     L.AMRC = take(amr ? 5 * N * 8 : 0);
+    L.AMRCA = take(amr ? 5 * N * ksz : 0);   // the same corrections in the Krylov precision, for the apply
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
     // per-cell kernels of a two-level grid use one more (partial) block than the cell count gives
@@ -841,25 +844,27 @@ int run_step(Solver &S)
         });
     // two-level grid: level-jump corrections of the operand x (scaled by *xs), read by the sweeps' epilogues
     double *corr = S.amr ? S.at<double>(S.L.AMRC) : nullptr;
-    auto level_view = [&](int l) {
+    AT *corrA = S.amr ? S.at<AT>(S.L.AMRCA) : nullptr;
+    auto level_view = [&](int l, const void *cbase, size_t esz) {
         AmrLv v;
         v.a = S.A;
         v.lev = l;
-        v.corr = corr ? corr + 5 * S.c0[l] : nullptr;
+        v.corr = cbase ? (const char *)cbase + esz * 5 * S.c0[l] : nullptr;
         return v;
     };
-    auto jump = [&](auto x, const double *xs, auto Cc) {
+    auto jump = [&](auto x, const double *xs, auto Cc, auto out) {
         using XT = std::remove_const_t<std::remove_pointer_t<decltype(x)>>;
         using FT = std::remove_const_t<std::remove_pointer_t<decltype(Cc)>>;
+        using OT = std::remove_pointer_t<decltype(out)>;
         const long long nt = S.nshell + S.ncoarse;
         S.timed(K_AMR, (double)nt * 10 * 8 * sizeof(XT), [&] {
-            hipLaunchKernelGGL((k_amr_jump<XT, CT, FT>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, S.st, S.A,
-                               S.gl[0], S.gl[1], S.nshell, S.ncoarse, (const XT *)x, xs, f, (const double *)sR64,
-                               (const FT *)Cc, corr);
+            hipLaunchKernelGGL((k_amr_jump<XT, CT, FT, OT>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, S.st,
+                               S.A, S.gl[0], S.gl[1], S.nshell, S.ncoarse, (const XT *)x, xs, f,
+                               (const double *)sR64, (const FT *)Cc, out);
         });
     };
     auto apply = [&](const KT *x, const double *xs, KT *y) {
-        if (S.amr) jump(x, xs, (const AT *)Cf);
+        if (S.amr) jump(x, xs, (const AT *)Cf, corrA);
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
             const long long o = S.c0[l];
@@ -869,12 +874,12 @@ int run_step(Solver &S)
                     hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM>), tiles(tg[l]), bt, 0, S.st, S.gl[l], tg[l],
                                        (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr, (const AT *)nullptr,
                                        (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l));
+                                       level_view(l, corrA, sizeof(AT)));
                 else
                     hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM>), tiles(tg[l]), bt, 0, S.st, S.gl[l], tg[l],
                                        f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
                                        (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l));
+                                       level_view(l, corrA, sizeof(AT)));
             };
             if (S.amr)
                 go(std::true_type{});
@@ -887,7 +892,7 @@ int run_step(Solver &S)
     // its norm's inverse becomes the scale s_0 of V[0].
     double nrm[5];
     auto residual = [&]() -> int {
-        if (S.amr) jump((const double *)X, (const double *)nullptr, (const double *)Cf64);
+        if (S.amr) jump((const double *)X, (const double *)nullptr, (const double *)Cf64, corr);
         // streams X, En/Fn/Tn/Ts, sR and face speeds (FP64), f, rho, kP; writes V[0], dE
         long long rrows = 0;
         S.timed(K_RESIDUAL, Nd * (32 + 48 + 32 + 8 * cb + 5 * kb), [&] {
@@ -898,7 +903,7 @@ int run_step(Solver &S)
                     hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT, AM>), tiles(tgr[l]), bt64, 0, S.st, S.gl[l],
                                        tgr[l], p.mode, S.En + o, S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o,
                                        f + 6 * o, sR64 + o, Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o,
-                                       part + rrows * 5, level_view(l));
+                                       part + rrows * 5, level_view(l, corr, sizeof(double)));
                 };
                 if (S.amr)
                     go(std::true_type{});
