@@ -43,7 +43,7 @@ class _Grid(ct.Structure):
 
 class _Coef(ct.Structure):
     _fields_ = [("rho", ct.c_void_p), ("kP", ct.c_void_p), ("kR", ct.c_void_p),
-                ("f", ct.c_void_p * 6)]
+                ("f", ct.c_void_p * 6), ("beta", ct.c_void_p * 3), ("vel_implicit", ct.c_int)]
 
 
 class _Params(ct.Structure):
@@ -117,11 +117,15 @@ def _interior(a):
 class Problem:
     """Grid, constants and coefficient fields of one implicit step (padded internally)."""
 
-    def __init__(self, rho, kP, kR, f, dt, dx, bc="periodic", c=1.0, aR=1.0, cv=1.0, padded=False):
+    def __init__(self, rho, kP, kR, f, dt, dx, bc="periodic", c=1.0, aR=1.0, cv=1.0, padded=False, beta=None,
+                 vel_implicit=False):
+        """beta: gas velocity over c, shape (3,) + field shape (None: v = 0); vel_implicit: the O(v/c)
+        gas-energy term implicit (else left to the explicit hydro update, the paper's default)."""
         self.padded = padded
         P = (lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64))) if padded else _pad
         self.rho, self.kP, self.kR = P(rho), P(kP), P(kR)
         self.f = P(f)
+        self.beta = None if beta is None else P(beta)
         nzp, nyp, nxp = self.rho.shape
         self.shape = (nzp - 2, nyp - 2, nxp - 2)
         g = _Grid()
@@ -132,12 +136,15 @@ class Problem:
         self.g = g
         self.c, self.aR, self.cv, self.dt, self.dx = float(c), float(aR), float(cv), float(dt), float(dx)
         L = lib()
-        for a in (self.rho, self.kP, self.kR, *self.f):
+        for a in (self.rho, self.kP, self.kR, *self.f, *(self.beta if self.beta is not None else ())):
             L.or_fill_ghosts(ct.byref(g), a.ctypes.data)
         cf = _Coef()
         cf.rho, cf.kP, cf.kR = self.rho.ctypes.data, self.kP.ctypes.data, self.kR.ctypes.data
         for q in range(6):
             cf.f[q] = self.f[q].ctypes.data
+        for q in range(3):
+            cf.beta[q] = None if self.beta is None else self.beta[q].ctypes.data
+        cf.vel_implicit = 1 if vel_implicit else 0
         self.cf = cf
 
     # padded state helpers -------------------------------------------------

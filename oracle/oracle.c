@@ -108,6 +108,39 @@ static double s_P(const or_grid *g, const or_coef *cf, size_t i) { return g->c *
 static double s_R(const or_grid *g, const or_coef *cf, size_t i) { return g->c * g->dt * sigma_R(cf, i); }
 static double alpha_of(const or_grid *g, const or_coef *cf, size_t i) { return cf->rho[i] * g->cv; }
 
+/* ------------------------------------------------------ velocity (O(v/c)) terms */
+
+/* With beta = v/c, kappa_E = kappa_P and kappa_F = kappa_R, dt times the O(v/c)
+ * parts of the four-force (eq. G and the G0 of the radiation energy equation):
+ *   energy row:  (sR - 2 sP) beta.F / c + (sP - sR) (beta.beta + beta.f.beta) E
+ *   flux row j: -sR c E (beta_j + (f beta)_j)
+ * X (the first) is also the O(v/c) energy the gas receives (eq. G0explicit). */
+static int has_velocity(const or_coef *cf) { return cf->beta[0] != NULL; }
+
+static void vel_vectors(const or_coef *cf, size_t i, double b[3], double fb[3])
+{
+    for (int a = 0; a < 3; ++a) b[a] = cf->beta[a][i];
+    for (int a = 0; a < 3; ++a) {
+        fb[a] = 0.0;
+        for (int k = 0; k < 3; ++k) fb[a] += cf->f[tens(a, k)][i] * b[k];
+    }
+}
+
+/* the energy-row term X at cell i for the state (E, F) */
+static double vel_energy(const or_grid *g, const or_coef *cf, size_t i, double E, const double F[3])
+{
+    double b[3], fb[3];
+    vel_vectors(cf, i, b, fb);
+    double bF = 0.0, bb = 0.0, bfb = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        bF += b[a] * F[a];
+        bb += b[a] * b[a];
+        bfb += b[a] * fb[a];
+    }
+    double sP = g->c * g->dt * cf->rho[i] * cf->kP[i], sR = g->c * g->dt * cf->rho[i] * cf->kR[i];
+    return (sR - 2.0 * sP) * bF / g->c + (sP - sR) * (bb + bfb) * E;
+}
+
 /* Optical-depth parameter of the wave-speed correction for one cell and one
  * direction (eq. taucorrect): tau = (10 dl rho kappa_R)^2 / (2 f), dl = h.
  * A cell with no opacity has tau = 0; a cell with zero diagonal Eddington
@@ -208,6 +241,12 @@ static void transport_apply(const or_grid *g, const or_coef *cf, const double *c
                     double diag = (q == 0) ? dE[c] : 1.0 + sR;
                     y[q][c] = diag * x[q][c] + lam * div;
                 }
+                if (has_velocity(cf)) {
+                    double b[3], fb[3], Fc[3] = {x[1][c], x[2][c], x[3][c]};
+                    vel_vectors(cf, c, b, fb);
+                    y[0][c] += vel_energy(g, cf, c, x[0][c], Fc);
+                    for (int q = 0; q < 3; ++q) y[1 + q][c] -= sR * g->c * x[0][c] * (b[q] + fb[q]);
+                }
             }
 
     for (int d = 0; d < 3; ++d)
@@ -253,6 +292,10 @@ void or_residual(const or_grid *g, const or_coef *cf, const double *En, double *
                 R[0][c] += -En[c] - sP * g->aR * T4;
                 for (int q = 0; q < 3; ++q) R[1 + q][c] -= Fn[q][c];
                 R[4][c] = alpha_of(g, cf, c) * (T[c] - Tn[c]) + sP * (g->aR * T4 - E[c]);
+                if (has_velocity(cf) && cf->vel_implicit) {
+                    double Fc[3] = {F[0][c], F[1][c], F[2][c]};
+                    R[4][c] -= vel_energy(g, cf, c, E[c], Fc);   /* the gas receives the O(v/c) energy */
+                }
             }
     free(dE);
 }
@@ -532,6 +575,12 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                     size_t c = idx(g, i, j, kk);
                     double sP = s_P(g, cf, c), a = alpha_of(g, cf, c);
                     double Ts = Tstar[c], Ts3 = Ts * Ts * Ts, Ts4 = Ts3 * Ts;
+                    /* implicit O(v/c) gas energy, taken at the current iterate (lagged) */
+                    double Xs = 0.0;
+                    if (has_velocity(cf) && cf->vel_implicit) {
+                        double Fc[3] = {F[0][c], F[1][c], F[2][c]};
+                        Xs = vel_energy(g, cf, c, E[c], Fc);
+                    }
                     if (p->mode == OR_LAGGED) {
                         o.dE[c] = 1.0 + sP;
                         bE[c] = En[c] + sP * g->aR * Ts4;
@@ -540,7 +589,7 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                         double den = a + 4.0 * sP * g->aR * Ts3;
                         double eta = den > 0 ? 4.0 * sP * g->aR * Ts3 / den : 0.0;
                         o.dE[c] = 1.0 + sP * (1.0 - eta);
-                        bE[c] = En[c] + eta * a * Tn[c] - 3.0 * (1.0 - eta) * sP * g->aR * Ts4;
+                        bE[c] = En[c] + eta * (a * Tn[c] + Xs) - 3.0 * (1.0 - eta) * sP * g->aR * Ts4;
                     }
                 }
         /* Jacobi scaling of this system */
@@ -598,7 +647,17 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                 for (int i = 0; i < g->nx; ++i) {
                     size_t c = idx(g, i, j, kk);
                     int flag = 0;
-                    T[c] = or_exchange_T(alpha_of(g, cf, c), Tn[c], s_P(g, cf, c), g->aR, E[c], &flag);
+                    double a = alpha_of(g, cf, c), sP = s_P(g, cf, c), Tb = Tn[c], Eb = E[c];
+                    if (has_velocity(cf) && cf->vel_implicit) {
+                        /* alpha (T - Tn) + sP (aR T^4 - E) = X: shift Tn (or E without heat capacity) */
+                        double Fc[3] = {F[0][c], F[1][c], F[2][c]};
+                        double X = vel_energy(g, cf, c, E[c], Fc);
+                        if (a > 0)
+                            Tb += X / a;
+                        else if (sP > 0)
+                            Eb += X / sP;
+                    }
+                    T[c] = or_exchange_T(a, Tb, sP, g->aR, Eb, &flag);
                     neg |= flag;
                 }
         st->neg_cells = neg;

@@ -51,10 +51,17 @@ typedef struct {
     int bc[6];     /* faces -x,+x,-y,+y,-z,+z */
 } or_grid;
 
-/* Padded input fields (see header comment). f holds xx,yy,zz,xy,xz,yz. */
+/* Padded input fields (see header comment). f holds xx,yy,zz,xy,xz,yz.
+ * beta: the gas velocity over c, three padded planes, or NULL (v = 0).  With a
+ * velocity the O(v/c) terms of G0 and G (eq. G, kappa_E = kappa_P and
+ * kappa_F = kappa_R) enter the radiation rows; vel_implicit = 1 also moves the
+ * O(v/c) part of cG0 into the gas energy row (the implicit alternative of
+ * eq. G0explicit), 0 leaves it to the explicit hydro update (the default). */
 typedef struct {
     const double *rho, *kP, *kR;
     const double *f[6];
+    const double *beta[3];
+    int vel_implicit;
 } or_coef;
 
 typedef struct {

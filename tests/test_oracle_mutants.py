@@ -1,6 +1,6 @@
 """Plants plausible mistakes in a copy of the oracle source (on the CPU) and checks that the
 oracle pins catch every one: a dropped or doubled term, a wrong sign, a wrong tensor index,
-a wrong ghost source, a missing direction.  Each mutant is compiled with gcc into a temporary
+a wrong ghost source, a missing direction, the O(v/c) terms.  Each mutant is compiled with gcc into a temporary
 directory and the pin module is run against it in a child process."""
 import os
 import subprocess
@@ -41,6 +41,15 @@ MUTANTS = [
     ("g = Fm / (c * E[i]);", "g = Fm / E[i];"),
     ("fxy = beam * nx * ny;", "fxy = beam * nx * nz;"),
     ("double fxx = 1.0 / 3.0, fyy = 1.0 / 3.0,", "double fxx = 1.0 / 3.0, fyy = 0.3,"),
+    # O(v/c) terms
+    ("y[1 + q][c] -= sR * g->c * x[0][c] * (b[q] + fb[q]);", "y[1 + q][c] -= sR * g->c * x[0][c] * fb[q];"),
+    ("y[1 + q][c] -= sR * g->c * x[0][c] * (b[q] + fb[q]);", "y[1 + q][c] += sR * g->c * x[0][c] * (b[q] + fb[q]);"),
+    ("return (sR - 2.0 * sP) * bF / g->c", "return (sR - sP) * bF / g->c"),
+    ("(sP - sR) * (bb + bfb) * E;", "(sP - sR) * bb * E;"),
+    ("R[4][c] -= vel_energy(g, cf, c, E[c], Fc);", "R[4][c] += vel_energy(g, cf, c, E[c], Fc);"),
+    ("bE[c] = En[c] + eta * (a * Tn[c] + Xs)", "bE[c] = En[c] + eta * (a * Tn[c])"),
+    ("Tb += X / a;", "Tb -= X / a;"),
+    ("fb[a] += cf->f[tens(a, k)][i] * b[k];", "fb[a] += cf->f[tens(a, a)][i] * b[k];"),
 ]
 
 
@@ -58,6 +67,7 @@ def test_pins_catch_planted_mistake(k, tmp_path):
     env = dict(os.environ, VETTAM_ORACLE_SO=str(so), OMP_NUM_THREADS="2")
     # a mutant that stalls the solver is caught by the per-test time limit (the pins take ~5 s)
     r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_velocity_pins.py"),
                         "-x", "-q", "-p", "no:cacheprovider", "--timeout", "20"], env=env, capture_output=True,
                        text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"mutant survived: {after}"
