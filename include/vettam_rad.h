@@ -77,6 +77,9 @@ typedef struct {
                              T_* -> T(E(T_*)) with this many past iterates (the acceleration the
                              paper names for its linearly convergent Picard iteration, Sec. 4.3).
                              Single-grid rad_step only; the batched plan requires 0. */
+    int vel_implicit;     /* rad_step_moving only: 1 moves the O(v/c) part of the gas-radiation
+                             energy exchange into the implicit gas energy row (the paper's runtime
+                             switch, Sec. 2.3.2); 0 (default) leaves it to the explicit hydro update */
 } rad_params_t;
 
 typedef struct {
@@ -96,7 +99,7 @@ typedef struct {
 
 /* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
  * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients,
- * anderson_m 0. */
+ * anderson_m 0, vel_implicit 0. */
 void rad_default_params(rad_params_t *p);
 
 /* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */
@@ -111,6 +114,24 @@ int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
              const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
              double dt, double dx, const int bc[6], const rad_params_t *p,
              void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
+
+/* ------------------------------------------------------- moving medium
+ * rad_step with a gas velocity: the O(v/c) terms of the radiation four-force
+ * (eq. G and G0, with kappa_E = kappa_P and kappa_F = kappa_R) enter the
+ * implicit radiation rows -- with beta = v/c, sP = c dt rho kappa_P and
+ * sR = c dt rho kappa_R, dt times
+ *   energy row:  (sR - 2 sP) beta.F / c + (sP - sR) (beta.beta + beta.f.beta) E
+ *   flux row:    -sR c E (beta + f beta)
+ * -- and, with params->vel_implicit = 1, the first of them also into the gas
+ * energy row (eq. G0explicit moved to the implicit subsystem).  beta: three
+ * planes [bx|by|bz] of coef_dtype, device memory, the velocity held fixed
+ * over the step (Sec. 2.3.2).  Other arguments as rad_step.  Errors as
+ * rad_step; anderson_m must be 0 with vel_implicit = 1. */
+size_t rad_workspace_bytes_moving(int nx, int ny, int nz, const rad_params_t *p);
+int rad_step_moving(int nx, int ny, int nz, double *E, double *F, double *T_gas,
+                    const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
+                    const void *beta, double dt, double dx, const int bc[6], const rad_params_t *p,
+                    void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
 
 /* ---------------------------------------------------- two-level AMR grid
  * A coarse grid (nx, ny, nz) of cell width dx with one box [lo, hi) of its

@@ -206,9 +206,10 @@ static void hlle_flux(const or_grid *g, const or_coef *cf, double *const x[4], i
 }
 
 /* y = diag * x + (dt/h) * sum_d (Phi_{i+1/2} - Phi_{i-1/2});  ghosts of x as given.
- * Face fluxes are formed once per face and then differenced. */
+ * Face fluxes are formed once per face and then differenced.  With a velocity
+ * the O(v/c) terms are added, those of the energy row times vscale (NULL: 1). */
 static void transport_apply(const or_grid *g, const or_coef *cf, const double *const C[3],
-                            const double *dE, double *const x[4], double *const y[4])
+                            const double *dE, double *const x[4], double *const y[4], const double *vscale)
 {
     size_t np = padded_size(g);
     double lam = g->dt / g->h;
@@ -244,7 +245,7 @@ static void transport_apply(const or_grid *g, const or_coef *cf, const double *c
                 if (has_velocity(cf)) {
                     double b[3], fb[3], Fc[3] = {x[1][c], x[2][c], x[3][c]};
                     vel_vectors(cf, c, b, fb);
-                    y[0][c] += vel_energy(g, cf, c, x[0][c], Fc);
+                    y[0][c] += (vscale ? vscale[c] : 1.0) * vel_energy(g, cf, c, x[0][c], Fc);
                     for (int q = 0; q < 3; ++q) y[1 + q][c] -= sR * g->c * x[0][c] * (b[q] + fb[q]);
                 }
             }
@@ -263,7 +264,7 @@ void or_apply(const or_grid *g, const or_coef *cf, const double *dE, double *con
 {
     double *C[3];
     all_face_speeds(g, cf, C);
-    transport_apply(g, cf, (const double *const *)C, dE, x, y);
+    transport_apply(g, cf, (const double *const *)C, dE, x, y, NULL);
     for (int d = 0; d < 3; ++d) free(C[d]);
 }
 
@@ -390,6 +391,7 @@ typedef struct {
     const or_coef *cf;
     double *C[3];
     double *dE;      /* E-row diagonal of the current linear system */
+    double *vscale;  /* factor of the energy row's O(v/c) terms in the linear system (NULL: 1) */
     double *pre[2];  /* Jacobi scaling: 1/D_E, 1/D_F */
     double *px[4], *py[4];
     size_t N;
@@ -442,7 +444,7 @@ static void lin_apply_prec(lin_ctx *o, const double *v, double *out)
     unpack(o, u, o->px);
     free(u);
     for (int q = 0; q < 4; ++q) fill_ghosts_linear(o->g, o->px[q]);
-    transport_apply(o->g, o->cf, (const double *const *)o->C, o->dE, o->px, o->py);
+    transport_apply(o->g, o->cf, (const double *const *)o->C, o->dE, o->px, o->py, o->vscale);
     pack(o, o->py, out);
     to_scaled(o, out);
     for (size_t n = 0; n < 4 * o->N; ++n) out[n] *= o->pre[n < o->N ? 0 : 1][n % o->N];
@@ -550,6 +552,9 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
     o.N = N;
     all_face_speeds(g, cf, o.C);
     o.dE = alloc_padded(g);
+    /* implicit O(v/c) gas energy with the linearised emission: eliminating the gas energy
+     * leaves the fraction 1 - eta of the energy row's O(v/c) terms (Newton-consistent) */
+    o.vscale = (has_velocity(cf) && cf->vel_implicit && p->mode != OR_LAGGED) ? alloc_padded(g) : NULL;
     for (int q = 0; q < 4; ++q) { o.px[q] = alloc_padded(g); o.py[q] = alloc_padded(g); }
     o.pre[0] = (double *)malloc(N * sizeof(double));
     o.pre[1] = (double *)malloc(N * sizeof(double));
@@ -575,12 +580,6 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                     size_t c = idx(g, i, j, kk);
                     double sP = s_P(g, cf, c), a = alpha_of(g, cf, c);
                     double Ts = Tstar[c], Ts3 = Ts * Ts * Ts, Ts4 = Ts3 * Ts;
-                    /* implicit O(v/c) gas energy, taken at the current iterate (lagged) */
-                    double Xs = 0.0;
-                    if (has_velocity(cf) && cf->vel_implicit) {
-                        double Fc[3] = {F[0][c], F[1][c], F[2][c]};
-                        Xs = vel_energy(g, cf, c, E[c], Fc);
-                    }
                     if (p->mode == OR_LAGGED) {
                         o.dE[c] = 1.0 + sP;
                         bE[c] = En[c] + sP * g->aR * Ts4;
@@ -589,7 +588,8 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                         double den = a + 4.0 * sP * g->aR * Ts3;
                         double eta = den > 0 ? 4.0 * sP * g->aR * Ts3 / den : 0.0;
                         o.dE[c] = 1.0 + sP * (1.0 - eta);
-                        bE[c] = En[c] + eta * (a * Tn[c] + Xs) - 3.0 * (1.0 - eta) * sP * g->aR * Ts4;
+                        bE[c] = En[c] + eta * a * Tn[c] - 3.0 * (1.0 - eta) * sP * g->aR * Ts4;
+                        if (o.vscale) o.vscale[c] = 1.0 - eta;
                     }
                 }
         /* Jacobi scaling of this system */
@@ -607,7 +607,7 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
         }
         /* residual of the linear system at the current iterate (Dirichlet data in ghosts) */
         for (int q = 0; q < 4; ++q) or_fill_ghosts(g, x[q]);
-        transport_apply(g, cf, (const double *const *)o.C, o.dE, x, y);
+        transport_apply(g, cf, (const double *const *)o.C, o.dE, x, y, o.vscale);
         {
             size_t n = 0;
             for (int kk = 0; kk < g->nz; ++kk)
@@ -707,6 +707,7 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
     for (int q = 0; q < 4; ++q) { free(o.px[q]); free(o.py[q]); free(y[q]); }
     for (int d = 0; d < 3; ++d) free(o.C[d]);
     free(o.dE); free(o.pre[0]); free(o.pre[1]);
+    free(o.vscale);
     return st->converged ? 0 : 1;
 }
 

@@ -396,18 +396,22 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // planes of the apply precision: transport of E and Ft, then the change of the
 // Jacobi diagonal), loaded with the epilogue's other extras ahead of the
 // plane's prefetch so that waiting for them leaves the prefetch in flight.
-template <class AT, class ST, bool PRE, bool AMR = false>
+// VEL (moving medium): the O(v/c) couplings of the energy row to Ft (vb, 3
+// planes) and of the flux rows to E (vc, 3 planes); the energy row's own
+// O(v/c) term is part of dE.
+template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
-                  AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{})
+                  AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{}, const AT *__restrict__ vb = nullptr,
+                  const AT *__restrict__ vc = nullptr)
 {
     __shared__ AT lds[2][Rec<PRE>::NL][TileShape<AT>::LY][kLX];
     const long long N = g.N;
     const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
     const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
-    constexpr int NEX = AMR ? 6 : 1;
+    constexpr int NEX = AMR ? 6 : (VEL ? 7 : 1);
     const AT *corr = (const AT *)al.corr;
     auto lex = [&](int k, long long pb, unsigned o, AT(&e)[NEX]) __attribute__((always_inline)) {
         e[0] = ld_off(dE + pb, o);
@@ -421,6 +425,12 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                 for (int q = 0; q < 5; ++q) e[1 + q] = AT(0);
             }
         }
+        if constexpr (VEL) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) e[1 + q] = ld_off(vb + q * N + pb, o);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) e[4 + q] = ld_off(vc + q * N + pb, o);
+        }
     };
     auto epi = [&](int k, int, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[NEX])
                    __attribute__((always_inline)) {
@@ -429,6 +439,12 @@ __global__ void __launch_bounds__(tile_threads<AT>())
         AT yE = dEc * S.Ec + nu * S.dEs, yFq[3];
         for (int q = 0; q < 3; ++q) yFq[q] = (AT(1) + S.sc) * S.Fc[q] + nu * S.dF[q];
         AT dtr = half * S.sumC_nb;   // transport part of the Jacobi diagonal
+        if constexpr (VEL) {
+            for (int q = 0; q < 3; ++q) {
+                yE += e[1 + q] * S.Fc[q];
+                yFq[q] += e[4 + q] * S.Ec;
+            }
+        }
         if constexpr (AMR) {
             const int jj = (int)(o / (unsigned)g.nx), ii = (int)(o - (unsigned)jj * (unsigned)g.nx);
             const int role = amr_role(al, ii, jj, k);

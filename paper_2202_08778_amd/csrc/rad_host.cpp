@@ -56,6 +56,7 @@ int check_params(const rad_params_t *p)
         return fail(RAD_EINVAL, "unknown coefficient dtype %d", p->coef_dtype);
     if (p->anderson_m < 0 || p->anderson_m > kMaxAnderson)
         return fail(RAD_EINVAL, "anderson_m must be in [0, %d]", kMaxAnderson);
+    if (p->vel_implicit != 0 && p->vel_implicit != 1) return fail(RAD_EINVAL, "vel_implicit must be 0 or 1");
     return RAD_OK;
 }
 
@@ -188,6 +189,7 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->mode = RAD_PICARD_LINEARISED;
     p->coef_dtype = RAD_F64;
     p->anderson_m = 0;
+    p->vel_implicit = 0;
 }
 
 // ------------------------------------------------------------------ autotune cache

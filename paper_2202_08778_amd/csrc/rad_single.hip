@@ -148,28 +148,41 @@ __global__ void __launch_bounds__(kBlock)
 // (the same values k_residual derives per face).  Partial sums per tile.
 // AMR: one level of the two-level composite grid (covered coarse cells keep
 // their local terms only, jump cells add their level-jump corrections).
-template <class CT, class KT, class DT, bool AMR = false>
+// VEL (moving medium): 1 adds the O(v/c) terms (coefficients VA, VB, VC of
+// k_vel_coef) to the radiation rows; 2 (implicit switch) with the linearised
+// emission keeps the fraction 1 - eta of the energy row's O(v/c) terms (the gas
+// energy eliminated, as for the emission) and writes that row's coupling to Ft
+// for the Krylov apply (vbw).
+template <class CT, class KT, class DT, bool AMR = false, int VEL = 0>
 __global__ void __launch_bounds__(tile_threads<double>())
     k_residual_tiled(Grid g, TileGeom tg, int picard_mode, const double *__restrict__ En,
                      const double *__restrict__ Fn, const double *__restrict__ Tn, const double *__restrict__ Ts,
                      const CT *__restrict__ rho, const CT *__restrict__ kP, const CT *__restrict__ f,
                      const double *__restrict__ sR64, const double *__restrict__ Cf64, const double *__restrict__ X,
-                     KT *__restrict__ out, DT *__restrict__ dEA, double *partials, AmrLv al = AmrLv{})
+                     KT *__restrict__ out, DT *__restrict__ dEA, double *partials, AmrLv al = AmrLv{},
+                     const double *__restrict__ VA = nullptr, const double *__restrict__ VB = nullptr,
+                     const double *__restrict__ VC = nullptr, DT *__restrict__ vbw = nullptr)
 {
     __shared__ double lds[2][Rec<true>::NL][TileShape<double>::LY][kLX];
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
     const double invc = 1.0 / g.c, nu = g.nu, half = 0.5 * g.nu, aR = g.aR, cdt = g.cdt, cv = g.cv;
     double acc[5] = {0, 0, 0, 0, 0};
-    auto lex = [&](int, long long pb, unsigned o, double(&e)[8]) __attribute__((always_inline)) {
+    constexpr int NEX = 8 + (VEL ? 7 : 0);
+    auto lex = [&](int, long long pb, unsigned o, double(&e)[NEX]) __attribute__((always_inline)) {
         e[0] = ld_off(En + pb, o);
         for (int q = 0; q < 3; ++q) e[1 + q] = ld_off(Fn + q * N + pb, o);
         e[4] = ld_off(Tn + pb, o);
         e[5] = ld_off(Ts + pb, o);
         e[6] = (double)ld_off(rho + pb, o);
         e[7] = (double)ld_off(kP + pb, o);
+        if constexpr (VEL) {
+            e[8] = ld_off(VA + pb, o);
+            for (int q = 0; q < 3; ++q) e[9 + q] = ld_off(VB + q * N + pb, o);
+            for (int q = 0; q < 3; ++q) e[12 + q] = ld_off(VC + q * N + pb, o);
+        }
     };
-    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<double> &S, const double(&e)[8])
+    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<double> &S, const double(&e)[NEX])
                    __attribute__((always_inline)) {
         const long long pb = plane * k;
         const double r_ = e[6];
@@ -187,6 +200,16 @@ __global__ void __launch_bounds__(tile_threads<double>())
         }
         const double E = S.Ec;
         double divE = nu * S.dEs, divF[3] = {nu * S.dF[0], nu * S.dF[1], nu * S.dF[2]};
+        double vf = 1.0;   // factor of the energy row's O(v/c) terms
+        if constexpr (VEL) {   // O(v/c) terms: local couplings, the E one joins the diagonal
+            if constexpr (VEL == 2)
+                if (picard_mode != 0) vf = 1.0 - 4.0 * sP * aR * T3 / fmax(alpha + 4.0 * sP * aR * T3, 1e-300);
+            dE += vf * e[8];
+            for (int q = 0; q < 3; ++q) {
+                divE += vf * e[9 + q] * S.Fc[q];
+                divF[q] += e[12 + q] * E;
+            }
+        }
         double dtr = half * S.sumC_nb;   // transport part of the Jacobi diagonal
         if constexpr (AMR) {
             const int jj = (int)(o / (unsigned)g.nx), ii = (int)(o - (unsigned)jj * (unsigned)g.nx);
@@ -218,6 +241,8 @@ __global__ void __launch_bounds__(tile_threads<double>())
             st_off(out + pb, o, (KT)zE);
             for (int q = 0; q < 3; ++q) st_off(out + (1 + q) * N + pb, o, (KT)zF[q]);
             st_off(dEA + pb, o, (DT)dE);
+            if constexpr (VEL == 2)
+                for (int q = 0; q < 3; ++q) st_off(vbw + q * N + pb, o, (DT)(vf * e[9 + q]));
             acc[0] += (rE / WE) * (rE / WE);
             acc[1] += wf;
             acc[2] += E * E;
@@ -225,8 +250,8 @@ __global__ void __launch_bounds__(tile_threads<double>())
             acc[4] += zz;
         }
     };
-    tile_sweep<double, CT, true, true, 8>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64, X, 1.0,
-                                          1.0, lds, lex, epi);
+    tile_sweep<double, CT, true, true, NEX>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64, X, 1.0,
+                                            1.0, lds, lex, epi);
     block_store<5, tile_threads<double>()>(acc, partials, blockIdx.x);
 }
 
@@ -340,11 +365,14 @@ __global__ void __launch_bounds__(kBlock)
 // Per-cell exchange solve (eq. PicardTemp) for T with E = X_E; then the
 // diagnostics of the Picard iteration, and X0 = X.  Partials:
 //   [sum (R_T/W_T)^2, sum T^2, sum dT^2, sum dE^2, sum E^2, sum dFt^2, sum Ft^2, neg]
-template <class CT>
+// VI (moving medium, implicit switch): the gas also receives the O(v/c) energy
+// X = VA E + VB.Ft of the new state.
+template <class CT, bool VI = false>
 __global__ void __launch_bounds__(kBlock)
     k_exchange(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP, const double *__restrict__ Tn,
                double *__restrict__ Tc, double *__restrict__ X, double *__restrict__ X0, double *partials,
-               double *__restrict__ Gk, double *__restrict__ fk)
+               double *__restrict__ Gk, double *__restrict__ fk, const double *__restrict__ VA = nullptr,
+               const double *__restrict__ VB = nullptr)
 {
     const long long N = g.N;
     long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -354,10 +382,20 @@ __global__ void __launch_bounds__(kBlock)
         const double sP = g.cdt * r_ * (double)kP[c], alpha = r_ * g.cv, aR = g.aR;
         const double E = X[c];
         bool neg = false;
-        const double T = exchange_T(alpha, Tn[c], sP, aR, E, neg);
+        double Xv = 0.0, Tb = Tn[c], Eb = E;
+        if constexpr (VI) {
+            Xv = VA[c] * E;
+            for (int q = 0; q < 3; ++q) Xv += VB[q * N + c] * X[(1 + q) * N + c];
+            // alpha (T - Tn) + sP (aR T^4 - E) = X: shift T_n (or E without heat capacity)
+            if (alpha > 0)
+                Tb += Xv / alpha;
+            else if (sP > 0)
+                Eb += Xv / sP;
+        }
+        const double T = exchange_T(alpha, Tb, sP, aR, Eb, neg);
         const double T3 = T * T * T;
         // where no non-negative root exists T = 0 is the active bound (R_T > 0 there)
-        const double RT0 = alpha * (T - Tn[c]) + sP * (aR * T3 * T - E);
+        const double RT0 = alpha * (T - Tn[c]) + sP * (aR * T3 * T - E) - Xv;
         const double RT = (T == 0.0 && RT0 > 0.0) ? 0.0 : RT0;
         const double WT = alpha + 4.0 * sP * aR * T3;
         const double dT = T - Tc[c];
@@ -382,6 +420,50 @@ __global__ void __launch_bounds__(kBlock)
         v[7] = neg ? 1.0 : 0.0;
     }
     block_store<8>(v, partials, blockIdx.x);
+}
+
+// Moving medium, once per step: the O(v/c) coefficients of eq. G and G0 with
+// beta = v/c (kappa_E = kappa_P, kappa_F = kappa_R), in FP64 and, for the
+// Krylov apply, copies in its precision:
+//   VA = (sP - sR)(b.b + b.f.b)   energy row, on E (joins the E diagonal)
+//   VB = (sR - 2 sP) b            energy row, on Ft
+//   VC = -sR (b + f b)            flux rows, on E
+// Counts non-finite beta.
+template <class CT, class AT>
+__global__ void __launch_bounds__(kBlock)
+    k_vel_coef(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP, const CT *__restrict__ kR,
+               const CT *__restrict__ f, const CT *__restrict__ beta, double *__restrict__ VA,
+               double *__restrict__ VB, double *__restrict__ VC, AT *__restrict__ VBA, AT *__restrict__ VCA,
+               double *partials)
+{
+    const long long N = g.N;
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0};
+    if (c < N) {
+        const double r_ = (double)rho[c];
+        const double sP = g.cdt * r_ * (double)kP[c], sR = g.cdt * r_ * (double)kR[c];
+        double b[3], fb[3], bb = 0, bfb = 0;
+        for (int q = 0; q < 3; ++q) b[q] = (double)beta[q * N + c];
+        for (int a = 0; a < 3; ++a) {
+            fb[a] = 0;
+            for (int k = 0; k < 3; ++k) fb[a] += (double)f[tens_row(a, k) * N + c] * b[k];
+        }
+        for (int q = 0; q < 3; ++q) {
+            bb += b[q] * b[q];
+            bfb += b[q] * fb[q];
+        }
+        v[0] = (isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2])) ? 0.0 : 1.0;
+        const double va = (sP - sR) * (bb + bfb);
+        VA[c] = va;
+        for (int q = 0; q < 3; ++q) {
+            const double vb = (sR - 2.0 * sP) * b[q], vc = -sR * (b[q] + fb[q]);
+            VB[q * N + c] = vb;
+            VC[q * N + c] = vc;
+            VBA[q * N + c] = (AT)vb;
+            VCA[q * N + c] = (AT)vc;
+        }
+    }
+    block_store<1>(v, partials, blockIdx.x);
 }
 
 // Anderson acceleration of the Picard map T_* -> G(T_*) = T(E(T_*)) (the
@@ -639,7 +721,8 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, V, W, part, small, total;
+    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, part, small,
+        total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
@@ -655,8 +738,9 @@ long long tile_bound(int nx, int ny, int nz)
 
 // part_rows: partial-sum rows the sweeps of every level need (tile_bound summed);
 // amr: room for the level-jump corrections (5 planes over the composite grid, FP64 for the
-// residual and in the Krylov precision for the apply).
-Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false)
+// residual and in the Krylov precision for the apply); vel: the O(v/c) coefficients of a
+// moving medium (7 FP64 planes, the 6 couplings again in the Krylov precision for the apply).
+Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false, bool vel = false)
 {
     Layout L;
     const bool mixed = p.prec == RAD_MIXED;
@@ -687,6 +771,11 @@ Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr 
     L.AAf = take(ma > 0 ? (size_t)(ma + 1) * N * 8 : 0);
     L.AMRC = take(amr ? 5 * N * 8 : 0);
     L.AMRCA = take(amr ? 5 * N * ksz : 0);   // the same corrections in the Krylov precision, for the apply
+    L.VA = take(vel ? N * 8 : 0);
+    L.VB = take(vel ? 3 * N * 8 : 0);
+    L.VC = take(vel ? 3 * N * 8 : 0);
+    L.VBA = take(vel ? 3 * N * ksz : 0);
+    L.VCA = take(vel ? 3 * N * ksz : 0);
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
     // per-cell kernels of a two-level grid use one more (partial) block than the cell count gives
@@ -718,6 +807,7 @@ struct Solver {
     Amr A{};
     long long nshell = 0, ncoarse = 0;  // threads of the level-jump kernel
     long long Ntot = 0;                 // cells of all levels
+    const void *beta = nullptr;         // moving medium: v / c (3 planes, coefficient type), else null
     rad_params_t p;
     hipStream_t st;
     char *ws;
@@ -842,6 +932,24 @@ int run_step(Solver &S)
                                    f + 6 * o, Cf64 + 3 * o);
             }
         });
+    // moving medium: the O(v/c) coefficients, once per step
+    const bool vel = S.beta != nullptr;
+    const int vimp = vel && p.vel_implicit;
+    double *VA = vel ? S.at<double>(S.L.VA) : nullptr, *VB = vel ? S.at<double>(S.L.VB) : nullptr;
+    double *VC = vel ? S.at<double>(S.L.VC) : nullptr;
+    AT *VBA = vel ? S.at<AT>(S.L.VBA) : nullptr, *VCA = vel ? S.at<AT>(S.L.VCA) : nullptr;
+    if (vel) {
+        S.timed(K_SETUP, Nd * (12 * cb + 56 + 6 * kb), [&] {
+            hipLaunchKernelGGL((k_vel_coef<CT, AT>), cell_grid(0), bl, 0, S.st, g, rho, kP, kR, f, (const CT *)S.beta,
+                               VA, VB, VC, VBA, VCA, part);
+        });
+        S.reduce(cell_grid(0).x, 1, 1, sm + SM_RED);
+        RAD_TRY(S.read(SM_RED, 1));
+        if (h[SM_RED] > 0) {
+            st.bad_cells = (int)h[SM_RED];
+            return fail(RAD_EDATA, "%d cells with non-finite velocity", st.bad_cells);
+        }
+    }
     // two-level grid: level-jump corrections of the operand x (scaled by *xs), read by the sweeps' epilogues
     double *corr = S.amr ? S.at<double>(S.L.AMRC) : nullptr;
     AT *corrA = S.amr ? S.at<AT>(S.L.AMRCA) : nullptr;
@@ -868,23 +976,26 @@ int run_step(Solver &S)
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
             const long long o = S.c0[l];
-            auto go = [&](auto amr_c) {
-                constexpr bool AM = decltype(amr_c)::value;
+            auto go = [&](auto amr_c, auto vel_c) {
+                constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value;
                 if (fA)
-                    hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM>), tiles(tg[l]), bt, 0, S.st, S.gl[l], tg[l],
-                                       (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr, (const AT *)nullptr,
-                                       (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l, corrA, sizeof(AT)));
+                    hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
+                                       tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
+                                       (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
+                                       y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)), (const AT *)VBA,
+                                       (const AT *)VCA);
                 else
-                    hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM>), tiles(tg[l]), bt, 0, S.st, S.gl[l], tg[l],
-                                       f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
+                    hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
+                                       tg[l], f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
                                        (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l, corrA, sizeof(AT)));
+                                       level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA);
             };
             if (S.amr)
-                go(std::true_type{});
+                go(std::true_type{}, std::false_type{});
+            else if (vel)
+                go(std::false_type{}, std::true_type{});
             else
-                go(std::false_type{});
+                go(std::false_type{}, std::false_type{});
         }
         prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
     };
@@ -898,17 +1009,23 @@ int run_step(Solver &S)
         S.timed(K_RESIDUAL, Nd * (32 + 48 + 32 + 8 * cb + 5 * kb), [&] {
             for (int l = 0; l < NL; ++l) {
                 const long long o = S.c0[l];
-                auto go = [&](auto amr_c) {
+                auto go = [&](auto amr_c, auto vel_c) {
                     constexpr bool AM = decltype(amr_c)::value;
-                    hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT, AM>), tiles(tgr[l]), bt64, 0, S.st, S.gl[l],
+                    constexpr int VL = decltype(vel_c)::value;
+                    hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT, AM, VL>), tiles(tgr[l]), bt64, 0, S.st, S.gl[l],
                                        tgr[l], p.mode, S.En + o, S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o,
                                        f + 6 * o, sR64 + o, Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o,
-                                       part + rrows * 5, level_view(l, corr, sizeof(double)));
+                                       part + rrows * 5, level_view(l, corr, sizeof(double)), (const double *)VA,
+                                       (const double *)VB, (const double *)VC, VBA);
                 };
                 if (S.amr)
-                    go(std::true_type{});
+                    go(std::true_type{}, std::integral_constant<int, 0>{});
+                else if (vimp)
+                    go(std::false_type{}, std::integral_constant<int, 2>{});
+                else if (vel)
+                    go(std::false_type{}, std::integral_constant<int, 1>{});
                 else
-                    go(std::false_type{});
+                    go(std::false_type{}, std::integral_constant<int, 0>{});
                 rrows += tiles(tgr[l]).x;
             }
         });
@@ -1092,9 +1209,14 @@ int run_step(Solver &S)
         S.timed(K_EXCHANGE, Nd * (2 * cb + 16 + 64 + 40 + (aa_m > 0 ? 16 : 0)), [&] {
             for (int l = 0; l < NL; ++l) {
                 const long long o = S.c0[l];
-                hipLaunchKernelGGL((k_exchange<CT>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kP + o, S.Tn + o,
-                                   Tc + o, X + 4 * o, X0 + 4 * o, part + xrows * 8, Gk ? Gk + o : nullptr,
-                                   fk ? fk + o : nullptr);
+                if (vimp)   // one level: moving media run on the single grid only
+                    hipLaunchKernelGGL((k_exchange<CT, true>), cell_grid(l), bl, 0, S.st, S.gl[l], rho, kP, S.Tn, Tc,
+                                       X, X0, part, Gk, fk, (const double *)VA, (const double *)VB);
+                else
+                    hipLaunchKernelGGL((k_exchange<CT>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kP + o,
+                                       S.Tn + o, Tc + o, X + 4 * o, X0 + 4 * o, part + xrows * 8,
+                                       Gk ? Gk + o : nullptr, fk ? fk + o : nullptr, (const double *)nullptr,
+                                       (const double *)nullptr);
                 xrows += cell_grid(l).x;
             }
         });
@@ -1304,6 +1426,43 @@ extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_
                         stream));
     int rc;
     try {  // small host vectors of the GMRES least-squares problem
+        rc = dispatch_step(S);
+    } catch (const std::bad_alloc &) {
+        rc = fail(RAD_ENOMEM, "host memory");
+    }
+    S.stats.status = rc;
+    S.stats.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S.stats;
+    return rc;
+}
+
+extern "C" size_t rad_workspace_bytes_moving(int nx, int ny, int nz, const rad_params_t *p)
+{
+    if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
+    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, true).total;
+}
+
+extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                               const void *kappa_P, const void *kappa_R, const void *f_ij, const void *beta, double dt,
+                               double dx, const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes,
+                               void *stream, rad_stats_t *stats)
+{
+    clear_error();
+    auto t0 = std::chrono::steady_clock::now();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Solver S;
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    if (!beta) return fail(RAD_EINVAL, "beta (velocity) is NULL");
+    if (p->vel_implicit && p->anderson_m > 0)
+        return fail(RAD_EINVAL, "anderson_m must be 0 with vel_implicit = 1");
+    RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace,
+                        (size_t)-1, stream));
+    S.L = layout(S.Ntot, *p, tile_bound(nx, ny, nz), false, true);
+    if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
+    S.beta = beta;
+    S.kz_apply = S.kz_res = 0;   // the velocity variants are not in the autotune cache
+    int rc;
+    try {
         rc = dispatch_step(S);
     } catch (const std::bad_alloc &) {
         rc = fail(RAD_ENOMEM, "host memory");

@@ -25,7 +25,7 @@ class Params(ct.Structure):
     _fields_ = [("c", ct.c_double), ("a_R", ct.c_double), ("c_v", ct.c_double), ("tol", ct.c_double),
                 ("eps_R", ct.c_double), ("eps_P", ct.c_double), ("max_picard", ct.c_int),
                 ("max_krylov", ct.c_int), ("gmres_m", ct.c_int), ("prec", ct.c_int), ("mode", ct.c_int),
-                ("coef_dtype", ct.c_int), ("anderson_m", ct.c_int)]
+                ("coef_dtype", ct.c_int), ("anderson_m", ct.c_int), ("vel_implicit", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -66,6 +66,10 @@ def _load():
     L.rad_workspace_bytes.restype = SZ
     L.rad_step.argtypes = [I, I, I, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
     L.rad_step.restype = I
+    L.rad_workspace_bytes_moving.argtypes = [I, I, I, PP]
+    L.rad_workspace_bytes_moving.restype = SZ
+    L.rad_step_moving.argtypes = [I, I, I, P, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
+    L.rad_step_moving.restype = I
     L.rad_workspace_bytes_amr2.argtypes = [ct.POINTER(Amr2), PP]
     L.rad_workspace_bytes_amr2.restype = SZ
     L.rad_step_amr2.argtypes = [ct.POINTER(Amr2), P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
@@ -112,7 +116,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_workspace_bytes_amr2", "rad_step_amr2",
+EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_workspace_bytes_moving", "rad_step_moving",
+            "rad_workspace_bytes_amr2", "rad_step_amr2",
             "rad_autotune_step", "rad_residual",
             "rad_face_speeds",
             "rad_apply", "rad_exchange", "rad_closure", "rad_batched_workspace_bytes", "rad_plan_batched",
@@ -223,6 +228,32 @@ def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace
     rc = lib.rad_step(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
                       _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
                       _stream(stream), ct.byref(st))
+    if check:
+        _check(rc)
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def rad_step_moving(E, F, T, rho, kappa_P, kappa_R, f, beta, dt, dx, bc, p: Params, workspace=None, stream=None,
+                    check=True):
+    """rad_step in a moving medium: beta = v/c as a (3, nz, ny, nx) tensor of the coefficients' dtype
+    (held fixed over the step); p.vel_implicit selects the implicit O(v/c) gas-energy term."""
+    torch = _torch()
+    nz, ny, nx = E.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
+            _ptr(rho, cd, N, "rho"), _ptr(kappa_P, cd, N, "kappa_P"), _ptr(kappa_R, cd, N, "kappa_R"),
+            _ptr(f, cd, 6 * N, "f"), _ptr(beta, cd, 3 * N, "beta")]
+    if workspace is None:
+        workspace = alloc_workspace(int(lib.rad_workspace_bytes_moving(nx, ny, nz, ct.byref(p))), E.device)
+    st = Stats()
+    rc = lib.rad_step_moving(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
+                             _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
+                             _stream(stream), ct.byref(st))
     if check:
         _check(rc)
     d = st.as_dict()

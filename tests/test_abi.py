@@ -24,7 +24,7 @@ def _declared():
 
 def test_library_exports_every_declared_symbol(rad):
     names = _declared()
-    assert len(names) >= 15
+    assert len(names) >= 17
     for n in names:
         assert hasattr(rad.lib, n), n
         assert n in rad.EXPORTED, n
@@ -34,6 +34,7 @@ def test_defaults(rad):
     p = rad.params()
     assert (p.c, p.a_R, p.c_v) == (1.0, 1.0, 1.0)
     assert p.gmres_m == 12 and p.prec == 0 and p.mode == 1 and p.eps_R == 1e-2 and p.anderson_m == 0
+    assert p.vel_implicit == 0
 
 
 def _step(rad, p, nx=4, ny=4, nz=4, ptr=0x1000, bc="periodic", dt=1.0, dx=1.0, ws=None, wsb=None):
@@ -131,3 +132,17 @@ def test_amr2_geometry_is_validated_on_host(rad):
     # an invalid params struct is caught before the geometry is used
     bad = rad.params(gmres_m=0)
     assert rad.lib.rad_workspace_bytes_amr2(ct.byref(ok), ct.byref(bad)) == 0
+
+
+def test_moving_step_is_validated_on_host(rad):
+    p = rad.params()
+    base = rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(p))
+    assert rad.lib.rad_workspace_bytes_moving(8, 8, 8, ct.byref(p)) > base
+    assert rad.lib.rad_workspace_bytes_moving(8, 8, 8, ct.byref(rad.params(vel_implicit=2))) == 0
+    P, st = 0x1000, rad.Stats()
+    call = lambda q, beta: rad.lib.rad_step_moving(8, 8, 8, P, P, P, P, P, P, P, beta, 1.0, 1.0,
+                                                   rad.bc_array("periodic"), ct.byref(q), 0x10000, 1 << 30, None,
+                                                   ct.byref(st))
+    assert call(p, None) == rad.RAD_EINVAL and "beta" in rad.last_error()
+    assert call(rad.params(vel_implicit=1, anderson_m=2), P) == rad.RAD_EINVAL and "anderson" in rad.last_error()
+    assert call(rad.params(vel_implicit=3), P) == rad.RAD_EINVAL

@@ -47,7 +47,7 @@ MUTANTS = [
     ("return (sR - 2.0 * sP) * bF / g->c", "return (sR - sP) * bF / g->c"),
     ("(sP - sR) * (bb + bfb) * E;", "(sP - sR) * bb * E;"),
     ("R[4][c] -= vel_energy(g, cf, c, E[c], Fc);", "R[4][c] += vel_energy(g, cf, c, E[c], Fc);"),
-    ("bE[c] = En[c] + eta * (a * Tn[c] + Xs)", "bE[c] = En[c] + eta * (a * Tn[c])"),
+    ("if (o.vscale) o.vscale[c] = 1.0 - eta;", "if (o.vscale) o.vscale[c] = 1.0;"),
     ("Tb += X / a;", "Tb -= X / a;"),
     ("fb[a] += cf->f[tens(a, k)][i] * b[k];", "fb[a] += cf->f[tens(a, a)][i] * b[k];"),
 ]
