@@ -84,7 +84,7 @@ def measured_traffic(kernel_class):
         return None
     rec = json.load(open(path))
     src = b"".join(open(os.path.join(ROOT, "paper_2202_08778_amd", "csrc", f), "rb").read()
-                   for f in ("rad_single.hip", "rad_device.h", "rad_apply_tiled.h"))
+                   for f in ("rad_single.hip", "rad_device.h", "rad_apply_tiled.h", "rad_amr.h"))
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
     k = rec.get("classes", {}).get(kernel_class)
