@@ -38,7 +38,7 @@ def build() -> str:
 class _Grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
                 ("h", ct.c_double), ("dt", ct.c_double), ("c", ct.c_double),
-                ("aR", ct.c_double), ("cv", ct.c_double), ("bc", ct.c_int * 6)]
+                ("aR", ct.c_double), ("cv", ct.c_double), ("bc", ct.c_int * 6), ("cv_cubic", ct.c_int)]
 
 
 class _Coef(ct.Structure):
@@ -118,9 +118,10 @@ class Problem:
     """Grid, constants and coefficient fields of one implicit step (padded internally)."""
 
     def __init__(self, rho, kP, kR, f, dt, dx, bc="periodic", c=1.0, aR=1.0, cv=1.0, padded=False, beta=None,
-                 vel_implicit=False):
+                 vel_implicit=False, cv_cubic=False):
         """beta: gas velocity over c, shape (3,) + field shape (None: v = 0); vel_implicit: the O(v/c)
-        gas-energy term implicit (else left to the explicit hydro update, the paper's default)."""
+        gas-energy term implicit (else left to the explicit hydro update, the paper's default);
+        cv_cubic: heat capacity rho cv T^3 (E_int = rho cv T^4 / 4) instead of rho cv."""
         self.padded = padded
         P = (lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64))) if padded else _pad
         self.rho, self.kP, self.kR = P(rho), P(kP), P(kR)
@@ -133,6 +134,7 @@ class Problem:
         g.h, g.dt, g.c, g.aR, g.cv = float(dx), float(dt), float(c), float(aR), float(cv)
         for i, code in enumerate(_bc_codes(bc)):
             g.bc[i] = code
+        g.cv_cubic = 1 if cv_cubic else 0
         self.g = g
         self.c, self.aR, self.cv, self.dt, self.dx = float(c), float(aR), float(cv), float(dt), float(dx)
         L = lib()

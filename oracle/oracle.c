@@ -108,6 +108,28 @@ static double s_P(const or_grid *g, const or_coef *cf, size_t i) { return g->c *
 static double s_R(const or_grid *g, const or_coef *cf, size_t i) { return g->c * g->dt * sigma_R(cf, i); }
 static double alpha_of(const or_grid *g, const or_coef *cf, size_t i) { return cf->rho[i] * g->cv; }
 
+/* gas internal energy and heat capacity: alpha T and alpha, or (Sec. 3.4, the Marshak-wave
+ * gas) C_v = alpha T^3 with E_int = alpha T^4 / 4 */
+static double gas_e(const or_grid *g, double alpha, double T)
+{
+    return g->cv_cubic ? 0.25 * alpha * T * T * T * T : alpha * T;
+}
+static double gas_C(const or_grid *g, double alpha, double T) { return g->cv_cubic ? alpha * T * T * T : alpha; }
+
+/* the exchange row with the cubic gas is linear in T^4:
+ *   (alpha/4 + sP aR) T^4 = alpha Tn^4 / 4 + sP E + X */
+static double exchange_T4(double alpha, double Tn, double sP, double aR, double E, double X, int *neg)
+{
+    double den = 0.25 * alpha + sP * aR;
+    if (den == 0.0) return Tn;
+    double num = 0.25 * alpha * Tn * Tn * Tn * Tn + sP * E + X;
+    if (!(num > 0.0)) {
+        if (neg) *neg = 1;
+        return 0.0;
+    }
+    return sqrt(sqrt(num / den));
+}
+
 /* ------------------------------------------------------ velocity (O(v/c)) terms */
 
 /* With beta = v/c, kappa_E = kappa_P and kappa_F = kappa_R, dt times the O(v/c)
@@ -292,7 +314,8 @@ void or_residual(const or_grid *g, const or_coef *cf, const double *En, double *
                 double sP = s_P(g, cf, c), T4 = T[c] * T[c] * T[c] * T[c];
                 R[0][c] += -En[c] - sP * g->aR * T4;
                 for (int q = 0; q < 3; ++q) R[1 + q][c] -= Fn[q][c];
-                R[4][c] = alpha_of(g, cf, c) * (T[c] - Tn[c]) + sP * (g->aR * T4 - E[c]);
+                double a = alpha_of(g, cf, c);
+                R[4][c] = gas_e(g, a, T[c]) - gas_e(g, a, Tn[c]) + sP * (g->aR * T4 - E[c]);
                 if (has_velocity(cf) && cf->vel_implicit) {
                     double Fc[3] = {F[0][c], F[1][c], F[2][c]};
                     R[4][c] -= vel_energy(g, cf, c, E[c], Fc);   /* the gas receives the O(v/c) energy */
@@ -312,7 +335,7 @@ static void weights(const or_grid *g, const or_coef *cf, double *const C[3], siz
     double sP = s_P(g, cf, c);
     *WE = 1.0 + sP + half;
     *WF = 1.0 + s_R(g, cf, c) + half;
-    *WT = alpha_of(g, cf, c) + 4.0 * sP * g->aR * T[c] * T[c] * T[c];
+    *WT = gas_C(g, alpha_of(g, cf, c), T[c]) + 4.0 * sP * g->aR * T[c] * T[c] * T[c];
 }
 
 void or_scaled_residual(const or_grid *g, const or_coef *cf, const double *En, double *const Fn[3],
@@ -584,11 +607,15 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                         o.dE[c] = 1.0 + sP;
                         bE[c] = En[c] + sP * g->aR * Ts4;
                     } else {
-                        /* emission linearised about Tstar, gas energy eliminated */
-                        double den = a + 4.0 * sP * g->aR * Ts3;
+                        /* emission and gas energy linearised about Tstar, gas energy eliminated */
+                        double den = gas_C(g, a, Ts) + 4.0 * sP * g->aR * Ts3;
                         double eta = den > 0 ? 4.0 * sP * g->aR * Ts3 / den : 0.0;
                         o.dE[c] = 1.0 + sP * (1.0 - eta);
-                        bE[c] = En[c] + eta * a * Tn[c] - 3.0 * (1.0 - eta) * sP * g->aR * Ts4;
+                        if (!g->cv_cubic)
+                            bE[c] = En[c] + eta * a * Tn[c] - 3.0 * (1.0 - eta) * sP * g->aR * Ts4;
+                        else
+                            bE[c] = En[c] + (1.0 - eta) * sP * g->aR * Ts4 +
+                                    eta * (gas_e(g, a, Tn[c]) - gas_e(g, a, Ts));
                         if (o.vscale) o.vscale[c] = 1.0 - eta;
                     }
                 }
@@ -647,17 +674,21 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                 for (int i = 0; i < g->nx; ++i) {
                     size_t c = idx(g, i, j, kk);
                     int flag = 0;
-                    double a = alpha_of(g, cf, c), sP = s_P(g, cf, c), Tb = Tn[c], Eb = E[c];
+                    double a = alpha_of(g, cf, c), sP = s_P(g, cf, c), Tb = Tn[c], Eb = E[c], X = 0.0;
                     if (has_velocity(cf) && cf->vel_implicit) {
-                        /* alpha (T - Tn) + sP (aR T^4 - E) = X: shift Tn (or E without heat capacity) */
                         double Fc[3] = {F[0][c], F[1][c], F[2][c]};
-                        double X = vel_energy(g, cf, c, E[c], Fc);
+                        X = vel_energy(g, cf, c, E[c], Fc);
+                    }
+                    if (g->cv_cubic) {
+                        T[c] = exchange_T4(a, Tn[c], sP, g->aR, E[c], X, &flag);
+                    } else {
+                        /* alpha (T - Tn) + sP (aR T^4 - E) = X: shift Tn (or E without heat capacity) */
                         if (a > 0)
                             Tb += X / a;
                         else if (sP > 0)
                             Eb += X / sP;
+                        T[c] = or_exchange_T(a, Tb, sP, g->aR, Eb, &flag);
                     }
-                    T[c] = or_exchange_T(a, Tb, sP, g->aR, Eb, &flag);
                     neg |= flag;
                 }
         st->neg_cells = neg;

@@ -49,6 +49,7 @@ typedef struct {
     double aR;     /* radiation constant */
     double cv;     /* gas heat capacity per unit mass: alpha = rho * cv */
     int bc[6];     /* faces -x,+x,-y,+y,-z,+z */
+    int cv_cubic;  /* 0: E_int = alpha T; 1: C_v = alpha T^3, E_int = alpha T^4 / 4 (the Marshak-wave gas) */
 } or_grid;
 
 /* Padded input fields (see header comment). f holds xx,yy,zz,xy,xz,yz.

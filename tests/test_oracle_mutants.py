@@ -1,6 +1,6 @@
 """Plants plausible mistakes in a copy of the oracle source (on the CPU) and checks that the
 oracle pins catch every one: a dropped or doubled term, a wrong sign, a wrong tensor index,
-a wrong ghost source, a missing direction, the O(v/c) terms.  Each mutant is compiled with gcc into a temporary
+a wrong ghost source, a missing direction, the O(v/c) terms, the cubic heat capacity.  Each mutant is compiled with gcc into a temporary
 directory and the pin module is run against it in a child process."""
 import os
 import subprocess
@@ -50,6 +50,11 @@ MUTANTS = [
     ("if (o.vscale) o.vscale[c] = 1.0 - eta;", "if (o.vscale) o.vscale[c] = 1.0;"),
     ("Tb += X / a;", "Tb -= X / a;"),
     ("fb[a] += cf->f[tens(a, k)][i] * b[k];", "fb[a] += cf->f[tens(a, a)][i] * b[k];"),
+    # cubic heat capacity
+    ("return g->cv_cubic ? 0.25 * alpha * T * T * T * T : alpha * T;", "return g->cv_cubic ? alpha * T * T * T * T : alpha * T;"),
+    ("return g->cv_cubic ? alpha * T * T * T : alpha; }", "return alpha; }"),
+    ("double den = 0.25 * alpha + sP * aR;", "double den = alpha + sP * aR;"),
+    ("eta * (gas_e(g, a, Tn[c]) - gas_e(g, a, Ts));", "eta * (gas_e(g, a, Tn[c]));"),
 ]
 
 
@@ -68,6 +73,7 @@ def test_pins_catch_planted_mistake(k, tmp_path):
     # a mutant that stalls the solver is caught by the per-test time limit (the pins take ~5 s)
     r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_velocity_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_gas_pins.py"),
                         "-x", "-q", "-p", "no:cacheprovider", "--timeout", "20"], env=env, capture_output=True,
                        text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"mutant survived: {after}"
