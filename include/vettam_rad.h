@@ -80,6 +80,10 @@ typedef struct {
     int vel_implicit;     /* rad_step_moving only: 1 moves the O(v/c) part of the gas-radiation
                              energy exchange into the implicit gas energy row (the paper's runtime
                              switch, Sec. 2.3.2); 0 (default) leaves it to the explicit hydro update */
+    int cv_cubic;         /* 0 (default): gas internal energy rho c_v T; 1: heat capacity rho c_v T^3,
+                             internal energy rho c_v T^4 / 4 (the gas of the Marshak-wave test, Sec. 3.4).
+                             rad_step, rad_step_moving, rad_residual and rad_exchange; the batched and
+                             two-level paths require 0 */
 } rad_params_t;
 
 typedef struct {
@@ -99,7 +103,7 @@ typedef struct {
 
 /* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
  * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients,
- * anderson_m 0, vel_implicit 0. */
+ * anderson_m 0, vel_implicit 0, cv_cubic 0. */
 void rad_default_params(rad_params_t *p);
 
 /* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */

@@ -359,7 +359,7 @@ void or_scaled_residual(const or_grid *g, const or_coef *cf, const double *En, d
                  * non-negative root (R_T > 0 at T = 0) the constraint T = 0 is active
                  * and the exchange row counts as satisfied */
                 double RT = (T[c] == 0.0 && R[4][c] > 0.0) ? 0.0 : R[4][c];
-                rT += (RT / WT) * (RT / WT);
+                if (WT > 0) rT += (RT / WT) * (RT / WT);   /* WT = 0 only at T = 0 with C_v(0) = 0 */
                 nE += E[c] * E[c];
                 for (int q = 0; q < 3; ++q) nF += F[q][c] * F[q][c];
                 nT += T[c] * T[c];

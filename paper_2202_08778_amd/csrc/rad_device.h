@@ -34,6 +34,7 @@ struct Grid {
     double cdt;       // c dt  (s = c dt rho kappa)
     double tau_k;     // tau_cell = tau_k * sR^2 / f_dd  with tau_k = 50 / nu^2
     double c, aR, cv;
+    int cv_cubic;     // 0: E_int = alpha T; 1: C_v = alpha T^3, E_int = alpha T^4 / 4 (alpha = rho cv)
 };
 
 // row d of the symmetric tensor in the (xx,yy,zz,xy,xz,yz) plane order: f_d0, f_d1, f_d2
@@ -188,6 +189,53 @@ __device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP,
     return T;
 }
 
+
+// Gas internal energy and heat capacity at T.
+__device__ __forceinline__ double gas_e(const Grid &g, double alpha, double T)
+{
+    return g.cv_cubic ? 0.25 * alpha * T * T * T * T : alpha * T;
+}
+__device__ __forceinline__ double gas_C(const Grid &g, double alpha, double T)
+{
+    return g.cv_cubic ? alpha * T * T * T : alpha;
+}
+
+// Gas temperature of the exchange row with an extra energy X the gas receives:
+// e(T) - e(Tn) + sP (aR T^4 - E) = X.  Constant capacity: exchange_T with T_n
+// shifted by X / alpha (or E by X / sP without capacity).  Cubic capacity: the
+// row is linear in T^4 and solved in closed form.  No non-negative root: 0, neg.
+__device__ __forceinline__ double gas_exchange(const Grid &g, double alpha, double Tn, double sP, double aR, double E,
+                                               double X, bool &neg)
+{
+    if (g.cv_cubic) {
+        const double den = 0.25 * alpha + sP * aR;
+        if (den == 0.0) return Tn;
+        const double num = 0.25 * alpha * Tn * Tn * Tn * Tn + sP * E + X;
+        if (!(num > 0.0)) {
+            neg = true;
+            return 0.0;
+        }
+        return sqrt(sqrt(num / den));
+    }
+    if (alpha > 0)
+        Tn += X / alpha;
+    else if (sP > 0)
+        E += X / sP;
+    return exchange_T(alpha, Tn, sP, aR, E, neg);
+}
+
+// Right-hand side of the energy row with the emission and the gas energy
+// linearised at T* and the gas energy eliminated (Newton on the T-eliminated
+// system); eta = 4 sP aR T*^3 / (C(T*) + 4 sP aR T*^3).  E diagonal 1 + sP (1 - eta).
+__device__ __forceinline__ double lin_rhs(const Grid &g, double En, double alpha, double Tn, double Ts, double sP,
+                                          double aR, double &eta)
+{
+    const double T3 = Ts * Ts * Ts, T4 = T3 * Ts;
+    const double den = gas_C(g, alpha, Ts) + 4.0 * sP * aR * T3;
+    eta = den > 0 ? 4.0 * sP * aR * T3 / den : 0.0;
+    if (!g.cv_cubic) return En + eta * alpha * Tn - 3.0 * (1.0 - eta) * sP * aR * T4;
+    return En + (1.0 - eta) * sP * aR * T4 + eta * (gas_e(g, alpha, Tn) - gas_e(g, alpha, Ts));
+}
 
 // Four consecutive elements of a Krylov vector, loaded/stored as one 16-byte
 // (FP32) or two 16-byte (FP64) vector accesses and widened to FP64.

@@ -57,6 +57,7 @@ int check_params(const rad_params_t *p)
     if (p->anderson_m < 0 || p->anderson_m > kMaxAnderson)
         return fail(RAD_EINVAL, "anderson_m must be in [0, %d]", kMaxAnderson);
     if (p->vel_implicit != 0 && p->vel_implicit != 1) return fail(RAD_EINVAL, "vel_implicit must be 0 or 1");
+    if (p->cv_cubic != 0 && p->cv_cubic != 1) return fail(RAD_EINVAL, "cv_cubic must be 0 or 1");
     return RAD_OK;
 }
 
@@ -190,6 +191,7 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->coef_dtype = RAD_F64;
     p->anderson_m = 0;
     p->vel_implicit = 0;
+    p->cv_cubic = 0;
 }
 
 // ------------------------------------------------------------------ autotune cache

@@ -103,10 +103,9 @@ __global__ void __launch_bounds__(kBlock)
             dE = 1.0 + sP;
             bE = En[c] + sP * aR * T4;
         } else {
-            const double den = alpha + 4.0 * sP * aR * T3;
-            const double eta = den > 0 ? 4.0 * sP * aR * T3 / den : 0.0;
+            double eta;
+            bE = lin_rhs(g, En[c], alpha, Tn[c], T, sP, aR, eta);
             dE = 1.0 + sP * (1.0 - eta);
-            bE = En[c] + eta * alpha * Tn[c] - 3.0 * (1.0 - eta) * sP * aR * T4;
         }
         const double E = ld(0, c);
         const double rE = bE - (dE * E + div[0]);
@@ -116,7 +115,7 @@ __global__ void __launch_bounds__(kBlock)
         if (MODE == RES_PHYSICAL) {
             outR[c] = -rE;
             for (int q = 0; q < 3; ++q) outR[(1 + q) * N + c] = -rF[q] * g.c;
-            outR[4 * N + c] = alpha * (T - Tn[c]) + sP * (aR * T4 - E);
+            outR[4 * N + c] = gas_e(g, alpha, T) - gas_e(g, alpha, Tn[c]) + sP * (aR * T4 - E);
         } else {
             const double half = 0.5 * g.nu;
             const double DE = dE + half * sC_nb, DF = 1.0 + sR + half * sC_nb;
@@ -193,17 +192,17 @@ __global__ void __launch_bounds__(tile_threads<double>())
             dE = 1.0 + sP;
             bE = e[0] + sP * aR * T4;
         } else {
-            const double den = alpha + 4.0 * sP * aR * T3;
-            const double eta = den > 0 ? 4.0 * sP * aR * T3 / den : 0.0;
+            double eta;
+            bE = lin_rhs(g, e[0], alpha, e[4], T, sP, aR, eta);
             dE = 1.0 + sP * (1.0 - eta);
-            bE = e[0] + eta * alpha * e[4] - 3.0 * (1.0 - eta) * sP * aR * T4;
         }
         const double E = S.Ec;
         double divE = nu * S.dEs, divF[3] = {nu * S.dF[0], nu * S.dF[1], nu * S.dF[2]};
         double vf = 1.0;   // factor of the energy row's O(v/c) terms
         if constexpr (VEL) {   // O(v/c) terms: local couplings, the E one joins the diagonal
             if constexpr (VEL == 2)
-                if (picard_mode != 0) vf = 1.0 - 4.0 * sP * aR * T3 / fmax(alpha + 4.0 * sP * aR * T3, 1e-300);
+                if (picard_mode != 0)
+                    vf = 1.0 - 4.0 * sP * aR * T3 / fmax(gas_C(g, alpha, T) + 4.0 * sP * aR * T3, 1e-300);
             dE += vf * e[8];
             for (int q = 0; q < 3; ++q) {
                 divE += vf * e[9 + q] * S.Fc[q];
@@ -382,22 +381,17 @@ __global__ void __launch_bounds__(kBlock)
         const double sP = g.cdt * r_ * (double)kP[c], alpha = r_ * g.cv, aR = g.aR;
         const double E = X[c];
         bool neg = false;
-        double Xv = 0.0, Tb = Tn[c], Eb = E;
+        double Xv = 0.0;
         if constexpr (VI) {
             Xv = VA[c] * E;
             for (int q = 0; q < 3; ++q) Xv += VB[q * N + c] * X[(1 + q) * N + c];
-            // alpha (T - Tn) + sP (aR T^4 - E) = X: shift T_n (or E without heat capacity)
-            if (alpha > 0)
-                Tb += Xv / alpha;
-            else if (sP > 0)
-                Eb += Xv / sP;
         }
-        const double T = exchange_T(alpha, Tb, sP, aR, Eb, neg);
+        const double T = gas_exchange(g, alpha, Tn[c], sP, aR, E, Xv, neg);
         const double T3 = T * T * T;
         // where no non-negative root exists T = 0 is the active bound (R_T > 0 there)
-        const double RT0 = alpha * (T - Tn[c]) + sP * (aR * T3 * T - E) - Xv;
+        const double RT0 = gas_e(g, alpha, T) - gas_e(g, alpha, Tn[c]) + sP * (aR * T3 * T - E) - Xv;
         const double RT = (T == 0.0 && RT0 > 0.0) ? 0.0 : RT0;
-        const double WT = alpha + 4.0 * sP * aR * T3;
+        const double WT = gas_C(g, alpha, T) + 4.0 * sP * aR * T3;
         const double dT = T - Tc[c];
         Tc[c] = T;
         if (Gk) {  // Picard map value and its residual for the Anderson history
@@ -523,9 +517,9 @@ __global__ void __launch_bounds__(kBlock)
         const double r_ = (double)rho[c];
         const double sP = g.cdt * r_ * (double)kP[c], alpha = r_ * g.cv, aR = g.aR, E = X[c];
         const double T3 = T * T * T;
-        const double RT0 = alpha * (T - Tn[c]) + sP * (aR * T3 * T - E);
+        const double RT0 = gas_e(g, alpha, T) - gas_e(g, alpha, Tn[c]) + sP * (aR * T3 * T - E);
         const double RT = (T == 0.0 && RT0 > 0.0) ? 0.0 : RT0;
-        const double WT = alpha + 4.0 * sP * aR * T3;
+        const double WT = gas_C(g, alpha, T) + 4.0 * sP * aR * T3;
         v[0] += WT > 0 ? (RT / WT) * (RT / WT) : 0.0;
         v[1] += T * T;
     }
@@ -674,7 +668,7 @@ __global__ void __launch_bounds__(kBlock)
     if (c >= n) return;
     const double r_ = (double)rho[c];
     bool neg = false;
-    T[c] = exchange_T(r_ * g.cv, Tn[c], g.cdt * r_ * (double)kP[c], g.aR, E[c], neg);
+    T[c] = gas_exchange(g, r_ * g.cv, Tn[c], g.cdt * r_ * (double)kP[c], g.aR, E[c], 0.0, neg);
 }
 
 // --------------------------------------------------------------- host side
@@ -696,6 +690,7 @@ Grid make_grid(int nx, int ny, int nz, const int bc[6], double dt, double dx, co
     g.cdt = p.c * dt;
     g.nu = p.c * dt / dx;
     g.tau_k = 50.0 / (g.nu * g.nu);
+    g.cv_cubic = p.cv_cubic;
     return g;
 }
 
@@ -1479,6 +1474,7 @@ namespace {
 int amr_setup(const rad_amr2_t *geom, const int bc[6], double dt, double dx, const rad_params_t *p, Solver &S)
 {
     if (!geom) return fail(RAD_EINVAL, "geometry is NULL");
+    if (p && p->cv_cubic) return fail(RAD_EINVAL, "the two-level grid requires cv_cubic = 0");
     const int nc[3] = {geom->nx, geom->ny, geom->nz};
     RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, false));
     Amr &A = S.A;
@@ -1758,6 +1754,7 @@ extern "C" int rad_exchange(long long n, const double *E, const double *T_n, dou
     g.aR = p->a_R;
     g.cv = p->c_v;
     g.c = p->c;
+    g.cv_cubic = p->cv_cubic;
     const dim3 gc((unsigned)((n + kBlock - 1) / kBlock)), bl(kBlock);
     hipStream_t st = (hipStream_t)stream;
     if (p->coef_dtype == RAD_F64)

@@ -146,3 +146,10 @@ def test_moving_step_is_validated_on_host(rad):
     assert call(p, None) == rad.RAD_EINVAL and "beta" in rad.last_error()
     assert call(rad.params(vel_implicit=1, anderson_m=2), P) == rad.RAD_EINVAL and "anderson" in rad.last_error()
     assert call(rad.params(vel_implicit=3), P) == rad.RAD_EINVAL
+
+
+def test_cubic_gas_is_validated(rad):
+    assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(cv_cubic=2))) == 0
+    g = rad.amr_geometry((8, 8, 8), (2, 2, 2), (6, 6, 6))
+    assert rad.lib.rad_workspace_bytes_amr2(ct.byref(g), ct.byref(rad.params(cv_cubic=1))) == 0
+    assert rad.params().cv_cubic == 0
