@@ -212,6 +212,39 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 #pragma unroll
         for (int q = 0; q < NL; ++q) lds[sl][q][sy][sxx] = u.v[q];
     };
+    // A halo cell is read only as the neighbour across its own axis (x for the side
+    // columns, y for the top and bottom rows): its state, that row of the tensor and
+    // its low-face speed of that axis (PRE) or its sR.  Lanes without a halo cell
+    // re-read their own cell along x (an L2 hit), so the loads stay unconditional.
+    // The apply loads these 8 values; the residual (CALL), whose FP64 records leave
+    // fewer registers, keeps the whole record (the lane-dependent planes cost it spills).
+    constexpr bool SLIM = !CALL;
+    const int hax = (threadIdx.x < 2 * kTX) ? 1 : 0;
+    struct Halo {
+        AT v[8];
+    };
+    auto load_halo = [&](int kp, unsigned o, Halo &u) __attribute__((always_inline)) {
+        const long long pb = plane * kp;
+        u.v[0] = s * ld_off(x + pb, o);
+#pragma unroll
+        for (int q = 1; q < 4; ++q) u.v[q] = sF * ld_off(x + q * N + pb, o);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u.v[4 + q] = (AT)ld_off(f + tens_row(hax, q) * N + pb, o);
+        if constexpr (PRE)
+            u.v[7] = ld_off(Cf + hax * N + pb, o);
+        else
+            u.v[7] = cdt * (AT)ld_off(rho + pb, o) * (AT)ld_off(kR + pb, o);
+    };
+    auto put_halo = [&](int sl, const Halo &u) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lds[sl][IX + q][hly][hlx] = u.v[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lds[sl][IF + tens_row(hax, q)][hly][hlx] = u.v[4 + q];
+        if constexpr (PRE)
+            lds[sl][IC + hax][hly][hlx] = u.v[7];
+        else
+            lds[sl][IS][hly][hlx] = u.v[7];
+    };
 
     ZRow prev[CPT];
     AT ex[CPT][NE > 0 ? NE : 1];
@@ -319,7 +352,21 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     // k are issued ahead of the prefetch, so waiting for them leaves it in flight.
     constexpr int DEPTH = TileShape<AT>::DEPTH;
     const unsigned hsrc = hly >= 0 ? hoff : off[0];
-    Full S0[CPT], S1[DEPTH == 2 ? CPT : 1], H0, H1;
+    using HT = std::conditional_t<SLIM, Halo, Full>;
+    auto load_h = [&](int kp, unsigned o, HT &u) __attribute__((always_inline)) {
+        if constexpr (SLIM)
+            load_halo(kp, o, u);
+        else
+            load_full(kp, o, u);
+    };
+    auto put_h = [&](int sl, const HT &u) __attribute__((always_inline)) {
+        if constexpr (SLIM)
+            put_halo(sl, u);
+        else
+            put(sl, hly, hlx, u);
+    };
+    Full S0[CPT], S1[DEPTH == 2 ? CPT : 1];
+    HT H0, H1;
     {
         Full t;
         for (int c = 0; c < CPT; ++c) {
@@ -333,29 +380,35 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
             load_full(z0, off[c], t);
             put(0, ly + TYT * c + 1, lx + 1, t);
         }
-        load_full(z0, hsrc, t);
-        if (hly >= 0) put(0, hly, hlx, t);
+        if constexpr (SLIM) {
+            Halo th;
+            load_halo(z0, hsrc, th);
+            if (hly >= 0) put_halo(0, th);
+        } else {
+            load_full(z0, hsrc, t);
+            if (hly >= 0) put(0, hly, hlx, t);
+        }
     }
     for (int c = 0; c < CPT; ++c) load_full(mapz(z0 + 1), off[c], S0[c]);
-    load_full(mapz(z0 + 1), hsrc, H0);
+    load_h(mapz(z0 + 1), hsrc, H0);
     if constexpr (DEPTH == 2) {
         for (int c = 0; c < CPT; ++c) load_full(mapz(min(z0 + 2, z1)), off[c], S1[c]);
-        load_full(mapz(min(z0 + 2, z1)), hsrc, H1);
+        load_h(mapz(min(z0 + 2, z1)), hsrc, H1);
     }
 
     // one plane: LOAD issues plane k+1+DEPTH (needed when k+1+DEPTH <= z1)
-    auto iter = [&](auto LOAD, int t, Full (&S)[CPT], Full &H) __attribute__((always_inline)) {
+    auto iter = [&](auto LOAD, int t, Full (&S)[CPT], HT &H) __attribute__((always_inline)) {
         const int k = z0 + t;
         const int a = t & 1, b = a ^ 1;
         // plane k+1 (issued DEPTH planes ago) into the free slot
         for (int c = 0; c < CPT; ++c) put(b, ly + TYT * c + 1, lx + 1, S[c]);
-        if (hly >= 0) put(b, hly, hlx, H);
+        if (hly >= 0) put_h(b, H);
         if constexpr (NE > 0)
             for (int c = 0; c < CPT; ++c) lex(k, plane * k, off[c], ex[c]);
         if constexpr (decltype(LOAD)::value) {
             const int kp = mapz(k + 1 + DEPTH);
             for (int c = 0; c < CPT; ++c) load_full(kp, off[c], S[c]);
-            load_full(kp, hsrc, H);
+            load_h(kp, hsrc, H);
         }
         lds_barrier();
         compute(k, a, b);
