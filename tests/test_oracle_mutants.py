@@ -41,7 +41,10 @@ MUTANTS = [
     ("g = Fm / (c * E[i]);", "g = Fm / E[i];"),
     ("fxy = beam * nx * ny;", "fxy = beam * nx * nz;"),
     ("double fxx = 1.0 / 3.0, fyy = 1.0 / 3.0,", "double fxx = 1.0 / 3.0, fyy = 0.3,"),
-    # O(v/c) terms
+]
+
+# caught by the O(v/c) pins
+VEL_MUTANTS = [
     ("y[1 + q][c] -= sR * g->c * x[0][c] * (b[q] + fb[q]);", "y[1 + q][c] -= sR * g->c * x[0][c] * fb[q];"),
     ("y[1 + q][c] -= sR * g->c * x[0][c] * (b[q] + fb[q]);", "y[1 + q][c] += sR * g->c * x[0][c] * (b[q] + fb[q]);"),
     ("return (sR - 2.0 * sP) * bF / g->c", "return (sR - sP) * bF / g->c"),
@@ -50,7 +53,10 @@ MUTANTS = [
     ("if (o.vscale) o.vscale[c] = 1.0 - eta;", "if (o.vscale) o.vscale[c] = 1.0;"),
     ("Tb += X / a;", "Tb -= X / a;"),
     ("fb[a] += cf->f[tens(a, k)][i] * b[k];", "fb[a] += cf->f[tens(a, a)][i] * b[k];"),
-    # cubic heat capacity
+]
+
+# caught by the cubic heat-capacity pins
+GAS_MUTANTS = [
     ("return g->cv_cubic ? 0.25 * alpha * T * T * T * T : alpha * T;", "return g->cv_cubic ? alpha * T * T * T * T : alpha * T;"),
     ("return g->cv_cubic ? alpha * T * T * T : alpha; }", "return alpha; }"),
     ("double den = 0.25 * alpha + sP * aR;", "double den = alpha + sP * aR;"),
@@ -58,10 +64,14 @@ MUTANTS = [
 ]
 
 
+CASES = ([(m, "test_oracle_pins.py") for m in MUTANTS] + [(m, "test_oracle_velocity_pins.py") for m in VEL_MUTANTS] +
+         [(m, "test_oracle_gas_pins.py") for m in GAS_MUTANTS])
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("k", range(len(MUTANTS)))
+@pytest.mark.parametrize("k", range(len(CASES)))
 def test_pins_catch_planted_mistake(k, tmp_path):
-    before, after = MUTANTS[k]
+    (before, after), pins = CASES[k]
     src = open(SRC).read()
     assert before in src, before
     path = tmp_path / "mutant.c"
@@ -71,9 +81,7 @@ def test_pins_catch_planted_mistake(k, tmp_path):
                     "-o", str(so), str(path), "-lm"], check=True)
     env = dict(os.environ, VETTAM_ORACLE_SO=str(so), OMP_NUM_THREADS="2")
     # a mutant that stalls the solver is caught by the per-test time limit (the pins take ~5 s)
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_velocity_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_gas_pins.py"),
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", pins),
                         "-x", "-q", "-p", "no:cacheprovider", "--timeout", "20"], env=env, capture_output=True,
                        text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"mutant survived: {after}"
