@@ -151,3 +151,13 @@ def test_two_level_full_size_against_oracle_rows_and_fp64(torch, rad):
     # exact conservation holds for the solution of the system; here the step stops at a scaled residual
     # of 1e-11, whose sum over 4 M cells (weights of up to ~1e3 in optically thick cells) bounds the defect
     assert abs(e1 - e0) <= 1e-6 * abs(e0)
+
+
+def test_two_level_with_anderson_matches_oracle(torch, rad):
+    """Anderson mixing of the Picard map on the two-level grid (history over both levels): same fixed point."""
+    d = _data(CASES[1])
+    ref = _oracle(1)
+    out, st = _gpu_step(torch, rad, d, "fp64", anderson_m=2)
+    errs = {f"{n}{lev}": _relerr(g[lev], r[lev]) for n, g, r in zip("EFT", out, ref[:3]) for lev in (0, 1)}
+    _say("amr + anderson", {k: f"{v:.2e}" for k, v in errs.items()}, "picard", st["picard_iters"])
+    assert max(errs.values()) <= FP64_TOL, errs
