@@ -180,12 +180,14 @@ int rad_step_amr2(const rad_amr2_t *geom, double *E, double *F, double *T_gas,
 /* Autotune rad_step for this grid, boundary set, precision and coefficient
  * type on the caller's data (same arguments as rad_step; the state E, F, T_gas
  * is left as it was on entry).  Times the stencil's z-range per workgroup
- * (8..128 planes) separately for the Krylov apply and the FP64 residual and,
- * if tune_restart != 0, one full step for each GMRES restart length in
- * {6, 8, 10, 12, 16, 24, 32, 48, 64} up to params->gmres_m (the workspace's
- * size).  The z-ranges are stored in the autotune cache
- * ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad) and used by every later
- * rad_step call with the same key; the fastest converged restart length is
+ * (8..128 planes) separately for the Krylov apply and the FP64 residual, for
+ * the apply also whether it reads the stored corrected face speeds or forms
+ * them per face from f and sR, and, if tune_restart != 0, one full step for
+ * each GMRES restart length in {6, 8, 10, 12, 16, 24, 32, 48, 64} up to
+ * params->gmres_m (the workspace's size).  The choices are stored in the
+ * autotune cache ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad, one
+ * "key TAB kz_apply kz_residual gmres_m load_speeds" line each) and used by
+ * every later rad_step call with the same key; the fastest converged restart length is
  * returned in *gmres_m as a recommendation (rad_step keeps the caller's).
  * Outputs may be NULL.  Synchronous. */
 int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,

@@ -118,22 +118,24 @@ struct CellSums {
     AT Ec, Fc[3], sc, dEs, dF[3], sumC_nb, sumC_all;
 };
 
-// The sweep.  PRE: sR and the low-face speeds Cf (divided by c, planes x|y|z)
-// are precomputed; otherwise both are derived from rho, kR and f per face.
+// The sweep.  PRE: sR is precomputed, otherwise derived from rho and kR.  CST
+// (PRE only): the low-face speeds Cf (divided by c, planes x|y|z) are
+// precomputed too; otherwise each face's speed is formed from f and sR.
 // lex(k, pb, o, e) loads the NE per-cell extras of the epilogue (plane k, its
 // base pb, in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell.
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
-template <class AT, class ST, bool PRE, bool CALL, int NE, class LEX, class EPI>
+template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, class LEX, class EPI>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
                                            const AT *__restrict__ x, AT s, AT sF,
-                                           AT (&lds)[2][Rec<PRE>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi)
+                                           AT (&lds)[2][Rec<CST>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi)
 {
     constexpr int TYT = TileShape<AT>::TYT, CPT = TileShape<AT>::CPT;
     constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
-    constexpr int NC = PRE ? 3 : 0;
-    constexpr int IX = Rec<PRE>::IX, IF = Rec<PRE>::IF, IS = Rec<PRE>::IS, IC = Rec<PRE>::IC, NL = Rec<PRE>::NL;
+    static_assert(PRE || !CST, "stored face speeds come with stored sR");
+    constexpr int NC = CST ? 3 : 0;
+    constexpr int IX = Rec<CST>::IX, IF = Rec<CST>::IF, IS = Rec<CST>::IS, IC = Rec<CST>::IC, NL = Rec<CST>::NL;
 
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
@@ -203,7 +205,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         if constexpr (PRE) {
             u.v[IS] = ld_off(sR + pb, o);
 #pragma unroll
-            for (int d = 0; d < NC; ++d) u.v[IC + d] = ld_off(Cf + d * N + pb, o);
+            for (int d = 0; d < NC; ++d) u.v[IC + d] = ld_off(Cf + d * N + pb, o);   // NC = 0 unless CST
         } else {
             u.v[IS] = cdt * (AT)ld_off(rho + pb, o) * (AT)ld_off(kR + pb, o);
         }
@@ -230,8 +232,10 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         for (int q = 1; q < 4; ++q) u.v[q] = sF * ld_off(x + q * N + pb, o);
 #pragma unroll
         for (int q = 0; q < 3; ++q) u.v[4 + q] = (AT)ld_off(f + tens_row(hax, q) * N + pb, o);
-        if constexpr (PRE)
+        if constexpr (CST)
             u.v[7] = ld_off(Cf + hax * N + pb, o);
+        else if constexpr (PRE)
+            u.v[7] = ld_off(sR + pb, o);
         else
             u.v[7] = cdt * (AT)ld_off(rho + pb, o) * (AT)ld_off(kR + pb, o);
     };
@@ -240,7 +244,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         for (int q = 0; q < 4; ++q) lds[sl][IX + q][hly][hlx] = u.v[q];
 #pragma unroll
         for (int q = 0; q < 3; ++q) lds[sl][IF + tens_row(hax, q)][hly][hlx] = u.v[4 + q];
-        if constexpr (PRE)
+        if constexpr (CST)
             lds[sl][IC + hax][hly][hlx] = u.v[7];
         else
             lds[sl][IS][hly][hlx] = u.v[7];
@@ -284,14 +288,14 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                        lds[a][IF + tens_row(d, 2)][ny_][nx_]};
                     // low face: own value; high face: the neighbour's low face
                     AT Cface;
-                    if constexpr (PRE)
+                    if constexpr (CST)
                         Cface = side ? lds[a][IC + d][ny_][nx_] : lds[a][IC + d][sy][sxx];
                     else
                         Cface = face_speed<AT>(fcr[d], fnr[d], S.sc, lds[a][IS][ny_][nx_], tk);
                     const bool self = d == 0 ? (side ? selfx_hi : selfx_lo) : (side ? selfy_hi[c] : selfy_lo[c]);
                     S.sumC_nb += self ? AT(0) : Cface;
                     if constexpr (CALL) {
-                        if (PRE && side && self)
+                        if (CST && side && self)
                             S.sumC_all += self_speed(fcr[d]);
                         else
                             S.sumC_all += Cface;
@@ -306,7 +310,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                 const ZRow &P = prev[c];
                 const AT Fn[3] = {P.x[1], P.x[2], P.x[3]};
                 AT Cface;
-                if constexpr (PRE)
+                if constexpr (CST)
                     Cface = lds[a][IC + 2][sy][sxx];
                 else
                     Cface = face_speed<AT>(fcr[2], P.f[2], S.sc, P.s, tk);
@@ -320,13 +324,13 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                 const AT fnr[3] = {lds[b][IF + tens_row(2, 0)][sy][sxx], lds[b][IF + tens_row(2, 1)][sy][sxx],
                                    lds[b][IF + tens_row(2, 2)][sy][sxx]};
                 AT Cface;
-                if constexpr (PRE)
+                if constexpr (CST)
                     Cface = lds[b][IC + 2][sy][sxx];
                 else
                     Cface = face_speed<AT>(fcr[2], fnr[2], S.sc, lds[b][IS][sy][sxx], tk);
                 S.sumC_nb += selfz_hi ? AT(0) : Cface;
                 if constexpr (CALL) {
-                    if (PRE && selfz_hi)
+                    if (CST && selfz_hi)
                         S.sumC_all += self_speed(fcr[2]);
                     else
                         S.sumC_all += Cface;
@@ -452,7 +456,9 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // VEL (moving medium): the O(v/c) couplings of the energy row to Ft (vb, 3
 // planes) and of the flux rows to E (vc, 3 planes); the energy row's own
 // O(v/c) term is part of dE.
-template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false>
+// LC (PRE only): read the stored face speeds Cf (false: form them per face from
+// f and sR, trading 3 loads per cell for two expm1/sqrt per face; an autotuner choice).
+template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
@@ -460,7 +466,8 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                   AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{}, const AT *__restrict__ vb = nullptr,
                   const AT *__restrict__ vc = nullptr)
 {
-    __shared__ AT lds[2][Rec<PRE>::NL][TileShape<AT>::LY][kLX];
+    constexpr bool CS = PRE && LC;
+    __shared__ AT lds[2][Rec<CS>::NL][TileShape<AT>::LY][kLX];
     const long long N = g.N;
     const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
     const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
@@ -521,7 +528,7 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, o, yFq[q] * yF);
         }
     };
-    tile_sweep<AT, ST, PRE, false, NEX>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi);
+    tile_sweep<AT, ST, PRE, false, NEX, CS>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

@@ -813,10 +813,11 @@ struct Solver {
     double *host;  // pinned staging, SM_TOTAL doubles
     rad_stats_t stats;
     int kz_apply = 0, kz_res = 0;  // tile z-ranges (0: default rule)
+    int loadc = 1;                 // the Krylov apply reads the stored face speeds (0: forms them per face)
     // tuning mode: after the setup and the first residual, time these z-ranges
     // for the apply and the residual instead of stepping
     const std::vector<int> *tune_kz = nullptr;
-    int tuned_apply = 0, tuned_res = 0;
+    int tuned_apply = 0, tuned_res = 0, tuned_loadc = 1;
 
     template <class P>
     P *at(size_t off) { return reinterpret_cast<P *>(ws + off); }
@@ -971,26 +972,28 @@ int run_step(Solver &S)
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
             const long long o = S.c0[l];
-            auto go = [&](auto amr_c, auto vel_c) {
-                constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value;
+            auto go = [&](auto amr_c, auto vel_c, auto lc_c) {
+                constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
                 if (fA)
-                    hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
+                    hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
                                        tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
                                        (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                        y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)), (const AT *)VBA,
                                        (const AT *)VCA);
                 else
-                    hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
+                    hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
                                        tg[l], f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
                                        (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
                                        level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA);
             };
             if (S.amr)
-                go(std::true_type{}, std::false_type{});
+                go(std::true_type{}, std::false_type{}, std::true_type{});
             else if (vel)
-                go(std::false_type{}, std::true_type{});
+                go(std::false_type{}, std::true_type{}, std::true_type{});
+            else if (S.loadc)
+                go(std::false_type{}, std::false_type{}, std::true_type{});
             else
-                go(std::false_type{}, std::false_type{});
+                go(std::false_type{}, std::false_type{}, std::false_type{});
         }
         prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
     };
@@ -1063,13 +1066,27 @@ int run_step(Solver &S)
         for (int kz : *S.tune_kz) {
             tg[0] = tile_geom<AT>(g, kz);
             tgr[0] = tile_geom<double>(g, kz);
-            float ms_a = 0, ms_r = 0;
-            apply(V, sm + SM_S, W);
-            if (hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
-            for (int r = 0; r < 5 && rc == RAD_OK; ++r) apply(V, sm + SM_S, W);
-            if (rc == RAD_OK && hipEventRecord(e1, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
-            if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "apply trial failed");
-            if (rc == RAD_OK && hipEventElapsedTime(&ms_a, e0, e1) != hipSuccess) rc = fail(RAD_EHIP, "timing failed");
+            float ms_r = 0;
+            // the apply with stored face speeds, then with face speeds formed per face
+            for (int lc = 1; lc >= 0 && rc == RAD_OK; --lc) {
+                S.loadc = lc;
+                float ms_a = 0;
+                apply(V, sm + SM_S, W);
+                if (hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+                for (int r = 0; r < 5 && rc == RAD_OK; ++r) apply(V, sm + SM_S, W);
+                if (rc == RAD_OK && hipEventRecord(e1, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
+                if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "apply trial failed");
+                if (rc == RAD_OK && hipEventElapsedTime(&ms_a, e0, e1) != hipSuccess)
+                    rc = fail(RAD_EHIP, "timing failed");
+                if (rc != RAD_OK) break;
+                if (trace) std::fprintf(stderr, "[rad] tune kz=%d loadc=%d: apply %.3f ms\n", kz, lc, ms_a / 5);
+                if (ms_a < best_a) {
+                    best_a = ms_a;
+                    S.tuned_apply = kz;
+                    S.tuned_loadc = lc;
+                }
+            }
+            S.loadc = 1;
             if (rc == RAD_OK) rc = residual();
             if (rc == RAD_OK && hipEventRecord(e0, S.st) != hipSuccess) rc = fail(RAD_EHIP, "event record failed");
             for (int r = 0; r < 3 && rc == RAD_OK; ++r) rc = residual();
@@ -1077,11 +1094,7 @@ int run_step(Solver &S)
             if (rc == RAD_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(RAD_EHIP, "residual trial failed");
             if (rc == RAD_OK && hipEventElapsedTime(&ms_r, e0, e1) != hipSuccess) rc = fail(RAD_EHIP, "timing failed");
             if (rc != RAD_OK) break;
-            if (trace) std::fprintf(stderr, "[rad] tune kz=%d: apply %.3f ms, residual %.3f ms\n", kz, ms_a / 5, ms_r / 3);
-            if (ms_a < best_a) {
-                best_a = ms_a;
-                S.tuned_apply = kz;
-            }
+            if (trace) std::fprintf(stderr, "[rad] tune kz=%d: residual %.3f ms\n", kz, ms_r / 3);
             if (ms_r < best_r) {
                 best_r = ms_r;
                 S.tuned_res = kz;
@@ -1347,22 +1360,30 @@ std::string single_key(int nx, int ny, int nz, const int bc[6], const rad_params
     return buf;
 }
 
-// tuned tile z-ranges per key, read from the cache file once per process
+// tuned choices per key (apply z-range, residual z-range, face speeds read by the
+// apply), read from the cache file once per process; entries are "kz_apply
+// kz_res gmres_m loadc" (older ones without loadc read the stored speeds)
+struct Tuned {
+    int kz_apply, kz_res, loadc;
+};
 std::mutex g_tile_mu;
-std::map<std::string, std::pair<int, int>> g_tiles;
+std::map<std::string, Tuned> g_tiles;
 
-void tile_lookup(const std::string &key, int &kz_apply, int &kz_res)
+void tile_lookup(const std::string &key, int &kz_apply, int &kz_res, int &loadc)
 {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     auto it = g_tiles.find(key);
     if (it == g_tiles.end()) {
         std::string v;
-        int a = 0, r = 0, m = 0;
-        if (!cache_get(key, v) || std::sscanf(v.c_str(), "%d %d %d", &a, &r, &m) < 2 || a < 1 || r < 1) a = r = 0;
-        it = g_tiles.emplace(key, std::make_pair(a, r)).first;
+        int a = 0, r = 0, m = 0, lc = 1;
+        const int n = cache_get(key, v) ? std::sscanf(v.c_str(), "%d %d %d %d", &a, &r, &m, &lc) : 0;
+        if (n < 2 || a < 1 || r < 1) a = r = 0;
+        if (n < 4 || (lc != 0 && lc != 1)) lc = 1;
+        it = g_tiles.emplace(key, Tuned{a, r, lc}).first;
     }
-    kz_apply = it->second.first;
-    kz_res = it->second.second;
+    kz_apply = it->second.kz_apply;
+    kz_res = it->second.kz_res;
+    loadc = it->second.loadc;
 }
 
 int dispatch_step(Solver &S)
@@ -1402,7 +1423,7 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     S.F = F;
     S.T = T_gas;
     std::memset(&S.stats, 0, sizeof(S.stats));
-    tile_lookup(single_key(nx, ny, nz, bc, *p), S.kz_apply, S.kz_res);
+    tile_lookup(single_key(nx, ny, nz, bc, *p), S.kz_apply, S.kz_res, S.loadc);
     return RAD_OK;
 }
 
@@ -1456,6 +1477,7 @@ extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, dou
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
     S.beta = beta;
     S.kz_apply = S.kz_res = 0;   // the velocity variants are not in the autotune cache
+    S.loadc = 1;
     int rc;
     try {
         rc = dispatch_step(S);
@@ -1591,7 +1613,7 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
     }
     S.tune_kz = &cand;
     RAD_TRY(dispatch_step(S));
-    const int ka = S.tuned_apply, kr = S.tuned_res;
+    const int ka = S.tuned_apply, kr = S.tuned_res, lc = S.tuned_loadc;
     int best_m = p->gmres_m;
     if (tune_restart) {
         // full steps at each restart length the workspace allows, from the same state
@@ -1622,6 +1644,7 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
             T.p.gmres_m = m;  // the layout keeps the caller's (largest) restart length
             T.kz_apply = ka;
             T.kz_res = kr;
+            T.loadc = lc;
             const auto t0 = std::chrono::steady_clock::now();
             const int rc = dispatch_step(T);
             const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1640,10 +1663,11 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
         RAD_TRY(restore());
     }
     const std::string key = single_key(nx, ny, nz, bc, *p);
-    cache_put(key, std::to_string(ka) + " " + std::to_string(kr) + " " + std::to_string(best_m));
+    cache_put(key, std::to_string(ka) + " " + std::to_string(kr) + " " + std::to_string(best_m) + " " +
+                       std::to_string(lc));
     {
         std::lock_guard<std::mutex> lk(g_tile_mu);
-        g_tiles[key] = std::make_pair(ka, kr);
+        g_tiles[key] = Tuned{ka, kr, lc};
     }
     if (kz_apply) *kz_apply = ka;
     if (kz_residual) *kz_residual = kr;
