@@ -33,12 +33,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30, autotune=None):
+def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30, autotune=None, eps_R=1e-2):
     """Warm up, restore the initial state, then time `steps` consecutive rad_step calls.  autotune:
     None, "tiles" (tune the stencil z-ranges) or "all" (also the restart length), outside the timing."""
     E, F, T = (t.clone() for t in state0)
     rho, kP, kR, f = coefs
-    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol, gmres_m=m)
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol, gmres_m=m, eps_R=eps_R)
     p.coef_dtype = 1 if rho.dtype == torch.float32 else 0
     ws = rad.alloc_workspace(rad.workspace_bytes(E.shape, p))
     tuned = None
@@ -283,6 +283,8 @@ def main():
                     help="autotune before timing: the stencil z-ranges (tiles) or also the restart length (all); "
                          "with --batched: the launch shape")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--eps-r", type=float, default=1e-2,
+                    help="relative tolerance of each linear solve (the library's default 1e-2)")
     ap.add_argument("--gmres-m", type=int, default=8,
                     help="GMRES restart length (8 is fastest on this workload: orthogonalisation grows with m "
                          "while the iteration count barely changes)")
@@ -323,7 +325,7 @@ def main():
 
     log("mixed path (FP32 Krylov + FP64 residual/refinement/exchange, FP32 coefficient storage):")
     mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile,
-                     args.gmres_m, args.autotune)
+                     args.gmres_m, args.autotune, args.eps_r)
     value = N * args.steps / mixed["seconds"]
     out_m = [t.cpu().numpy() for t in mixed["state"]]
 
@@ -346,7 +348,7 @@ def main():
         log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
         c64 = tuple(dev(d[k]) for k in ("rho", "kP", "kR", "f"))
         fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False, args.gmres_m,
-                        args.autotune)
+                        args.autotune, args.eps_r)
         del c64
 
     res = {
