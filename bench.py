@@ -33,12 +33,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30, autotune=None, eps_R=1e-2):
+def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=30, autotune=None, eps_R=1e-2,
+             poly=1):
     """Warm up, restore the initial state, then time `steps` consecutive rad_step calls.  autotune:
     None, "tiles" (tune the stencil z-ranges) or "all" (also the restart length), outside the timing."""
     E, F, T = (t.clone() for t in state0)
     rho, kP, kR, f = coefs
-    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol, gmres_m=m, eps_R=eps_R)
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, tol=tol, gmres_m=m, eps_R=eps_R, krylov_poly=poly)
     p.coef_dtype = 1 if rho.dtype == torch.float32 else 0
     ws = rad.alloc_workspace(rad.workspace_bytes(E.shape, p))
     tuned = None
@@ -189,7 +190,7 @@ def bench_amr(args, torch, np, rad, W):
     coefs = [pk(k, torch.float32) for k in ("rho", "kP", "kR", "f")]
     Nc, Nf = n ** 3, (2 * q) ** 3 * 8
     leaf = Nc - (2 * q) ** 3 + Nf
-    p = rad.params(prec="mixed", tol=args.tol, gmres_m=args.gmres_m, coef_dtype=1)
+    p = rad.params(prec="mixed", tol=args.tol, gmres_m=args.gmres_m, coef_dtype=1, krylov_poly=args.krylov_poly)
     ws = rad.alloc_workspace(rad.workspace_bytes_amr2(geom, p))
     E, F, T = (t.clone() for t in state0)
     for s in range(args.warmup):
@@ -221,7 +222,8 @@ def bench_amr(args, torch, np, rad, W):
            "config": {"workload": f"two-level grid: coarse {n}^3 periodic with the box [{q},{3 * q})^3 refined by 2 "
                                   f"(fine {2 * q * 2}^3), lognormal sigma 1, optical depth 1e-2..1e2 per coarse cell, "
                                   f"dt = 20 coarse crossings, FP32-exact inputs, {args.steps} steps, tol {args.tol:g}",
-                      "leaf_cells": leaf, "stored_cells": Nc + Nf, "gmres_m": p.gmres_m},
+                      "leaf_cells": leaf, "stored_cells": Nc + Nf, "gmres_m": p.gmres_m,
+                      "krylov_poly": p.krylov_poly},
            "krylov_iters_per_step": sum(s_["krylov_iters"] for s_ in stats) / args.steps,
            "picard_iters_per_step": sum(s_["picard_iters"] for s_ in stats) / args.steps,
            "converged_steps": sum(1 for s_ in stats if s_["rc"] == 0),
@@ -285,6 +287,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--eps-r", type=float, default=1e-2,
                     help="relative tolerance of each linear solve (the library's default 1e-2)")
+    ap.add_argument("--krylov-poly", type=int, choices=(0, 1), default=1,
+                    help="1: GMRES on the Jacobi-scaled operator times the Neumann polynomial 2I - B (the "
+                         "library's default); 0: Jacobi scaling alone")
     ap.add_argument("--gmres-m", type=int, default=8,
                     help="GMRES restart length (8 is fastest on this workload: orthogonalisation grows with m "
                          "while the iteration count barely changes)")
@@ -325,7 +330,7 @@ def main():
 
     log("mixed path (FP32 Krylov + FP64 residual/refinement/exchange, FP32 coefficient storage):")
     mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile,
-                     args.gmres_m, args.autotune, args.eps_r)
+                     args.gmres_m, args.autotune, args.eps_r, args.krylov_poly)
     value = N * args.steps / mixed["seconds"]
     out_m = [t.cpu().numpy() for t in mixed["state"]]
 
@@ -348,7 +353,7 @@ def main():
         log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
         c64 = tuple(dev(d[k]) for k in ("rho", "kP", "kR", "f"))
         fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False, args.gmres_m,
-                        args.autotune, args.eps_r)
+                        args.autotune, args.eps_r, args.krylov_poly)
         del c64
 
     res = {
@@ -367,6 +372,7 @@ def main():
         "config": {"workload": f"mixed-depth medium {n}^3 ({recipe}), periodic, "
                                f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
                    "cells": N, "gmres_m": (mixed["tuned"] or {}).get("gmres_m", args.gmres_m),
+                   "krylov_poly": args.krylov_poly,
                    "autotune": mixed["tuned"],
                    "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
         "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,

@@ -84,12 +84,19 @@ typedef struct {
                              internal energy rho c_v T^4 / 4 (the gas of the Marshak-wave test, Sec. 3.4).
                              rad_step, rad_step_moving, rad_residual and rad_exchange; the batched and
                              two-level paths require 0 */
+    int krylov_poly;      /* 1 (default): GMRES on the Jacobi-scaled operator B right-multiplied by the
+                             first-order Neumann polynomial 2I - B (Arnoldi on 2B - B^2; each Krylov
+                             iteration applies B twice, the correction is (2I - B) times the GMRES
+                             combination, so the residual GMRES minimises is still that of B);
+                             0: Jacobi scaling alone.  rad_step, rad_step_moving and rad_step_amr2;
+                             the batched plan ignores it */
 } rad_params_t;
 
 typedef struct {
     int status;            /* rad_status of the step (per block in the batched call) */
     int picard_iters;
-    int krylov_iters;      /* Krylov iterations summed over Picard iterations */
+    int krylov_iters;      /* Krylov (Arnoldi) iterations summed over Picard iterations; with
+                              krylov_poly = 1 each applies the scaled operator twice */
     int refine_sweeps;     /* FP64 residual evaluations (GMRES restarts) */
     int neg_cells;         /* cells whose exchange solve had no positive root (T set to 0) */
     int bad_cells;         /* cells with invalid coefficient data */
@@ -103,7 +110,7 @@ typedef struct {
 
 /* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
  * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients,
- * anderson_m 0, vel_implicit 0, cv_cubic 0. */
+ * anderson_m 0, vel_implicit 0, cv_cubic 0, krylov_poly 1. */
 void rad_default_params(rad_params_t *p);
 
 /* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */

@@ -458,13 +458,15 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // O(v/c) term is part of dE.
 // LC (PRE only): read the stored face speeds Cf (false: form them per face from
 // f and sR, trading 3 loads per cell for two expm1/sqrt per face; an autotuner choice).
+// pg != 0 (PRE, xF yF = 1): y = pg s x - D^-1 A (s x), the second factor of the
+// Neumann polynomial step (2I - B) B at no extra traffic.
 template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
                   AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{}, const AT *__restrict__ vb = nullptr,
-                  const AT *__restrict__ vc = nullptr)
+                  const AT *__restrict__ vc = nullptr, AT pg = AT(0))
 {
     constexpr bool CS = PRE && LC;
     __shared__ AT lds[2][Rec<CS>::NL][TileShape<AT>::LY][kLX];
@@ -522,6 +524,10 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             yE *= AT(1) / (dEc + dtr);
             const AT iDF = AT(1) / (AT(1) + S.sc + dtr);
             for (int q = 0; q < 3; ++q) yFq[q] *= iDF;
+        }
+        if (pg != AT(0)) {   // polynomial step: pg s x - B (s x), the centre of s x already in the sums
+            yE = pg * S.Ec - yE;
+            for (int q = 0; q < 3; ++q) yFq[q] = pg * S.Fc[q] - yFq[q];
         }
         if (active) {
             st_off(y + pb, o, yE);

@@ -58,6 +58,7 @@ int check_params(const rad_params_t *p)
         return fail(RAD_EINVAL, "anderson_m must be in [0, %d]", kMaxAnderson);
     if (p->vel_implicit != 0 && p->vel_implicit != 1) return fail(RAD_EINVAL, "vel_implicit must be 0 or 1");
     if (p->cv_cubic != 0 && p->cv_cubic != 1) return fail(RAD_EINVAL, "cv_cubic must be 0 or 1");
+    if (p->krylov_poly != 0 && p->krylov_poly != 1) return fail(RAD_EINVAL, "krylov_poly must be 0 or 1");
     return RAD_OK;
 }
 
@@ -192,6 +193,7 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->anderson_m = 0;
     p->vel_implicit = 0;
     p->cv_cubic = 0;
+    p->krylov_poly = 1;
 }
 
 // ------------------------------------------------------------------ autotune cache

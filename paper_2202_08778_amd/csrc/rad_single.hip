@@ -3,9 +3,12 @@
 // Host-driven Picard loop (Sec. 2.3.1 steps iv-vi):
 //   residual   r = b(T*) - A(T*) X  in FP64 for the linear system of the current
 //              iteration; its scaled norm is also the nonlinear residual
-//   Krylov     restarted GMRES(m) on the Jacobi-scaled system, Arnoldi in FP32
-//              (mixed) or FP64, solution accumulated into the FP64 state; each
-//              restart re-evaluates the FP64 residual (iterative refinement)
+//   Krylov     restarted GMRES(m) on the Jacobi-scaled system B, right-multiplied
+//              by the Neumann polynomial 2I - B by default (Arnoldi on 2B - B^2:
+//              half the iterations, so half the orthogonalisation traffic, for
+//              the same applies of B), Arnoldi in FP32 (mixed) or FP64, solution
+//              accumulated into the FP64 state; each restart re-evaluates the
+//              FP64 residual (iterative refinement)
 //   exchange   per-cell FP64 Newton solve of eq. PicardTemp for T
 // Every vector operation and reduction runs in the kernels below; the host
 // only keeps the (m+1) x m Hessenberg matrix and decides when to stop.
@@ -358,6 +361,24 @@ __global__ void __launch_bounds__(kBlock)
             for (int k = 0; k < 4; ++k) acc[k] += cf.a[i] * a[k];
         }
         Quad<double>::store(X + e, acc, r);
+    }
+}
+
+// z = sum_i a_i V_i over the 4N-vector, stored in the Krylov precision.
+template <class KT>
+__global__ void __launch_bounds__(kBlock)
+    k_combine(KT *__restrict__ z, const KT *__restrict__ V, long long stride, int cnt, Coefs cf, long long n)
+{
+    const long long step = (long long)gridDim.x * kBlock * 4;
+    for (long long e = ((long long)blockIdx.x * kBlock + threadIdx.x) * 4; e < n; e += step) {
+        double acc[4] = {0, 0, 0, 0}, r[4];
+        for (int i = 0; i < cnt; ++i) {
+            double a[4];
+            Quad<KT>::load(V + (long long)i * stride + e, a);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += cf.a[i] * a[k];
+        }
+        Quad<KT>::store(z + e, acc, r);
     }
 }
 
@@ -876,6 +897,7 @@ int run_step(Solver &S)
     KT *V = S.at<KT>(S.L.V), *W = S.at<KT>(S.L.W);
     double *part = S.part(), *sm = S.sm(), *h = S.host;
     const int m = p.gmres_m;
+    const bool poly = p.krylov_poly != 0;
     const long long stride = n4;
     rad_stats_t &st = S.stats;
 
@@ -967,7 +989,7 @@ int run_step(Solver &S)
                                (const double *)sR64, (const FT *)Cc, out);
         });
     };
-    auto apply = [&](const KT *x, const double *xs, KT *y) {
+    auto apply = [&](const KT *x, const double *xs, KT *y, AT pg = AT(0)) {
         if (S.amr) jump(x, xs, (const AT *)Cf, corrA);
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
@@ -979,12 +1001,12 @@ int run_step(Solver &S)
                                        tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
                                        (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                        y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)), (const AT *)VBA,
-                                       (const AT *)VCA);
+                                       (const AT *)VCA, pg);
                 else
                     hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
                                        tg[l], f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
                                        (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA);
+                                       level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA, pg);
             };
             if (S.amr)
                 go(std::true_type{}, std::false_type{}, std::true_type{});
@@ -1148,7 +1170,12 @@ int run_step(Solver &S)
             int cols = 0;
             for (int j = 0; j < m && its < p.max_krylov; ++j) {
                 KT *vn = V + (long long)(j + 1) * stride;
-                apply(V + (long long)j * stride, sm + SM_S + j, W);
+                if (poly) {   // W = (2I - B) B (s_j V_j); B (s_j V_j) parks in the slot of V_j+1
+                    apply(V + (long long)j * stride, sm + SM_S + j, vn);
+                    apply(vn, nullptr, W, AT(2));
+                } else {
+                    apply(V + (long long)j * stride, sm + SM_S + j, W);
+                }
                 ++its;
                 multidot(j + 1, W);
                 S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
@@ -1199,8 +1226,21 @@ int run_step(Solver &S)
                 y[i] = H[i * m + i] != 0 ? s / H[i * m + i] : 0.0;
             }
             for (int i = 0; i < cols; ++i) cf.a[i] = y[i] * sv[i];
-            S.timed(kUpd, 4 * Nd * (16 + kb * cols),
-                    [&] { hipLaunchKernelGGL((k_update_x<KT>), gf, bl, 0, S.st, X, V, stride, cols, cf, n4); });
+            if (poly) {
+                // X += (2I - B) z, z = sum_i a_i V_i formed in the slot of V_cols (not part of the combination)
+                KT *z = V + (long long)cols * stride;
+                S.timed(kUpd, 4 * Nd * kb * (cols + 1), [&] {
+                    hipLaunchKernelGGL((k_combine<KT>), gf, bl, 0, S.st, z, V, stride, cols, cf, n4);
+                });
+                apply(z, nullptr, W, AT(2));
+                Coefs one;
+                one.a[0] = 1.0;
+                S.timed(kUpd, 4 * Nd * (16 + kb),
+                        [&] { hipLaunchKernelGGL((k_update_x<KT>), gf, bl, 0, S.st, X, W, stride, 1, one, n4); });
+            } else {
+                S.timed(kUpd, 4 * Nd * (16 + kb * cols),
+                        [&] { hipLaunchKernelGGL((k_update_x<KT>), gf, bl, 0, S.st, X, V, stride, cols, cf, n4); });
+            }
             RAD_TRY(residual());
             ++cycles;
             if (trace)

@@ -26,7 +26,7 @@ class Params(ct.Structure):
                 ("eps_R", ct.c_double), ("eps_P", ct.c_double), ("max_picard", ct.c_int),
                 ("max_krylov", ct.c_int), ("gmres_m", ct.c_int), ("prec", ct.c_int), ("mode", ct.c_int),
                 ("coef_dtype", ct.c_int), ("anderson_m", ct.c_int), ("vel_implicit", ct.c_int),
-                ("cv_cubic", ct.c_int)]
+                ("cv_cubic", ct.c_int), ("krylov_poly", ct.c_int)]
 
 
 class Stats(ct.Structure):

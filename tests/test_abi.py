@@ -153,3 +153,10 @@ def test_cubic_gas_is_validated(rad):
     g = rad.amr_geometry((8, 8, 8), (2, 2, 2), (6, 6, 6))
     assert rad.lib.rad_workspace_bytes_amr2(ct.byref(g), ct.byref(rad.params(cv_cubic=1))) == 0
     assert rad.params().cv_cubic == 0
+
+
+def test_krylov_polynomial_is_validated(rad):
+    assert rad.params().krylov_poly == 1
+    assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(krylov_poly=2))) == 0
+    assert "krylov_poly" in rad.last_error()
+    assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(krylov_poly=0))) > 0

@@ -88,13 +88,14 @@ def _relerr(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
 
 
+@pytest.mark.parametrize("poly", [1, 0], ids=["poly", "jacobi"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("i", range(len(CASES)), ids=IDS)
-def test_two_level_step_matches_oracle(torch, rad, i, prec):
-    _say("amr parity", IDS[i], prec)
+def test_two_level_step_matches_oracle(torch, rad, i, prec, poly):
+    _say("amr parity", IDS[i], prec, "poly" if poly else "jacobi")
     d = _data(CASES[i])
     ref = _oracle(i)
-    out, st = _gpu_step(torch, rad, d, prec, gmres_m=GMRES_M[i])
+    out, st = _gpu_step(torch, rad, d, prec, gmres_m=GMRES_M[i], krylov_poly=poly)
     tol = FP64_TOL if prec == "fp64" else MIXED_TOL
     errs = {}
     for name, g, r in zip("EFT", out, ref[:3]):

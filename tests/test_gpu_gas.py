@@ -60,8 +60,11 @@ def test_cubic_gas_step_matches_oracle(torch, rad, kind, shape, seed, mode, prec
     ref = P.step(d["E"], d["F"], d["T"], tol=1e-14, mode=mode, max_picard=5000)
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
-    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, mode=mode, tol=1e-13, cv_cubic=1,
-                   max_picard=5000)
+    # the outflow case has cold cells (T = 0 active where E < 0): there a scaled residual of 1e-13 leaves
+    # T errors of up to ~2e-10 (the oracle's own steps with inexact linear solves show it), so the FP64
+    # step runs to 1e-14
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], prec=prec, mode=mode,
+                   tol=1e-14 if (kind == "outflow" and prec == "fp64") else 1e-13, cv_cubic=1, max_picard=5000)
     st = rad.rad_step(E, F, T, g(d["rho"]), g(d["kP"]), g(d["kR"]), g(d["f"]), d["dt"], d["dx"], d["bc"], p)
     torch.cuda.synchronize()
     errs = {k: _relerr(a.cpu().numpy(), b) for k, a, b in zip("EFT", (E, F, T), ref[:3])}

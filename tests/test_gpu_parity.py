@@ -164,16 +164,18 @@ STEP_CASES = [("clumpy", (9, 10, 12), 1), ("outflow", (11, 13, 20), 2), ("clumpy
               ("periodic", (20, 20, 20), 4), ("outflow", (1, 12, 40), 5)]
 
 
+@pytest.mark.parametrize("poly", [1, 0], ids=["poly", "jacobi"])
 @pytest.mark.parametrize("kind,shape,seed", STEP_CASES)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_step_matches_oracle(torch, rad, kind, shape, seed, prec):
-    _say("step", kind, shape, seed, prec)
+def test_step_matches_oracle(torch, rad, kind, shape, seed, prec, poly):
+    """Both Krylov operators (Jacobi scaling with and without the Neumann polynomial) reach the oracle's step."""
+    _say("step", kind, shape, seed, prec, "poly" if poly else "jacobi")
     d = _case(kind, shape, seed)
     if prec == "mixed":
         for k in ("E", "F", "T", "rho", "kP", "kR", "f"):
             d[k] = W._f32(d[k])
     ref = _oracle_problem(d).step(d["E"], d["F"], d["T"], tol=1e-14)
-    out = _gpu_step(torch, rad, d, prec, coef="f32" if prec == "mixed" else None)
+    out = _gpu_step(torch, rad, d, prec, coef="f32" if prec == "mixed" else None, krylov_poly=poly)
     _say("  stats", out[3])
     _compare(out, ref, FP64_TOL if prec == "fp64" else MIXED_TOL, f"{kind}{shape}/{prec}")
 
