@@ -120,7 +120,7 @@ def bench_batched(args, torch, np, rad, W):
     batch = W.batched_blocks(nblocks=1024, seed=4)
     descs, ar = rad.pack_blocks(batch["blocks"])
     cells = sum(b["n"] ** 3 for b in batch["blocks"])
-    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1)
+    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1, krylov_poly=args.krylov_poly)
     g = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
     dev = [g(ar["E"]), g(ar["F"]), g(ar["T"])] + [g(ar[k], torch.float32) for k in ("rho", "kP", "kR", "f")]
     init = [t.clone() for t in dev[:3]]
@@ -150,7 +150,7 @@ def bench_batched(args, torch, np, rad, W):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "1024 Dirichlet blocks, edges uniform on {8,12,16,24,32}, dt 1..1000 crossings, "
                                   "kappa 1e-2..1e3 per block, one persistent graph-replayed launch per step",
-                      "cells": cells, "gmres_m": p.gmres_m,
+                      "cells": cells, "gmres_m": p.gmres_m, "krylov_poly": p.krylov_poly,
                       "launch": dict(zip(("threads", "per_cu", "largest_first"), plan.launch_shape()))},
            "blocks_converged": conv, "blocks": len(batch["blocks"]),
            "krylov_iters_max_block": int(st["krylov_iters"].max()),

@@ -88,8 +88,8 @@ typedef struct {
                              first-order Neumann polynomial 2I - B (Arnoldi on 2B - B^2; each Krylov
                              iteration applies B twice, the correction is (2I - B) times the GMRES
                              combination, so the residual GMRES minimises is still that of B);
-                             0: Jacobi scaling alone.  rad_step, rad_step_moving and rad_step_amr2;
-                             the batched plan ignores it */
+                             0: Jacobi scaling alone.  Every stepping entry point, the batched plan
+                             included */
 } rad_params_t;
 
 typedef struct {

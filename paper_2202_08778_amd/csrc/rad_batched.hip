@@ -6,7 +6,8 @@
 // ordered largest first (longest-processing-time first) and solves each
 // block entirely inside one workgroup: FP64 residual of the Picard linear
 // system, restarted GMRES(m) with workgroup-level reductions (Arnoldi in FP32
-// or FP64), FP64 solution accumulation and refinement, per-cell FP64 exchange
+// or FP64; on the Jacobi-scaled operator times the Neumann polynomial 2I - B
+// unless krylov_poly = 0), FP64 solution accumulation and refinement, per-cell FP64 exchange
 // solve, and the same convergence test as the single-grid step.  Every loop is
 // bounded (max_picard, max_krylov, m) and the queue ends every workgroup, so
 // the grid always drains.  The launch (queue reset + persistent kernel) is a
@@ -46,7 +47,7 @@ struct BatchArgs {
     long long slot_bytes;
     int *queue;
     double c, aR, cv, tol, eps_R;
-    int max_picard, max_krylov, m, mode;
+    int max_picard, max_krylov, m, mode, poly;
 };
 
 // per-slot scratch layout for a block of up to nmax^3 cells
@@ -162,7 +163,7 @@ template <class CT, int NT>
 __device__ __noinline__ void apply_planes(Blk B, int n, int Nb, long long AR, const CT *__restrict__ f,
                                           const float *__restrict__ x, float s, const float *__restrict__ Cs,
                                           const float *__restrict__ sR, const float *__restrict__ dEv,
-                                          float *__restrict__ y, float *spl_)
+                                          float *__restrict__ y, float *spl_, float pg)
 {
     using KT = float;
     auto spl = reinterpret_cast<float(*)[10][32 * 32]>(spl_);
@@ -223,10 +224,16 @@ __device__ __noinline__ void apply_planes(Blk B, int n, int Nb, long long AR, co
             KT div[4], sumC;
             transport_blk_pre<KT>(nu, ld, fl, cs, div, sumC);
             const KT sRc = sR[c], dEc = dEv[c];
-            y[c] = (dEc * ld(0, 0, 0, 0) + div[0]) / (dEc + half * sumC);
+            const KT xc = ld(0, 0, 0, 0);
+            const KT yE = (dEc * xc + div[0]) / (dEc + half * sumC);
+            y[c] = pg != KT(0) ? pg * xc - yE : yE;
             const KT DF = KT(1) + sRc + half * sumC;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) y[(1 + t) * Nb + c] = ((KT(1) + sRc) * ld(1 + t, 0, 0, 0) + div[1 + t]) / DF;
+            for (int t = 0; t < 3; ++t) {
+                const KT xq = ld(1 + t, 0, 0, 0);
+                const KT yq = ((KT(1) + sRc) * xq + div[1 + t]) / DF;
+                y[(1 + t) * Nb + c] = pg != KT(0) ? pg * xq - yq : yq;
+            }
         }
         lds_barrier();
         if (k + 2 < n) store((k + 2) % 3);
@@ -391,11 +398,12 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
             wg_sum<NT, 5>(nr, red);
         };
 
-        // w = D^-1 A (s x): linear operator, ghost part of the correction is zero
-        auto apply = [&](const KT *x, KT s, KT *y) {
+        // w = D^-1 A (s x): linear operator, ghost part of the correction is zero;
+        // pg != 0: w = pg s x - D^-1 A (s x), the second factor of the polynomial step
+        auto apply = [&](const KT *x, KT s, KT *y, KT pg = KT(0)) {
             if constexpr (sizeof(KT) == 4) {
                 if (n <= 32) {
-                    apply_planes<CT, NT>(B, n, Nb, AR, f, x, s, Cs, sR, dEv, y, &spl[0][0][0]);
+                    apply_planes<CT, NT>(B, n, Nb, AR, f, x, s, Cs, sR, dEv, y, &spl[0][0][0], pg);
                     return;
                 }
             }
@@ -416,9 +424,15 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                 KT div[4], sumC;
                 transport_blk_pre<KT>((KT)B.nu, ld, fl, cs, div, sumC);
                 const KT sRc = sR[c], dEc = dEv[c], half = KT(0.5) * (KT)B.nu;
-                y[c] = (dEc * ld(0, 0, 0, 0) + div[0]) / (dEc + half * sumC);
+                const KT xc = ld(0, 0, 0, 0);
+                const KT yE = (dEc * xc + div[0]) / (dEc + half * sumC);
+                y[c] = pg != KT(0) ? pg * xc - yE : yE;
                 const KT DF = KT(1) + sRc + half * sumC;
-                for (int q = 0; q < 3; ++q) y[(1 + q) * Nb + c] = ((KT(1) + sRc) * ld(1 + q, 0, 0, 0) + div[1 + q]) / DF;
+                for (int q = 0; q < 3; ++q) {
+                    const KT xq = ld(1 + q, 0, 0, 0);
+                    const KT yq = ((KT(1) + sRc) * xq + div[1 + q]) / DF;
+                    y[(1 + q) * Nb + c] = pg != KT(0) ? pg * xq - yq : yq;
+                }
             }
         };
 
@@ -465,7 +479,13 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                 int cols = 0;
                 for (int j = 0; j < m && its < a.max_krylov; ++j) {
                     KT *vj = V + (long long)j * n4, *vn = V + (long long)(j + 1) * n4;
-                    apply(vj, (KT)sh_s[j], Wv);
+                    if (a.poly) {   // w = (2I - B) B (s_j V_j), B (s_j V_j) parked in the slot of V_j+1
+                        apply(vj, (KT)sh_s[j], vn);
+                        __syncthreads();
+                        apply(vn, KT(1), Wv, KT(2));
+                    } else {
+                        apply(vj, (KT)sh_s[j], Wv);
+                    }
                     ++its;
                     __syncthreads();
                     // dots <V_i, w>, i <= j, in chunks of DC, and <w, w>; indices past j are
@@ -556,16 +576,42 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
                     for (int i = 0; i < cols; ++i) sh_a[i] = sh_y[i] * sh_s[i];
                 }
                 __syncthreads();
-                for (int e = 4 * tid; e < n4; e += 4 * NT) {
-                    double acc[4], r[4];
-                    Quad<double>::load(X + e, acc);
-                    for (int i = 0; i < cols; ++i) {
-                        double a1[4];
-                        Quad<KT>::load(V + (long long)i * n4 + e, a1);
+                if (a.poly) {
+                    // X += (2I - B) z, z = sum_i a_i V_i formed in the slot of V_cols
+                    KT *z = V + (long long)cols * n4;
+                    for (int e = 4 * tid; e < n4; e += 4 * NT) {
+                        double acc[4] = {0, 0, 0, 0}, r[4];
+                        for (int i = 0; i < cols; ++i) {
+                            double a1[4];
+                            Quad<KT>::load(V + (long long)i * n4 + e, a1);
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) acc[k] += sh_a[i] * a1[k];
+                            for (int k = 0; k < 4; ++k) acc[k] += sh_a[i] * a1[k];
+                        }
+                        Quad<KT>::store(z + e, acc, r);
                     }
-                    Quad<double>::store(X + e, acc, r);
+                    __syncthreads();
+                    apply(z, KT(1), Wv, KT(2));
+                    __syncthreads();
+                    for (int e = 4 * tid; e < n4; e += 4 * NT) {
+                        double acc[4], w4[4], r[4];
+                        Quad<double>::load(X + e, acc);
+                        Quad<KT>::load(Wv + e, w4);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) acc[k] += w4[k];
+                        Quad<double>::store(X + e, acc, r);
+                    }
+                } else {
+                    for (int e = 4 * tid; e < n4; e += 4 * NT) {
+                        double acc[4], r[4];
+                        Quad<double>::load(X + e, acc);
+                        for (int i = 0; i < cols; ++i) {
+                            double a1[4];
+                            Quad<KT>::load(V + (long long)i * n4 + e, a1);
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) acc[k] += sh_a[i] * a1[k];
+                        }
+                        Quad<double>::store(X + e, acc, r);
+                    }
                 }
                 __syncthreads();
                 residual(nr);
@@ -781,6 +827,7 @@ void fill_args(rad_plan P, double *E, double *F, double *T, const void *rho, con
     a.max_picard = P->p.max_picard;
     a.max_krylov = P->p.max_krylov;
     a.m = P->p.gmres_m;
+    a.poly = P->p.krylov_poly;
     a.mode = P->p.mode;
     P->argv[0] = &P->args;
 }
@@ -843,7 +890,7 @@ std::string plan_key(rad_plan P)
     int hist[65] = {0};
     for (auto &d : P->desc) hist[d.n]++;
     std::ostringstream os;
-    os << "batched|" << device_tag() << "|p" << P->p.prec << "|c" << P->p.coef_dtype << "|m" << P->p.gmres_m << "|";
+    os << "batched|" << device_tag() << "|p" << P->p.prec << "|c" << P->p.coef_dtype << "|m" << P->p.gmres_m << "|k" << P->p.krylov_poly << "|";
     for (int k = 1; k <= 64; ++k)
         if (hist[k]) os << k << "x" << hist[k] << ",";
     return os.str();

@@ -65,11 +65,11 @@ def _relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1):
+def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1, poly=1):
     descs, ar = rad.pack_blocks(batch["blocks"])
     c32 = prec == "mixed"
     p = rad.params(c=batch["c"], a_R=batch["aR"], c_v=batch["cv"], prec=prec, tol=tol,
-                   coef_dtype=1 if c32 else 0)
+                   coef_dtype=1 if c32 else 0, krylov_poly=poly)
     dev = _upload(torch, ar, c32)
     plan = rad.Plan(descs, p)
     if autotune:
@@ -91,11 +91,12 @@ def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1):
     return descs, outs, stats
 
 
+@pytest.mark.parametrize("poly", [1, 0], ids=["poly", "jacobi"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
-def test_small_batch_matches_oracle_block_by_block(torch, rad, prec, tol):
-    _say("batched small", prec)
+def test_small_batch_matches_oracle_block_by_block(torch, rad, prec, tol, poly):
+    _say("batched small", prec, "poly" if poly else "jacobi")
     batch = W.batched_blocks(nblocks=12, seed=11, sizes=(3, 4, 5, 6, 8))
-    descs, outs, stats = _run(torch, rad, batch, prec)
+    descs, outs, stats = _run(torch, rad, batch, prec, poly=poly)
     st = stats[0]
     _say("  status", st["status"].tolist(), "krylov", st["krylov_iters"].tolist())
     assert np.all(st["status"] == 0)
