@@ -121,6 +121,8 @@ def bench_batched(args, torch, np, rad, W):
     descs, ar = rad.pack_blocks(batch["blocks"])
     cells = sum(b["n"] ** 3 for b in batch["blocks"])
     p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1, krylov_poly=args.krylov_poly)
+    if args.gmres_m is not None:
+        p.gmres_m = args.gmres_m
     g = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
     dev = [g(ar["E"]), g(ar["F"]), g(ar["T"])] + [g(ar[k], torch.float32) for k in ("rho", "kP", "kR", "f")]
     init = [t.clone() for t in dev[:3]]
@@ -141,6 +143,9 @@ def bench_batched(args, torch, np, rad, W):
         if s >= args.warmup:
             times.append(dt)
         log(f"  [batched] {'warmup ' if s < args.warmup else ''}step {s}: {1000 * dt:.0f} ms")
+        if s == args.warmup - 1 and args.reorder:
+            plan.reorder(stats)   # queue the timed steps by the warm-up step's block solve times
+            log("  [batched] queue reordered by measured block solve times")
     st = rad.Plan.read_stats(stats)
     sec = sum(times)
     conv = int((st["status"] == 0).sum())
@@ -151,6 +156,8 @@ def bench_batched(args, torch, np, rad, W):
            "config": {"workload": "1024 Dirichlet blocks, edges uniform on {8,12,16,24,32}, dt 1..1000 crossings, "
                                   "kappa 1e-2..1e3 per block, one persistent graph-replayed launch per step",
                       "cells": cells, "gmres_m": p.gmres_m, "krylov_poly": p.krylov_poly,
+                      "queue": ("longest measured solve first (warm-up step's block times)"
+                                if args.warmup > 0 and args.reorder else "largest block first"),
                       "launch": dict(zip(("threads", "per_cu", "largest_first"), plan.launch_shape()))},
            "blocks_converged": conv, "blocks": len(batch["blocks"]),
            "krylov_iters_max_block": int(st["krylov_iters"].max()),
@@ -281,6 +288,9 @@ def main():
                          "coarse 256^3 with the central half-box refined")
     ap.add_argument("--batched", action="store_true",
                     help="instead: the batched path on 1024 AMR-like Dirichlet blocks (one graph replay per step)")
+    ap.add_argument("--reorder", action="store_true",
+                    help="with --batched: queue the timed steps by the warm-up step's measured block solve times "
+                         "(longest first) instead of largest block first")
     ap.add_argument("--autotune", nargs="?", const="tiles", choices=("tiles", "all"), default=None,
                     help="autotune before timing: the stencil z-ranges (tiles) or also the restart length (all); "
                          "with --batched: the launch shape")
@@ -290,9 +300,9 @@ def main():
     ap.add_argument("--krylov-poly", type=int, choices=(0, 1), default=1,
                     help="1: GMRES on the Jacobi-scaled operator times the Neumann polynomial 2I - B (the "
                          "library's default); 0: Jacobi scaling alone")
-    ap.add_argument("--gmres-m", type=int, default=8,
-                    help="GMRES restart length (8 is fastest on this workload: orthogonalisation grows with m "
-                         "while the iteration count barely changes)")
+    ap.add_argument("--gmres-m", type=int, default=None,
+                    help="GMRES restart length (default 8 on the grids, where orthogonalisation grows with m "
+                         "while the iteration count barely changes; the library's 12 for --batched)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
@@ -301,6 +311,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 4 plain device copies of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.gmres_m is None and not args.batched:
+        args.gmres_m = 8
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (one GPU's share is "
               "the kernel at its real shape; see DESIGN.md for how the step would shard)", file=sys.stderr)

@@ -286,7 +286,8 @@ int rad_autotune_batched(rad_plan plan, double *E, double *F, double *T_gas, con
                          void *scratch, size_t scratch_bytes, void *stream);
 
 /* One step of every block: a single graph launch, asynchronous on `stream`.
- * dev_stats: device array of nblocks rad_stats_t (per-block status etc.). */
+ * dev_stats: device array of nblocks rad_stats_t (per-block status etc.;
+ * t_total_ms is the block's solve time on the device wall clock). */
 int rad_step_batched(rad_plan plan, double *E, double *F, double *T_gas, const void *rho,
                      const void *kappa_P, const void *kappa_R, const void *f_ij,
                      rad_stats_t *dev_stats, void *stream);
@@ -294,6 +295,17 @@ int rad_step_batched(rad_plan plan, double *E, double *F, double *T_gas, const v
 /* The plan's launch shape: threads per workgroup, workgroups per CU and
  * whether blocks are queued largest first (any output may be NULL). */
 int rad_plan_launch_shape(rad_plan plan, int *threads, int *per_cu, int *largest_first);
+
+/* Queue the plan's blocks by the solve times of an earlier step, longest
+ * first (longest-processing-time order on measured cost: a block's difficulty
+ * -- its optical depth per cell and crossings per step -- persists between
+ * steps, while the default order only knows its size).  dev_stats: the device
+ * stats array that step filled, whose t_total_ms holds each block's solve
+ * time on the device wall clock.  Synchronises `stream` (one small copy to
+ * the host), then uploads the new order; the results of later steps do not
+ * depend on the order.  The order holds until the next rad_plan_reorder or
+ * rad_autotune_batched.  RAD_ENOTIMPL if the device has no wall-clock rate. */
+int rad_plan_reorder(rad_plan plan, const rad_stats_t *dev_stats, void *stream);
 
 void rad_plan_destroy(rad_plan plan);
 

@@ -48,6 +48,7 @@ struct BatchArgs {
     int *queue;
     double c, aR, cv, tol, eps_R;
     int max_picard, max_krylov, m, mode, poly;
+    double clk_khz;                // rate of the device wall clock (per-block solve times; 0: not timed)
 };
 
 // per-slot scratch layout for a block of up to nmax^3 cells
@@ -269,6 +270,7 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
         __syncthreads();
         if (qi >= a.nblocks) break;
         const int bid = a.order[qi];
+        const long long t_start = wall_clock64();
         const rad_block_desc_t ds = a.desc[bid];
         Blk B;
         B.n = ds.n;
@@ -675,6 +677,7 @@ __global__ void __launch_bounds__(NT) k_batched(BatchArgs a)
         }
         if (tid == 0) {
             st.status = status;
+            st.t_total_ms = a.clk_khz > 0 ? (double)(wall_clock64() - t_start) / a.clk_khz : 0.0;
             a.stats[bid] = st;
         }
         __syncthreads();
@@ -776,6 +779,8 @@ struct rad_plan_s {
     int nt = 512;
     int per_cu = 1;
     bool lpt = true;
+    std::vector<double> cost;  // measured solve time per block (rad_plan_reorder), empty until then
+    double clk_khz = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t knode = nullptr;
@@ -791,7 +796,11 @@ int upload_order(rad_plan P, hipStream_t st)
 {
     std::vector<int> order(P->nblocks);
     for (int b = 0; b < P->nblocks; ++b) order[b] = b;
-    if (P->lpt)  // longest processing time first: estimated by interior cells
+    // longest processing time first: by the measured solve times of an earlier step when the caller
+    // has supplied them, else estimated by interior cells
+    if (P->lpt && (int)P->cost.size() == P->nblocks)
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return P->cost[x] > P->cost[y]; });
+    else if (P->lpt)
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return P->desc[x].n > P->desc[y].n; });
     HIP_TRY(hipMemcpyAsync(P->ws + P->L.order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -829,6 +838,7 @@ void fill_args(rad_plan P, double *E, double *F, double *T, const void *rho, con
     a.m = P->p.gmres_m;
     a.poly = P->p.krylov_poly;
     a.mode = P->p.mode;
+    a.clk_khz = P->clk_khz;
     P->argv[0] = &P->args;
 }
 
@@ -952,6 +962,12 @@ int plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *
     P->nt = 512;  // one 8-wave workgroup per CU unless the autotune cache says otherwise
     P->per_cu = 1;
     P->lpt = true;
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            P->clk_khz = khz;
+    }
     cache_lookup(P);
     int rc = RAD_OK;
     if (hipMemcpyAsync(P->ws + L.desc, desc, nblocks * sizeof(rad_block_desc_t), hipMemcpyHostToDevice, st) !=
@@ -1088,6 +1104,31 @@ extern "C" int rad_plan_launch_shape(rad_plan P, int *threads, int *per_cu, int 
     if (per_cu) *per_cu = P->per_cu;
     if (largest_first) *largest_first = P->lpt ? 1 : 0;
     return RAD_OK;
+}
+
+extern "C" int rad_plan_reorder(rad_plan P, const rad_stats_t *dev_stats, void *stream)
+{
+    clear_error();
+    if (!P) return fail(RAD_EINVAL, "plan is NULL");
+    if (!dev_stats) return fail(RAD_EINVAL, "dev_stats is NULL");
+    if (P->clk_khz <= 0) return fail(RAD_ENOTIMPL, "the device reports no wall-clock rate: blocks are not timed");
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        std::vector<rad_stats_t> h(P->nblocks);
+        HIP_TRY(hipMemcpyAsync(h.data(), dev_stats, h.size() * sizeof(rad_stats_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<double> cost(P->nblocks);
+        for (int b = 0; b < P->nblocks; ++b) {
+            const double t = h[b].t_total_ms;
+            if (!(t >= 0) || !std::isfinite(t)) return fail(RAD_EINVAL, "block %d: no solve time in dev_stats", b);
+            cost[b] = t;
+        }
+        P->cost.swap(cost);
+    } catch (const std::bad_alloc &) {
+        return fail(RAD_ENOMEM, "host memory for the block times");
+    }
+    P->lpt = true;
+    return upload_order(P, st);
 }
 
 extern "C" void rad_plan_destroy(rad_plan P)

@@ -100,6 +100,8 @@ def _load():
     L.rad_closure.restype = I
     L.rad_plan_launch_shape.argtypes = [P, ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
     L.rad_plan_launch_shape.restype = I
+    L.rad_plan_reorder.argtypes = [P, P, P]
+    L.rad_plan_reorder.restype = I
     L.rad_plan_destroy.argtypes = [P]
     L.rad_plan_destroy.restype = None
     L.rad_profile_enable.argtypes = [I]
@@ -123,7 +125,7 @@ EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_worksp
             "rad_face_speeds",
             "rad_apply", "rad_exchange", "rad_closure", "rad_batched_workspace_bytes", "rad_plan_batched",
             "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_launch_shape",
-            "rad_plan_destroy",
+            "rad_plan_reorder", "rad_plan_destroy",
             "rad_profile_enable", "rad_profile_reset", "rad_profile_count", "rad_profile_get", "rad_last_error")
 
 
@@ -535,6 +537,10 @@ class Plan:
         _check(lib.rad_step_batched(self.handle, *self._args(E, F, T, rho, kP, kR, f),
                                     _ptr(stats, name="stats"), _stream(stream)))
         return stats
+
+    def reorder(self, stats, stream=None):
+        """Queue the blocks longest measured solve first, from the stats buffer of an earlier step."""
+        _check(lib.rad_plan_reorder(self.handle, _ptr(stats, name="stats"), _stream(stream)))
 
     def launch_shape(self):
         """(threads per workgroup, workgroups per CU, largest-first queue) of the plan's launch."""

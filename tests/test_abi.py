@@ -155,6 +155,10 @@ def test_cubic_gas_is_validated(rad):
     assert rad.params().cv_cubic == 0
 
 
+def test_plan_reorder_rejects_null(rad):
+    assert rad.lib.rad_plan_reorder(None, None, None) == rad.RAD_EINVAL and "plan" in rad.last_error()
+
+
 def test_krylov_polynomial_is_validated(rad):
     assert rad.params().krylov_poly == 1
     assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(krylov_poly=2))) == 0

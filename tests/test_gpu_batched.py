@@ -136,6 +136,32 @@ def test_autotuned_plan_matches_default(torch, rad):
         assert _relerr(x, y) <= 1e-9
 
 
+def test_reorder_by_measured_times_keeps_results(torch, rad):
+    """Per-block solve times come back in the stats; queueing by them changes no block's result."""
+    _say("batched reorder")
+    batch = W.batched_blocks(nblocks=40, seed=14, sizes=(4, 8, 12))
+    descs, ar = rad.pack_blocks(batch["blocks"])
+    p = rad.params(c=batch["c"], a_R=batch["aR"], c_v=batch["cv"], prec="mixed", tol=1e-10, coef_dtype=1)
+    dev = _upload(torch, ar, True)
+    init = [t.clone() for t in dev[:3]]
+    plan = rad.Plan(descs, p)
+    st0 = plan.step(*dev)
+    torch.cuda.synchronize()
+    s0 = rad.Plan.read_stats(st0)
+    out0 = [t.cpu().numpy() for t in dev[:3]]
+    _say("  solve ms: min %.3f max %.3f" % (s0["t_total_ms"].min(), s0["t_total_ms"].max()))
+    assert np.all(s0["t_total_ms"] > 0)
+    plan.reorder(st0)
+    for t, t0 in zip(dev[:3], init):
+        t.copy_(t0)
+    s1 = rad.Plan.read_stats(plan.step(*dev))
+    out1 = [t.cpu().numpy() for t in dev[:3]]
+    for a, b in zip(out0, out1):
+        assert np.array_equal(a, b)
+    for k in ("status", "picard_iters", "krylov_iters"):
+        assert np.array_equal(s0[k], s1[k])
+
+
 def test_full_batch_1024_blocks(torch, rad):
     """1024 blocks with edges 8..32, dt 1..1000 crossings, kappa 1e-2..1e3, mixed precision: every
     block converges; sampled blocks match the oracle (small ones exactly to 1e-8, the largest
