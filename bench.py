@@ -388,6 +388,9 @@ def main():
                    "autotune": mixed["tuned"],
                    "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
         "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
+        "krylov_iters_per_s": sum(s["krylov_iters"] for s in mixed["stats"]) / mixed["seconds"],
+        "operator_applies_per_step": (1 + args.krylov_poly) * sum(s["krylov_iters"] for s in mixed["stats"])
+                                     / args.steps,
         "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / args.steps,
         "converged_steps": sum(1 for s in mixed["stats"] if s["rc"] == 0),
         "final_scaled_residual": mixed["stats"][-1]["scaled_residual"],
