@@ -48,6 +48,7 @@ def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=
                                   tune_restart=autotune == "all", workspace=ws)
         log(f"  [{prec}] autotune: {tuned}")
         p.gmres_m = tuned["gmres_m"]
+        p.krylov_poly = tuned["krylov_poly"]
     for s in range(warmup):
         st = rad.rad_step(E, F, T, rho, kP, kR, f, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
         log(f"  [{prec}] warmup step {s}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
@@ -384,13 +385,13 @@ def main():
         "config": {"workload": f"mixed-depth medium {n}^3 ({recipe}), periodic, "
                                f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
                    "cells": N, "gmres_m": (mixed["tuned"] or {}).get("gmres_m", args.gmres_m),
-                   "krylov_poly": args.krylov_poly,
+                   "krylov_poly": (mixed["tuned"] or {}).get("krylov_poly", args.krylov_poly),
                    "autotune": mixed["tuned"],
                    "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
         "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
         "krylov_iters_per_s": sum(s["krylov_iters"] for s in mixed["stats"]) / mixed["seconds"],
-        "operator_applies_per_step": (1 + args.krylov_poly) * sum(s["krylov_iters"] for s in mixed["stats"])
-                                     / args.steps,
+        "operator_applies_per_step": (1 + (mixed["tuned"] or {}).get("krylov_poly", args.krylov_poly))
+                                     * sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
         "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / args.steps,
         "converged_steps": sum(1 for s in mixed["stats"] if s["rc"] == 0),
         "final_scaled_residual": mixed["stats"][-1]["scaled_residual"],

@@ -191,17 +191,19 @@ int rad_step_amr2(const rad_amr2_t *geom, double *E, double *F, double *T_gas,
  * the apply also whether it reads the stored corrected face speeds or forms
  * them per face from f and sR, and, if tune_restart != 0, one full step for
  * each GMRES restart length in {6, 8, 10, 12, 16, 24, 32, 48, 64} up to
- * params->gmres_m (the workspace's size).  The choices are stored in the
- * autotune cache ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad, one
- * "key TAB kz_apply kz_residual gmres_m load_speeds" line each) and used by
- * every later rad_step call with the same key; the fastest converged restart length is
- * returned in *gmres_m as a recommendation (rad_step keeps the caller's).
+ * params->gmres_m (the workspace's size), with and without the Neumann
+ * polynomial (krylov_poly 1 and 0).  The choices are stored in the autotune
+ * cache ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad, one "key TAB kz_apply
+ * kz_residual gmres_m load_speeds krylov_poly" line each) and the tiles and
+ * face-speed variant are used by every later rad_step call with the same key;
+ * the fastest converged restart length and Krylov operator are returned in
+ * *gmres_m and *krylov_poly as recommendations (rad_step keeps the caller's).
  * Outputs may be NULL.  Synchronous. */
 int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
                       const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
                       double dt, double dx, const int bc[6], const rad_params_t *p,
                       void *workspace, size_t ws_bytes, void *stream, int tune_restart,
-                      int *kz_apply, int *kz_residual, int *gmres_m);
+                      int *kz_apply, int *kz_residual, int *gmres_m, int *krylov_poly);
 
 /* Nonlinear residual of the backward-Euler system at a state (E, F, T) given
  * the old state (E_n, F_n, T_n): R holds 5 planes [R_E | R_Fx | R_Fy | R_Fz | R_T]

@@ -1402,7 +1402,8 @@ std::string single_key(int nx, int ny, int nz, const int bc[6], const rad_params
 
 // tuned choices per key (apply z-range, residual z-range, face speeds read by the
 // apply), read from the cache file once per process; entries are "kz_apply
-// kz_res gmres_m loadc" (older ones without loadc read the stored speeds)
+// kz_res gmres_m loadc krylov_poly" (older ones without loadc read the stored speeds;
+// gmres_m and krylov_poly are recommendations only)
 struct Tuned {
     int kz_apply, kz_res, loadc;
 };
@@ -1640,7 +1641,7 @@ namespace {
 int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho, const void *kappa_P,
                   const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6], const rad_params_t *p,
                   void *workspace, size_t ws_bytes, void *stream, int tune_restart, int *kz_apply, int *kz_residual,
-                  int *gmres_m)
+                  int *gmres_m, int *krylov_poly)
 {
     Solver S;
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
@@ -1654,9 +1655,10 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
     S.tune_kz = &cand;
     RAD_TRY(dispatch_step(S));
     const int ka = S.tuned_apply, kr = S.tuned_res, lc = S.tuned_loadc;
-    int best_m = p->gmres_m;
+    int best_m = p->gmres_m, best_poly = p->krylov_poly;
     if (tune_restart) {
-        // full steps at each restart length the workspace allows, from the same state
+        // full steps at each restart length the workspace allows, with and without the
+        // Neumann polynomial, from the same state
         const size_t N = (size_t)nx * ny * nz;
         std::vector<double> save(5 * N);
         hipStream_t st = (hipStream_t)stream;
@@ -1676,35 +1678,39 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
             if (m <= p->gmres_m) ms.push_back(m);
         if (std::find(ms.begin(), ms.end(), p->gmres_m) == ms.end()) ms.push_back(p->gmres_m);
         double best_t = INFINITY;
-        for (int m : ms) {
-            RAD_TRY(restore());
-            Solver T;
-            RAD_TRY(init_solver(T, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace,
-                                ws_bytes, stream));
-            T.p.gmres_m = m;  // the layout keeps the caller's (largest) restart length
-            T.kz_apply = ka;
-            T.kz_res = kr;
-            T.loadc = lc;
-            const auto t0 = std::chrono::steady_clock::now();
-            const int rc = dispatch_step(T);
-            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (rc < 0) {
-                (void)restore();
-                return rc;
+        for (int m : ms)
+            for (int poly : {1, 0}) {
+                RAD_TRY(restore());
+                Solver T;
+                RAD_TRY(init_solver(T, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p,
+                                    workspace, ws_bytes, stream));
+                T.p.gmres_m = m;  // the layout keeps the caller's (largest) restart length
+                T.p.krylov_poly = poly;
+                T.kz_apply = ka;
+                T.kz_res = kr;
+                T.loadc = lc;
+                const auto t0 = std::chrono::steady_clock::now();
+                const int rc = dispatch_step(T);
+                const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (rc < 0) {
+                    (void)restore();
+                    return rc;
+                }
+                clear_error();
+                if (trace_enabled())
+                    std::fprintf(stderr, "[rad] tune m=%d poly=%d: %.3f s, rc %d, %d Krylov\n", m, poly, sec, rc,
+                                 T.stats.krylov_iters);
+                if (rc == RAD_OK && sec < best_t) {
+                    best_t = sec;
+                    best_m = m;
+                    best_poly = poly;
+                }
             }
-            clear_error();
-            if (trace_enabled())
-                std::fprintf(stderr, "[rad] tune m=%d: %.3f s, rc %d, %d Krylov\n", m, sec, rc, T.stats.krylov_iters);
-            if (rc == RAD_OK && sec < best_t) {
-                best_t = sec;
-                best_m = m;
-            }
-        }
         RAD_TRY(restore());
     }
     const std::string key = single_key(nx, ny, nz, bc, *p);
     cache_put(key, std::to_string(ka) + " " + std::to_string(kr) + " " + std::to_string(best_m) + " " +
-                       std::to_string(lc));
+                       std::to_string(lc) + " " + std::to_string(best_poly));
     {
         std::lock_guard<std::mutex> lk(g_tile_mu);
         g_tiles[key] = Tuned{ka, kr, lc};
@@ -1712,6 +1718,7 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
     if (kz_apply) *kz_apply = ka;
     if (kz_residual) *kz_residual = kr;
     if (gmres_m) *gmres_m = best_m;
+    if (krylov_poly) *krylov_poly = best_poly;
     return RAD_OK;
 }
 }  // namespace
@@ -1719,12 +1726,13 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
 extern "C" int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
                                  const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
                                  const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes,
-                                 void *stream, int tune_restart, int *kz_apply, int *kz_residual, int *gmres_m)
+                                 void *stream, int tune_restart, int *kz_apply, int *kz_residual, int *gmres_m,
+                                 int *krylov_poly)
 {
     clear_error();
     try {  // the host copy of the state is the one large host allocation
         return autotune_step(nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
-                             stream, tune_restart, kz_apply, kz_residual, gmres_m);
+                             stream, tune_restart, kz_apply, kz_residual, gmres_m, krylov_poly);
     } catch (const std::bad_alloc &) {
         return fail(RAD_ENOMEM, "host memory for the autotuner's copy of the state");
     }

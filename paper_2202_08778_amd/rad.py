@@ -94,7 +94,7 @@ def _load():
     L.rad_step_batched.argtypes = [P, P, P, P, P, P, P, P, P, P]
     L.rad_step_batched.restype = I
     L.rad_autotune_step.argtypes = [I, I, I, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, I,
-                                    ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
+                                    ct.POINTER(I), ct.POINTER(I), ct.POINTER(I), ct.POINTER(I)]
     L.rad_autotune_step.restype = I
     L.rad_closure.argtypes = [ct.c_longlong, P, P, I, ct.c_double, P, I, P]
     L.rad_closure.restype = I
@@ -326,8 +326,9 @@ def rad_step_amr2(geom: Amr2, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: 
 
 def autotune_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, tune_restart=True, workspace=None,
                   stream=None):
-    """Autotune rad_step on this data (state left unchanged): returns {"kz_apply", "kz_residual", "gmres_m"}.
-    The z-ranges are cached and used by later rad_step calls; gmres_m is a recommendation."""
+    """Autotune rad_step on this data (state left unchanged): returns {"kz_apply", "kz_residual", "gmres_m",
+    "krylov_poly"}.  The z-ranges are cached and used by later rad_step calls; gmres_m and krylov_poly are
+    recommendations."""
     torch = _torch()
     nz, ny, nx = E.shape
     N = nx * ny * nz
@@ -339,11 +340,12 @@ def autotune_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, tune
             _ptr(f, cd, 6 * N, "f")]
     if workspace is None:
         workspace = alloc_workspace(int(lib.rad_workspace_bytes(nx, ny, nz, ct.byref(p))), E.device)
-    ka, kr, m = ct.c_int(), ct.c_int(), ct.c_int()
+    ka, kr, m, kp = ct.c_int(), ct.c_int(), ct.c_int(), ct.c_int()
     _check(lib.rad_autotune_step(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
                                  _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
-                                 _stream(stream), 1 if tune_restart else 0, ct.byref(ka), ct.byref(kr), ct.byref(m)))
-    return {"kz_apply": ka.value, "kz_residual": kr.value, "gmres_m": m.value}
+                                 _stream(stream), 1 if tune_restart else 0, ct.byref(ka), ct.byref(kr), ct.byref(m),
+                                 ct.byref(kp)))
+    return {"kz_apply": ka.value, "kz_residual": kr.value, "gmres_m": m.value, "krylov_poly": kp.value}
 
 
 def rad_residual(En, Fn, Tn, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, R=None, stream=None):

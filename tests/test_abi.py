@@ -109,9 +109,9 @@ def test_other_entry_points_validate(rad):
     assert rad.lib.rad_closure(0, None, None, 1, 1.0, None, 0, None) == rad.RAD_OK
     # autotune validates like rad_step before touching the device
     assert rad.lib.rad_autotune_step(4, 4, 4, None, 8, 8, 8, 8, 8, 8, 1.0, 1.0, bc, ct.byref(p), 0x1000, 1 << 30,
-                                     None, 1, None, None, None) == rad.RAD_EINVAL
+                                     None, 1, None, None, None, None) == rad.RAD_EINVAL
     assert rad.lib.rad_autotune_step(0, 4, 4, 8, 8, 8, 8, 8, 8, 8, 1.0, 1.0, bc, ct.byref(p), 0x1000, 1 << 30,
-                                     None, 1, None, None, None) == rad.RAD_EINVAL
+                                     None, 1, None, None, None, None) == rad.RAD_EINVAL
 
 
 def test_amr2_geometry_is_validated_on_host(rad):

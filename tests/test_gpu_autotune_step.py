@@ -35,13 +35,14 @@ def test_autotune_step_caches_tiles_and_keeps_state(torch, rad, tmp_path, monkey
     out = rad.autotune_step(E, F, T, *coef, d["dt"], d["dx"], d["bc"], p, tune_restart=True)
     print("autotune", out, flush=True)
     assert out["kz_apply"] in (8, 16, 32, 40) and out["kz_residual"] in (8, 16, 32, 40)
-    assert out["gmres_m"] in (6, 8, 10, 12, 16)
+    assert out["gmres_m"] in (6, 8, 10, 12, 16) and out["krylov_poly"] in (0, 1)
     for t, a in zip((E, F, T), (d["E"], d["F"], d["T"])):
         assert np.array_equal(t.cpu().numpy(), a)
     lines = open(os.path.join(str(tmp_path), "autotune.txt")).read().splitlines()
     assert any(l.startswith("single|") and "|24x20x40|" in l for l in lines)
     # a step with the tuned tiles (read back from the cache) and restart length matches the oracle
     p.gmres_m = out["gmres_m"]
+    p.krylov_poly = out["krylov_poly"]
     p.tol = 1e-13
     st = rad.rad_step(E, F, T, *coef, d["dt"], d["dx"], d["bc"], p)
     P = oracle.Problem(d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"], c=d["c"], aR=d["aR"],
