@@ -84,12 +84,18 @@ typedef struct {
                              internal energy rho c_v T^4 / 4 (the gas of the Marshak-wave test, Sec. 3.4).
                              rad_step, rad_step_moving, rad_residual and rad_exchange; the batched and
                              two-level paths require 0 */
-    int krylov_poly;      /* 1 (default): GMRES on the Jacobi-scaled operator B right-multiplied by the
-                             first-order Neumann polynomial 2I - B (Arnoldi on 2B - B^2; each Krylov
-                             iteration applies B twice, the correction is (2I - B) times the GMRES
-                             combination, so the residual GMRES minimises is still that of B);
-                             0: Jacobi scaling alone.  Every stepping entry point, the batched plan
-                             included */
+    int krylov_poly;      /* Krylov operator, always right-multiplied onto the Jacobi-scaled operator B
+                             so that GMRES minimises the residual of B itself:
+                             1 (default): the first-order Neumann polynomial 2I - B (Arnoldi on
+                             2B - B^2, two applies of B per iteration); every stepping entry point,
+                             the batched plan included;
+                             0: Jacobi scaling alone;
+                             2: one multigrid V-cycle (levels halve the grid while every extent is
+                             even and >= 8, at most 6 levels; coarse operators re-discretised on the
+                             children's mean sR, tensor and E diagonal; one damped Jacobi sweep,
+                             weight 0.4, before and after each coarse correction, 8 on the coarsest
+                             level).  rad_step only, on grids whose extents halve at least once
+                             (RAD_EINVAL otherwise); its levels enlarge the workspace */
 } rad_params_t;
 
 typedef struct {
@@ -192,7 +198,8 @@ int rad_step_amr2(const rad_amr2_t *geom, double *E, double *F, double *T_gas,
  * them per face from f and sR, and, if tune_restart != 0, one full step for
  * each GMRES restart length in {6, 8, 10, 12, 16, 24, 32, 48, 64} up to
  * params->gmres_m (the workspace's size), with and without the Neumann
- * polynomial (krylov_poly 1 and 0).  The choices are stored in the autotune
+ * polynomial (krylov_poly 1 and 0) and, when params->krylov_poly = 2 (the
+ * workspace then holds the multigrid levels), with the V-cycle too.  The choices are stored in the autotune
  * cache ($VETTAM_RAD_CACHE_DIR or ~/.cache/vettam_rad, one "key TAB kz_apply
  * kz_residual gmres_m load_speeds krylov_poly" line each) and the tiles and
  * face-speed variant are used by every later rad_step call with the same key;

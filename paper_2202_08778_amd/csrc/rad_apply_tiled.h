@@ -459,19 +459,23 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // LC (PRE only): read the stored face speeds Cf (false: form them per face from
 // f and sR, trading 3 loads per cell for two expm1/sqrt per face; an autotuner choice).
 // pg != 0 (PRE, xF yF = 1): y = pg s x - D^-1 A (s x), the second factor of the
-// Neumann polynomial step (2I - B) B at no extra traffic.
+// Neumann polynomial step (2I - B) B at no extra traffic.  The operand's scale s
+// is *xs times xm.  qv (PRE, pg = 0): y = s x + qm (qs qv - D^-1 A (s x)), a damped
+// Jacobi sweep on B e = qs qv.  dout (PRE): also write the Jacobi diagonal D (E
+// row, then the F rows' common value; two planes).  Used by the multigrid cycle.
 template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
                   AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{}, const AT *__restrict__ vb = nullptr,
-                  const AT *__restrict__ vc = nullptr, AT pg = AT(0))
+                  const AT *__restrict__ vc = nullptr, AT pg = AT(0), AT xm = AT(1), const AT *__restrict__ qv = nullptr,
+                  AT qm = AT(0), AT qs = AT(1), AT *__restrict__ dout = nullptr)
 {
     constexpr bool CS = PRE && LC;
     __shared__ AT lds[2][Rec<CS>::NL][TileShape<AT>::LY][kLX];
     const long long N = g.N;
-    const AT s = (PRE && xs) ? (AT)(*xs) : AT(1);
+    const AT s = ((PRE && xs) ? (AT)(*xs) : AT(1)) * xm;
     const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
     constexpr int NEX = AMR ? 6 : (VEL ? 7 : 1);
     const AT *corr = (const AT *)al.corr;
@@ -524,10 +528,17 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             yE *= AT(1) / (dEc + dtr);
             const AT iDF = AT(1) / (AT(1) + S.sc + dtr);
             for (int q = 0; q < 3; ++q) yFq[q] *= iDF;
+            if (dout && active) {   // the Jacobi diagonal itself (E row, F rows)
+                st_off(dout + pb, o, dEc + dtr);
+                st_off(dout + N + pb, o, AT(1) + S.sc + dtr);
+            }
         }
         if (pg != AT(0)) {   // polynomial step: pg s x - B (s x), the centre of s x already in the sums
             yE = pg * S.Ec - yE;
             for (int q = 0; q < 3; ++q) yFq[q] = pg * S.Fc[q] - yFq[q];
+        } else if (qv) {     // damped Jacobi sweep on B e = qs qv from e = s x
+            yE = S.Ec + qm * (qs * ld_off(qv + pb, o) - yE);
+            for (int q = 0; q < 3; ++q) yFq[q] = S.Fc[q] + qm * (qs * ld_off(qv + (1 + q) * N + pb, o) - yFq[q]);
         }
         if (active) {
             st_off(y + pb, o, yE);

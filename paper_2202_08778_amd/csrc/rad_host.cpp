@@ -58,7 +58,7 @@ int check_params(const rad_params_t *p)
         return fail(RAD_EINVAL, "anderson_m must be in [0, %d]", kMaxAnderson);
     if (p->vel_implicit != 0 && p->vel_implicit != 1) return fail(RAD_EINVAL, "vel_implicit must be 0 or 1");
     if (p->cv_cubic != 0 && p->cv_cubic != 1) return fail(RAD_EINVAL, "cv_cubic must be 0 or 1");
-    if (p->krylov_poly != 0 && p->krylov_poly != 1) return fail(RAD_EINVAL, "krylov_poly must be 0 or 1");
+    if (p->krylov_poly < 0 || p->krylov_poly > 2) return fail(RAD_EINVAL, "krylov_poly must be 0, 1 or 2");
     return RAD_OK;
 }
 
@@ -67,7 +67,7 @@ int check_params(const rad_params_t *p)
 static const char *const kNames[K_NCLASS] = {
     "setup", "residual_fp64", "apply_fp32", "apply_fp64", "multidot_fp32", "multidot_fp64", "orth_update_fp32",
     "orth_update_fp64", "update_x_fp32", "update_x_fp64", "exchange_fp64", "commit", "reduce", "batched_persistent",
-    "closure", "amr_jump"};
+    "closure", "amr_jump", "multigrid_levels"};
 
 struct Pending {
     hipEvent_t a, b;

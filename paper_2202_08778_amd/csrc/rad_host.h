@@ -38,7 +38,7 @@ std::string device_tag();
 
 enum {
     K_SETUP = 0, K_RESIDUAL, K_APPLY32, K_APPLY64, K_MULTIDOT32, K_MULTIDOT64, K_ORTH32, K_ORTH64,
-    K_UPDATEX32, K_UPDATEX64, K_EXCHANGE, K_COMMIT, K_REDUCE, K_BATCHED, K_CLOSURE, K_AMR, K_NCLASS
+    K_UPDATEX32, K_UPDATEX64, K_EXCHANGE, K_COMMIT, K_REDUCE, K_BATCHED, K_CLOSURE, K_AMR, K_MG, K_NCLASS
 };
 
 }  // namespace vr

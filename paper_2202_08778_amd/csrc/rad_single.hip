@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -382,6 +383,89 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// ---- multigrid cycle of the Krylov preconditioner (krylov_poly = 2).  Level l+1
+// halves every extent of level l; a coarse cell's children are (2i+a, 2j+b, 2k+e).
+
+__device__ __forceinline__ long long mg_child(const Grid &gf, int ic, int jc, int kc, int t)
+{
+    return (long long)(2 * ic + (t & 1)) + (long long)gf.nx * ((2 * jc + ((t >> 1) & 1)) +
+                                                                 (long long)gf.ny * (2 * kc + (t >> 2)));
+}
+
+// dst (np planes of the coarse grid) = mean of the 8 children of src (np planes, stride sN)
+template <class ST, class AT>
+__global__ void __launch_bounds__(kBlock)
+    k_mg_average(Grid gf, Grid gc, int np, const ST *__restrict__ src, long long sN, AT *__restrict__ dst)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= gc.N) return;
+    int i, j, k;
+    cell_ijk(gc, c, i, j, k);
+    for (int q = 0; q < np; ++q) {
+        double a = 0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a += (double)src[q * sN + mg_child(gf, i, j, k, t)];
+        dst[q * gc.N + c] = (AT)(0.125 * a);
+    }
+}
+
+// corrected low-face speeds of a coarse level from its sR and tensor (as k_face_coef)
+template <class AT>
+__global__ void __launch_bounds__(kBlock)
+    k_mg_face(Grid g, const AT *__restrict__ sR, const AT *__restrict__ f, AT *__restrict__ Cf)
+{
+    const long long N = g.N;
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    int i, j, k;
+    cell_ijk(g, c, i, j, k);
+    for (int d = 0; d < 3; ++d) {
+        const long long nb = neighbour(g, i, j, k, c, d, 0);
+        Cf[d * N + c] = (AT)face_speed<double>((double)f[d * N + nb], (double)f[d * N + c], (double)sR[nb],
+                                                (double)sR[c], g.tau_k);
+    }
+}
+
+// coarse right-hand side of the scaled system: q_c = Dc^-1 mean_children(Df t)
+template <class AT>
+__global__ void __launch_bounds__(kBlock)
+    k_mg_restrict(Grid gf, Grid gc, const AT *__restrict__ t, const AT *__restrict__ Df, const AT *__restrict__ Dc,
+                  AT *__restrict__ q)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= gc.N) return;
+    int i, j, k;
+    cell_ijk(gc, c, i, j, k);
+    const long long Nf = gf.N, Nc = gc.N;
+    double a[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const long long f = mg_child(gf, i, j, k, u);
+        const double dE = (double)Df[f], dF = (double)Df[Nf + f];
+        a[0] += dE * (double)t[f];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) a[r] += dF * (double)t[r * Nf + f];
+    }
+    q[c] = (AT)(0.125 * a[0] / (double)Dc[c]);
+    const double iF = 0.125 / (double)Dc[Nc + c];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) q[r * Nc + c] = (AT)(a[r] * iF);
+}
+
+// e = qs q + (the coarse correction of the cell's parent)
+template <class AT>
+__global__ void __launch_bounds__(kBlock)
+    k_mg_inject(Grid gf, Grid gc, const AT *__restrict__ q, AT qs, const AT *__restrict__ ec, AT *__restrict__ e)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= gf.N) return;
+    int i, j, k;
+    cell_ijk(gf, c, i, j, k);
+    const long long pc = (long long)(i >> 1) + (long long)gc.nx * ((j >> 1) + (long long)gc.ny * (k >> 1));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) e[r * gf.N + c] = qs * q[r * gf.N + c] + ec[r * gc.N + pc];
+}
+
 // Per-cell exchange solve (eq. PicardTemp) for T with E = X_E; then the
 // diagnostics of the Picard iteration, and X0 = X.  Partials:
 //   [sum (R_T/W_T)^2, sum T^2, sum dT^2, sum dE^2, sum E^2, sum dFt^2, sum Ft^2, neg]
@@ -737,7 +821,7 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, part, small,
+    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG, part, small,
         total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
@@ -752,11 +836,33 @@ long long tile_bound(int nx, int ny, int nz)
     return (long long)((nx + 63) / 64) * ((ny + 3) / 4) * (nz <= 8 ? 1 : (nz + 3) / 4);
 }
 
+// Multigrid levels below an nx x ny x nz grid: halve while every extent is even and
+// the halves stay >= 4 cells, at most 6 levels in all.  Returns the level count
+// (1: no coarse level) and the cells of the coarse levels.
+constexpr int kMaxMg = 6;
+int mg_levels(int nx, int ny, int nz, long long &coarse_cells)
+{
+    int L = 1;
+    coarse_cells = 0;
+    while (L < kMaxMg && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx >= 8 && ny >= 8 && nz >= 8) {
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+        coarse_cells += (long long)nx * ny * nz;
+        ++L;
+    }
+    return L;
+}
+
 // part_rows: partial-sum rows the sweeps of every level need (tile_bound summed);
 // amr: room for the level-jump corrections (5 planes over the composite grid, FP64 for the
 // residual and in the Krylov precision for the apply); vel: the O(v/c) coefficients of a
 // moving medium (7 FP64 planes, the 6 couplings again in the Krylov precision for the apply).
-Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false, bool vel = false)
+// mg_cells: cells of the multigrid levels below the grid (krylov_poly = 2): per coarse cell 25
+// values (sR, tensor, face speeds, E diagonal, Jacobi diagonal, right-hand side, residual,
+// correction), and per grid cell 6 more (Jacobi diagonal, the fine correction)
+Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false, bool vel = false,
+              long long mg_cells = 0)
 {
     Layout L;
     const bool mixed = p.prec == RAD_MIXED;
@@ -794,6 +900,7 @@ Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr 
     L.VCA = take(vel ? 3 * N * ksz : 0);
     L.V = take((size_t)(m + 1) * 4 * N * ksz);
     L.W = take(4 * N * ksz);
+    L.MG = take(mg_cells > 0 ? (size_t)(6 * N + 25 * mg_cells) * ksz : 0);
     // per-cell kernels of a two-level grid use one more (partial) block than the cell count gives
     L.part = take((size_t)std::max(std::max<long long>(L.nblk_cells + 2, L.nblk_vec), part_rows) * 24 * 8);
     L.small = take(512 * 8);
@@ -818,6 +925,8 @@ struct Solver {
     // of every per-cell array; each level is a complete single-grid array set)
     int nlev = 1;
     Grid gl[2];
+    int mgL = 1;          // multigrid levels (krylov_poly = 2), the grid included
+    Grid mg[kMaxMg];      // their grids (mg[0] = g)
     long long c0[2] = {0, 0};
     bool amr = false;
     Amr A{};
@@ -989,7 +1098,8 @@ int run_step(Solver &S)
                                (const double *)sR64, (const FT *)Cc, out);
         });
     };
-    auto apply = [&](const KT *x, const double *xs, KT *y, AT pg = AT(0)) {
+    auto apply = [&](const KT *x, const double *xs, KT *y, AT pg = AT(0), AT xm = AT(1), const AT *qv = nullptr,
+                     AT qm = AT(0), AT qs = AT(1), AT *dout = nullptr) {
         if (S.amr) jump(x, xs, (const AT *)Cf, corrA);
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
@@ -1001,12 +1111,13 @@ int run_step(Solver &S)
                                        tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
                                        (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                        y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)), (const AT *)VBA,
-                                       (const AT *)VCA, pg);
+                                       (const AT *)VCA, pg, xm, qv, qm, qs, dout);
                 else
                     hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
                                        tg[l], f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
                                        (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA, pg);
+                                       level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA, pg, xm,
+                                       qv, qm, qs, dout);
             };
             if (S.amr)
                 go(std::true_type{}, std::false_type{}, std::true_type{});
@@ -1017,9 +1128,136 @@ int run_step(Solver &S)
             else
                 go(std::false_type{}, std::false_type{}, std::false_type{});
         }
-        prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb));
+        // the smoothing form also reads q (4 planes), the diagonal form writes D (2 planes)
+        prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
     };
+    // ---- multigrid cycle (krylov_poly = 2): levels l >= 1 halve the grid; each carries the
+    // children's mean sR, tensor and E diagonal, its own corrected face speeds and Jacobi
+    // diagonal, and a right-hand side q, residual t and correction e.  One V-cycle with one
+    // damped Jacobi sweep (weight kOm) before and after the coarse correction and kCoarse
+    // sweeps on the coarsest level is the (fixed, linear) right preconditioner M^-1 of B.
+    // The weight is small because the scaled operator has eigenvalues far off the real axis
+    // in optically thin media, which larger weights amplify.
+    constexpr double kOm = 0.4;
+    constexpr int kCoarse = 8;
+    const int mgL = p.krylov_poly == 2 ? S.mgL : 1;
+    struct MgLev {
+        AT *sR, *f, *Cf, *dE, *D, *q, *t, *e;
+        TileGeom tg;
+    };
+    MgLev ml[kMaxMg] = {};
+    AT *mgE0 = nullptr;
+    auto mg_cells = [&](const Grid &g) { return dim3((unsigned)((g.N + kBlock - 1) / kBlock)); };
+    if (mgL > 1) {
+        AT *b = S.at<AT>(S.L.MG);
+        ml[0].D = b;
+        b += 2 * N;
+        mgE0 = b;
+        b += 4 * N;
+        ml[0].tg = tg[0];
+        for (int l = 1; l < mgL; ++l) {
+            const long long Nl = S.mg[l].N;
+            AT **dst[8] = {&ml[l].sR, &ml[l].f, &ml[l].Cf, &ml[l].dE, &ml[l].D, &ml[l].q, &ml[l].t, &ml[l].e};
+            const int planes[8] = {1, 6, 3, 1, 2, 4, 4, 4};
+            for (int u = 0; u < 8; ++u) {
+                *dst[u] = b;
+                b += planes[u] * Nl;
+            }
+            // small levels: short z-ranges, so that their few columns still give a few hundred workgroups
+            // (a sweep of one workgroup over 8 planes is latency-bound)
+            ml[l].tg = tile_geom<AT>(S.mg[l]);
+            const long long cols = (long long)ml[l].tg.tiles_x * ml[l].tg.tiles_y;
+            if (cols * ml[l].tg.tiles_z < 256) ml[l].tg = tile_geom<AT>(S.mg[l], 2);
+        }
+        S.timed(K_SETUP, Nd * (7 * kb + 1.25 * kb), [&] {
+            for (int l = 1; l < mgL; ++l) {
+                const Grid &gf = S.mg[l - 1], &gc = S.mg[l];
+                if (l == 1) {
+                    hipLaunchKernelGGL((k_mg_average<AT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 1, (const AT *)sR,
+                                       N, ml[1].sR);
+                    if (fA)
+                        hipLaunchKernelGGL((k_mg_average<AT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 6,
+                                           (const AT *)fA, N, ml[1].f);
+                    else
+                        hipLaunchKernelGGL((k_mg_average<CT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 6, f, N,
+                                           ml[1].f);
+                } else {
+                    hipLaunchKernelGGL((k_mg_average<AT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 1,
+                                       (const AT *)ml[l - 1].sR, gf.N, ml[l].sR);
+                    hipLaunchKernelGGL((k_mg_average<AT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 6,
+                                       (const AT *)ml[l - 1].f, gf.N, ml[l].f);
+                }
+                hipLaunchKernelGGL((k_mg_face<AT>), mg_cells(gc), bl, 0, S.st, gc, (const AT *)ml[l].sR,
+                                   (const AT *)ml[l].f, ml[l].Cf);
+            }
+        });
+    }
+    // the operator of level l >= 1 (same sweep as the grid's apply, coarse coefficients)
+    // (profiled as the multigrid class, so the grid's apply keeps its own class)
+    auto mg_apply = [&](int l, const AT *x, AT xm, AT *y, AT pg, const AT *qv, AT qm, AT *dout) {
+        const int tok = prof_begin(K_MG, S.st);
+        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, false, false, true>), tiles(ml[l].tg), bt, 0, S.st, S.mg[l],
+                           ml[l].tg, (const AT *)ml[l].f, (const AT *)ml[l].sR, (const AT *)nullptr,
+                           (const AT *)nullptr, (const AT *)ml[l].Cf, (const AT *)ml[l].dE, x,
+                           (const double *)nullptr, y, AT(1), AT(1), AmrLv{}, (const AT *)nullptr,
+                           (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout);
+        prof_end(tok, S.st, (double)S.mg[l].N * (8 * kb + 6 * kb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
+    };
+    // this Picard iteration's Jacobi diagonals of every level (dE changes with T*)
+    auto mg_diagonals = [&]() {
+        apply(V, nullptr, mgE0, AT(0), AT(1), nullptr, AT(0), AT(1), ml[0].D);
+        for (int l = 1; l < mgL; ++l) {
+            const Grid &gf = S.mg[l - 1], &gc = S.mg[l];
+            hipLaunchKernelGGL((k_mg_average<AT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 1,
+                               (const AT *)(l == 1 ? dEA : ml[l - 1].dE), gf.N, ml[l].dE);
+            mg_apply(l, ml[l].f, AT(1), ml[l].t, AT(0), nullptr, AT(0), ml[l].D);
+        }
+    };
+    // q_{l+1} = D_{l+1}^-1 mean(D_l t) and e = qs q + P e_c, between levels l and l+1
+    auto mg_restrict = [&](int l, const AT *t, const AT *D) {
+        const Grid &gf = S.mg[l], &gc = S.mg[l + 1];
+        S.timed(K_MG, (double)kb * (6.0 * gf.N + 6.0 * gc.N), [&] {
+            hipLaunchKernelGGL((k_mg_restrict<AT>), mg_cells(gc), bl, 0, S.st, gf, gc, t, D, (const AT *)ml[l + 1].D,
+                               ml[l + 1].q);
+        });
+    };
+    auto mg_inject = [&](int l, const AT *q, AT qs, const AT *ec, AT *e) {
+        const Grid &gf = S.mg[l], &gc = S.mg[l + 1];
+        S.timed(K_MG, (double)kb * (8.0 * gf.N + 4.0 * gc.N), [&] {
+            hipLaunchKernelGGL((k_mg_inject<AT>), mg_cells(gf), bl, 0, S.st, gf, gc, q, qs, ec, e);
+        });
+    };
+    // V-cycle on level l >= 1 for B_l e = q_l; returns the buffer holding e
+    std::function<AT *(int)> mg_cycle = [&](int l) -> AT * {
+        const Grid &g = S.mg[l];
+        if (l == mgL - 1) {   // coarsest: damped Jacobi sweeps from e = om q
+            AT *cur = ml[l].e, *nxt = ml[l].t;
+            mg_apply(l, ml[l].q, AT(kOm), cur, AT(0), ml[l].q, AT(kOm), nullptr);
+            for (int k = 1; k < kCoarse; ++k) {
+                mg_apply(l, cur, AT(1), nxt, AT(0), ml[l].q, AT(kOm), nullptr);
+                std::swap(cur, nxt);
+            }
+            return cur;
+        }
+        // t = q - B (om q): the residual after the first sweep from zero
+        mg_apply(l, ml[l].q, AT(kOm), ml[l].t, AT(1.0 / kOm), nullptr, AT(0), nullptr);
+        mg_restrict(l, ml[l].t, ml[l].D);
+        AT *ec = mg_cycle(l + 1);
+        mg_inject(l, ml[l].q, AT(kOm), ec, ml[l].e);
+        mg_apply(l, ml[l].e, AT(1), ml[l].t, AT(0), ml[l].q, AT(kOm), nullptr);
+        return ml[l].t;
+    };
+    // out = M^-1 (sx x) on the grid; xs: the device copy of the scale sx (or null for 1)
+    auto mg_precond = [&](const KT *x, const double *xs, double sx, KT *out) {
+        apply(x, xs, W, AT(1.0 / kOm), AT(kOm));   // W = q - B (om q), q = sx x
+        mg_restrict(0, W, ml[0].D);
+        AT *ec = mg_cycle(1);
+        mg_inject(0, x, AT(kOm * sx), ec, mgE0);
+        apply(mgE0, nullptr, out, AT(0), AT(1), (const AT *)x, AT(kOm), AT(sx));
+    };
+
     // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
+
     // its norm's inverse becomes the scale s_0 of V[0].
     double nrm[5];
     auto residual = [&]() -> int {
@@ -1154,6 +1392,7 @@ int run_step(Solver &S)
 
         // ---- Krylov solve of A d = r for the correction, accumulated into X.
         // Linear tolerance: eps_R relative, tightened so the last solve reaches tol.
+        if (mgL > 1) mg_diagonals();
         double beta = std::sqrt(nrm[4]);
         const double rtol = std::min(1.0, std::max(std::min(p.eps_R, 1.0), 0.1 * p.tol / std::max(res, 1e-300)));
         const double target = beta * rtol;
@@ -1170,16 +1409,21 @@ int run_step(Solver &S)
             int cols = 0;
             for (int j = 0; j < m && its < p.max_krylov; ++j) {
                 KT *vn = V + (long long)(j + 1) * stride;
-                if (poly) {   // W = (2I - B) B (s_j V_j); B (s_j V_j) parks in the slot of V_j+1
+                KT *wv = W;   // the new Krylov direction before orthogonalisation
+                if (mgL > 1) {   // w = B M^-1 (s_j V_j), formed in the slot of V_j+1
+                    mg_precond(V + (long long)j * stride, sm + SM_S + j, sv[j], W);
+                    apply(W, nullptr, vn);
+                    wv = vn;
+                } else if (poly) {   // W = (2I - B) B (s_j V_j); B (s_j V_j) parks in the slot of V_j+1
                     apply(V + (long long)j * stride, sm + SM_S + j, vn);
                     apply(vn, nullptr, W, AT(2));
                 } else {
                     apply(V + (long long)j * stride, sm + SM_S + j, W);
                 }
                 ++its;
-                multidot(j + 1, W);
+                multidot(j + 1, wv);
                 S.timed(kOrth, 4 * Nd * kb * (j + 3), [&] {
-                    launch_orth_update<KT>(j + 1, gf, S.st, V, stride, W, vn, sm + SM_DOTS, sm + SM_S, n4, part);
+                    launch_orth_update<KT>(j + 1, gf, S.st, V, stride, wv, vn, sm + SM_DOTS, sm + SM_S, n4, part);
                 });
                 S.reduce(S.L.nblk_cells, 1, 1, sm + SM_NRM, nullptr, 0, sm + SM_S + j + 1);
                 RAD_TRY(S.read(0, SM_TOTAL));
@@ -1227,12 +1471,16 @@ int run_step(Solver &S)
             }
             for (int i = 0; i < cols; ++i) cf.a[i] = y[i] * sv[i];
             if (poly) {
-                // X += (2I - B) z, z = sum_i a_i V_i formed in the slot of V_cols (not part of the combination)
+                // X += (2I - B) z or M^-1 z, z = sum_i a_i V_i formed in the slot of V_cols (not part of
+                // the combination)
                 KT *z = V + (long long)cols * stride;
                 S.timed(kUpd, 4 * Nd * kb * (cols + 1), [&] {
                     hipLaunchKernelGGL((k_combine<KT>), gf, bl, 0, S.st, z, V, stride, cols, cf, n4);
                 });
-                apply(z, nullptr, W, AT(2));
+                if (mgL > 1)
+                    mg_precond(z, nullptr, 1.0, W);
+                else
+                    apply(z, nullptr, W, AT(2));
                 Coefs one;
                 one.a[0] = 1.0;
                 S.timed(kUpd, 4 * Nd * (16 + kb),
@@ -1383,10 +1631,23 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
 
 // ------------------------------------------------------------------ C ABI
 
+// cells of the multigrid levels the configuration needs (0 unless krylov_poly = 2);
+// fails when the grid has no coarse level
+int mg_cells_for(int nx, int ny, int nz, const rad_params_t &p, long long &cells)
+{
+    cells = 0;
+    if (p.krylov_poly != 2) return RAD_OK;
+    if (mg_levels(nx, ny, nz, cells) < 2)
+        return fail(RAD_EINVAL, "krylov_poly = 2 (multigrid) needs even grid extents of at least 8 cells");
+    return RAD_OK;
+}
+
 extern "C" size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t *p)
 {
     if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
-    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz)).total;
+    long long mgc = 0;
+    if (mg_cells_for(nx, ny, nz, *p, mgc) != RAD_OK) return 0;
+    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc).total;
 }
 
 namespace {
@@ -1443,13 +1704,24 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace) % 256) return fail(RAD_EINVAL, "workspace must be 256-byte aligned");
     S.p = *p;
-    S.L = layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz));
+    long long mgc = 0;
+    RAD_TRY(mg_cells_for(nx, ny, nz, *p, mgc));
+    S.L = layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc);
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
     S.host = pinned_staging();
     if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
     S.g = make_grid(nx, ny, nz, bc, dt, dx, *p);
     S.nlev = 1;
     S.gl[0] = S.g;
+    S.mgL = 1;
+    S.mg[0] = S.g;
+    if (p->krylov_poly == 2) {
+        long long cells = 0;
+        S.mgL = mg_levels(nx, ny, nz, cells);
+        for (int l = 1; l < S.mgL; ++l)
+            S.mg[l] = make_grid(S.mg[l - 1].nx / 2, S.mg[l - 1].ny / 2, S.mg[l - 1].nz / 2, bc, dt,
+                                dx * (double)(1 << l), *p);
+    }
     S.Ntot = S.g.N;
     S.st = (hipStream_t)stream;
     S.ws = (char *)workspace;
@@ -1496,6 +1768,7 @@ extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_
 extern "C" size_t rad_workspace_bytes_moving(int nx, int ny, int nz, const rad_params_t *p)
 {
     if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
+    if (p->krylov_poly == 2) return (void)fail(RAD_EINVAL, "the moving-medium step has no multigrid Krylov operator"), 0;
     return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, true).total;
 }
 
@@ -1512,6 +1785,7 @@ extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, dou
     if (!beta) return fail(RAD_EINVAL, "beta (velocity) is NULL");
     if (p->vel_implicit && p->anderson_m > 0)
         return fail(RAD_EINVAL, "anderson_m must be 0 with vel_implicit = 1");
+    if (p->krylov_poly == 2) return fail(RAD_EINVAL, "the moving-medium step has no multigrid Krylov operator");
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace,
                         (size_t)-1, stream));
     S.L = layout(S.Ntot, *p, tile_bound(nx, ny, nz), false, true);
@@ -1538,6 +1812,7 @@ int amr_setup(const rad_amr2_t *geom, const int bc[6], double dt, double dx, con
 {
     if (!geom) return fail(RAD_EINVAL, "geometry is NULL");
     if (p && p->cv_cubic) return fail(RAD_EINVAL, "the two-level grid requires cv_cubic = 0");
+    if (p && p->krylov_poly == 2) return fail(RAD_EINVAL, "the two-level grid has no multigrid Krylov operator");
     const int nc[3] = {geom->nx, geom->ny, geom->nz};
     RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, false));
     Amr &A = S.A;
@@ -1678,8 +1953,11 @@ int autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, c
             if (m <= p->gmres_m) ms.push_back(m);
         if (std::find(ms.begin(), ms.end(), p->gmres_m) == ms.end()) ms.push_back(p->gmres_m);
         double best_t = INFINITY;
+        // Krylov operators: the multigrid one too when the caller's workspace holds its levels
+        std::vector<int> polys = {1, 0};
+        if (p->krylov_poly == 2) polys.insert(polys.begin(), 2);
         for (int m : ms)
-            for (int poly : {1, 0}) {
+            for (int poly : polys) {
                 RAD_TRY(restore());
                 Solver T;
                 RAD_TRY(init_solver(T, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p,

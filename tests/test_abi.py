@@ -161,6 +161,14 @@ def test_plan_reorder_rejects_null(rad):
 
 def test_krylov_polynomial_is_validated(rad):
     assert rad.params().krylov_poly == 1
-    assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(krylov_poly=2))) == 0
+    assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(krylov_poly=3))) == 0
     assert "krylov_poly" in rad.last_error()
     assert rad.lib.rad_workspace_bytes(8, 8, 8, ct.byref(rad.params(krylov_poly=0))) > 0
+    # multigrid: extents must halve at least once; its levels enlarge the workspace
+    mg = rad.params(krylov_poly=2)
+    assert rad.lib.rad_workspace_bytes(9, 8, 8, ct.byref(mg)) == 0 and "multigrid" in rad.last_error()
+    assert rad.lib.rad_workspace_bytes(16, 16, 16, ct.byref(mg)) > rad.lib.rad_workspace_bytes(
+        16, 16, 16, ct.byref(rad.params()))
+    assert rad.lib.rad_workspace_bytes_moving(16, 16, 16, ct.byref(mg)) == 0
+    g = rad.amr_geometry((8, 8, 8), (2, 2, 2), (6, 6, 6))
+    assert rad.lib.rad_workspace_bytes_amr2(ct.byref(g), ct.byref(mg)) == 0

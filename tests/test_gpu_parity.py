@@ -180,6 +180,26 @@ def test_step_matches_oracle(torch, rad, kind, shape, seed, prec, poly):
     _compare(out, ref, FP64_TOL if prec == "fp64" else MIXED_TOL, f"{kind}{shape}/{prec}")
 
 
+# grids whose extents halve at least once (the multigrid operator's levels, x y z: 20 -> 10 -> 5,
+# 16x8x32 -> 8x4x16, 16^3 -> 8^3 -> 4^3)
+MG_CASES = [("periodic", (20, 20, 20), 4), ("outflow", (32, 8, 16), 6), ("clumpy", (16, 16, 16), 7)]
+
+
+@pytest.mark.parametrize("kind,shape,seed", MG_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multigrid_operator_step_matches_oracle(torch, rad, kind, shape, seed, prec):
+    """krylov_poly = 2: GMRES on B times a V-cycle of re-discretised coarse levels reaches the oracle's step."""
+    _say("multigrid step", kind, shape, seed, prec)
+    d = _case(kind, shape, seed)
+    if prec == "mixed":
+        for k in ("E", "F", "T", "rho", "kP", "kR", "f"):
+            d[k] = W._f32(d[k])
+    ref = _oracle_problem(d).step(d["E"], d["F"], d["T"], tol=1e-14)
+    out = _gpu_step(torch, rad, d, prec, coef="f32" if prec == "mixed" else None, krylov_poly=2)
+    _say("  stats", out[3])
+    _compare(out, ref, FP64_TOL if prec == "fp64" else MIXED_TOL, f"mg {kind}{shape}/{prec}")
+
+
 def test_lagged_mode_matches_oracle(torch, rad):
     _say("lagged")
     d = _case("clumpy", (6, 7, 8), 5)
