@@ -300,8 +300,8 @@ def main():
                     help="relative tolerance of each linear solve (the library's default 1e-2)")
     ap.add_argument("--krylov-poly", type=int, choices=(0, 1, 2), default=None,
                     help="Krylov operator: the Jacobi-scaled B times 1: the Neumann polynomial 2I - B (the library's "
-                         "default), 0: nothing, 2: a multigrid V-cycle (default here on the precision workload; the "
-                         "scale, two-level and batched runs default to 1)")
+                         "default), 0: nothing, 2: a multigrid V-cycle (default here on the uniform grids; the "
+                         "two-level and batched runs default to 1)")
     ap.add_argument("--gmres-m", type=int, default=None,
                     help="GMRES restart length (default 8 on the grids, where orthogonalisation grows with m "
                          "while the iteration count barely changes; the library's 12 for --batched)")
@@ -316,9 +316,9 @@ def main():
     if args.gmres_m is None and not args.batched:
         args.gmres_m = 8
     if args.krylov_poly is None:
-        # the multigrid operator where it converges: the 256^3 precision workload (on the 512^3 scale
-        # workload it stalls, so that one and the two-level and batched paths use the Neumann operator)
-        args.krylov_poly = 2 if (not args.batched and args.workload == "precision") else 1
+        # the multigrid operator on the uniform grids (it falls back to the Neumann one by itself where a
+        # cycle stalls); the two-level and batched paths have only the Neumann operator
+        args.krylov_poly = 1 if (args.batched or args.workload == "amr") else 2
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (one GPU's share is "
               "the kernel at its real shape; see DESIGN.md for how the step would shard)", file=sys.stderr)

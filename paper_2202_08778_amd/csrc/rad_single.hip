@@ -1141,6 +1141,7 @@ int run_step(Solver &S)
     constexpr double kOm = 0.4;
     constexpr int kCoarse = 8;
     const int mgL = p.krylov_poly == 2 ? S.mgL : 1;
+    bool use_mg = mgL > 1;   // cleared for the rest of the step if a cycle stalls
     struct MgLev {
         AT *sR, *f, *Cf, *dE, *D, *q, *t, *e;
         TileGeom tg;
@@ -1392,7 +1393,7 @@ int run_step(Solver &S)
 
         // ---- Krylov solve of A d = r for the correction, accumulated into X.
         // Linear tolerance: eps_R relative, tightened so the last solve reaches tol.
-        if (mgL > 1) mg_diagonals();
+        if (use_mg) mg_diagonals();
         double beta = std::sqrt(nrm[4]);
         const double rtol = std::min(1.0, std::max(std::min(p.eps_R, 1.0), 0.1 * p.tol / std::max(res, 1e-300)));
         const double target = beta * rtol;
@@ -1410,7 +1411,7 @@ int run_step(Solver &S)
             for (int j = 0; j < m && its < p.max_krylov; ++j) {
                 KT *vn = V + (long long)(j + 1) * stride;
                 KT *wv = W;   // the new Krylov direction before orthogonalisation
-                if (mgL > 1) {   // w = B M^-1 (s_j V_j), formed in the slot of V_j+1
+                if (use_mg) {   // w = B M^-1 (s_j V_j), formed in the slot of V_j+1
                     mg_precond(V + (long long)j * stride, sm + SM_S + j, sv[j], W);
                     apply(W, nullptr, vn);
                     wv = vn;
@@ -1477,7 +1478,7 @@ int run_step(Solver &S)
                 S.timed(kUpd, 4 * Nd * kb * (cols + 1), [&] {
                     hipLaunchKernelGGL((k_combine<KT>), gf, bl, 0, S.st, z, V, stride, cols, cf, n4);
                 });
-                if (mgL > 1)
+                if (use_mg)
                     mg_precond(z, nullptr, 1.0, W);
                 else
                     apply(z, nullptr, W, AT(2));
@@ -1495,6 +1496,14 @@ int run_step(Solver &S)
                 std::fprintf(stderr, "[rad]   cycle: %d Arnoldi steps, estimate %.3e, true %.3e (target %.3e)\n", cols,
                              std::fabs(gvec[cols]), std::sqrt(nrm[4]), target);
             beta = std::sqrt(nrm[4]);
+            // safeguard: a V-cycle-preconditioned cycle that gains less than 10% means the cycle is not
+            // a preconditioner for this state (seen where many cells sit at the T >= 0 bound); the rest
+            // of the step runs the Neumann operator, whose cycles are tested by the loop as before
+            if (use_mg && beta > 0.9 * beta_prev) {
+                use_mg = false;
+                beta_prev = INFINITY;
+                if (trace) std::fprintf(stderr, "[rad]   multigrid cycle stalled: Neumann operator from here\n");
+            }
         }
         st.krylov_iters += its;
 
