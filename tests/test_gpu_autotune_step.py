@@ -80,3 +80,28 @@ def test_apply_forming_face_speeds_matches_oracle(torch, rad, tmp_path, monkeypa
     errs = (rel(E.cpu().numpy(), Eo), rel(F.cpu().numpy(), Fo), rel(T.cpu().numpy(), To))
     print("  formed face speeds:", prec, st["krylov_iters"], "Krylov; rel errors", errs, flush=True)
     assert max(errs) <= (1e-10 if prec == "fp64" else 1e-8)
+
+
+def test_autotune_with_multigrid_workspace_tries_the_cycle(torch, rad, tmp_path, monkeypatch):
+    """With krylov_poly = 2 (the workspace holds the multigrid levels) the restart trials include the V-cycle; the
+    recommended operator and restart length give the oracle's step."""
+    monkeypatch.setenv("VETTAM_RAD_CACHE_DIR", str(tmp_path))
+    d = W.mixed_depth(shape=(16, 16, 32), seed=21, steps=1)
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    coef = [g(d[k]) for k in ("rho", "kP", "kR", "f")]
+    p = rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], gmres_m=8, tol=1e-12, krylov_poly=2)
+    out = rad.autotune_step(E, F, T, *coef, d["dt"], d["dx"], d["bc"], p, tune_restart=True)
+    print("autotune (multigrid workspace)", out, flush=True)
+    assert out["krylov_poly"] in (0, 1, 2) and out["gmres_m"] in (6, 8)
+    for t, a in zip((E, F, T), (d["E"], d["F"], d["T"])):
+        assert np.array_equal(t.cpu().numpy(), a)
+    p.gmres_m, p.krylov_poly, p.tol = out["gmres_m"], out["krylov_poly"], 1e-13
+    rad.rad_step(E, F, T, *coef, d["dt"], d["dx"], d["bc"], p)
+    P = oracle.Problem(d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"], c=d["c"], aR=d["aR"],
+                       cv=d["cv"])
+    Eo, Fo, To, _ = P.step(d["E"], d["F"], d["T"], tol=1e-14)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    errs = (rel(E.cpu().numpy(), Eo), rel(F.cpu().numpy(), Fo), rel(T.cpu().numpy(), To))
+    print("  step with the recommendation:", errs, flush=True)
+    assert max(errs) <= 1e-10
