@@ -6,9 +6,10 @@
 //   Krylov     restarted GMRES(m) on the Jacobi-scaled system B, right-multiplied
 //              by the Neumann polynomial 2I - B by default (Arnoldi on 2B - B^2:
 //              half the iterations, so half the orthogonalisation traffic, for
-//              the same applies of B), Arnoldi in FP32 (mixed) or FP64, solution
-//              accumulated into the FP64 state; each restart re-evaluates the
-//              FP64 residual (iterative refinement)
+//              the same applies of B) or by one multigrid V-cycle of
+//              re-discretised coarse levels, Arnoldi in FP32 (mixed) or FP64,
+//              solution accumulated into the FP64 state; each restart
+//              re-evaluates the FP64 residual (iterative refinement)
 //   exchange   per-cell FP64 Newton solve of eq. PicardTemp for T
 // Every vector operation and reduction runs in the kernels below; the host
 // only keeps the (m+1) x m Hessenberg matrix and decides when to stop.
