@@ -93,8 +93,8 @@ typedef struct {
                              2: one multigrid V-cycle (levels halve the grid while every extent is
                              even and >= 8, at most 6 levels; coarse operators re-discretised on the
                              children's mean sR, tensor and E diagonal; one damped Jacobi sweep,
-                             weight 0.4, before and after each coarse correction, 8 on the coarsest
-                             level).  A GMRES cycle that gains less than 10% under the V-cycle
+                             weight 0.4, before and after each coarse correction, two on the
+                             coarsest level).  A GMRES cycle that gains less than 10% under the V-cycle
                              switches the rest of the step to the Neumann operator.  rad_step only,
                              on grids whose extents halve at least once (RAD_EINVAL otherwise); its
                              levels enlarge the workspace */

@@ -1135,12 +1135,13 @@ int run_step(Solver &S)
     // ---- multigrid cycle (krylov_poly = 2): levels l >= 1 halve the grid; each carries the
     // children's mean sR, tensor and E diagonal, its own corrected face speeds and Jacobi
     // diagonal, and a right-hand side q, residual t and correction e.  One V-cycle with one
-    // damped Jacobi sweep (weight kOm) before and after the coarse correction and kCoarse
-    // sweeps on the coarsest level is the (fixed, linear) right preconditioner M^-1 of B.
+    // damped Jacobi sweep (weight kOm) before and after the coarse correction, and kCoarse + 1
+    // sweeps from zero on the coarsest level (the first is e = om q; more did not pay at 256^3,
+    // whose coarsest level is 8^3), is the (fixed, linear) right preconditioner M^-1 of B.
     // The weight is small because the scaled operator has eigenvalues far off the real axis
     // in optically thin media, which larger weights amplify.
     constexpr double kOm = 0.4;
-    constexpr int kCoarse = 8;
+    constexpr int kCoarse = 1;
     const int mgL = p.krylov_poly == 2 ? S.mgL : 1;
     bool use_mg = mgL > 1;   // cleared for the rest of the step if a cycle stalls
     struct MgLev {
@@ -1232,7 +1233,7 @@ int run_step(Solver &S)
     // V-cycle on level l >= 1 for B_l e = q_l; returns the buffer holding e
     std::function<AT *(int)> mg_cycle = [&](int l) -> AT * {
         const Grid &g = S.mg[l];
-        if (l == mgL - 1) {   // coarsest: damped Jacobi sweeps from e = om q
+        if (l == mgL - 1) {   // coarsest: kCoarse sweeps after e = om q
             AT *cur = ml[l].e, *nxt = ml[l].t;
             mg_apply(l, ml[l].q, AT(kOm), cur, AT(0), ml[l].q, AT(kOm), nullptr);
             for (int k = 1; k < kCoarse; ++k) {
