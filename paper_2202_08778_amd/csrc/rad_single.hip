@@ -1232,7 +1232,6 @@ int run_step(Solver &S)
     };
     // V-cycle on level l >= 1 for B_l e = q_l; returns the buffer holding e
     std::function<AT *(int)> mg_cycle = [&](int l) -> AT * {
-        const Grid &g = S.mg[l];
         if (l == mgL - 1) {   // coarsest: kCoarse sweeps after e = om q
             AT *cur = ml[l].e, *nxt = ml[l].t;
             mg_apply(l, ml[l].q, AT(kOm), cur, AT(0), ml[l].q, AT(kOm), nullptr);
@@ -1260,7 +1259,6 @@ int run_step(Solver &S)
     };
 
     // FP64 residual of the current linear system at X, Jacobi-scaled, into V[0];
-
     // its norm's inverse becomes the scale s_0 of V[0].
     double nrm[5];
     auto residual = [&]() -> int {
