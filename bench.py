@@ -320,8 +320,9 @@ def main():
         # cycle stalls); the two-level and batched paths have only the Neumann operator
         args.krylov_poly = 1 if (args.batched or args.workload == "amr") else 2
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (one GPU's share is "
-              "the kernel at its real shape; see DESIGN.md for how the step would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path; a sharded step would give "
+              "each GPU a slab of the grid at this shape, with a one-plane halo exchange per operator apply",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
