@@ -243,12 +243,14 @@ def test_multi_step_mixed_depth_128_properties(torch, rad):
             assert res[3] <= 1.5e-10
 
 
-def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad):
-    """The 256^3 precision workload in the bench's configuration (FP32-exact inputs, m = 8): one mixed
-    step and one FP64 step from the same state agree within 1e-8 per field, and the mixed output meets
-    the oracle's residual definition at the requested tolerance (an implicit step has no per-cell output
-    the oracle could compute alone; its residual is the per-cell check)."""
-    _say("full size 256^3")
+@pytest.mark.parametrize("poly", [1, 2], ids=["neumann", "multigrid"])
+def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad, poly):
+    """The 256^3 precision workload (FP32-exact inputs, m = 8) with either Krylov operator, the multigrid
+    one being the bench's configuration: one mixed step and one FP64 step from the same state agree within
+    1e-8 per field, and the mixed output meets the oracle's residual definition at the requested tolerance
+    (an implicit step has no per-cell output the oracle could compute alone; its residual is the per-cell
+    check)."""
+    _say(f"full size 256^3, krylov_poly {poly}")
     d = W.mixed_depth_256(n=256, steps=1)
     P = _oracle_problem(d)
     g = lambda a, dt=None: _dev(torch, a, dt)
@@ -256,7 +258,8 @@ def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad):
     for prec in ("mixed", "fp64"):
         cd = torch.float32 if prec == "mixed" else torch.float64
         E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
-        p = _params(rad, d, prec=prec, tol=1e-10, gmres_m=8, coef_dtype=1 if prec == "mixed" else 0)
+        p = _params(rad, d, prec=prec, tol=1e-10, gmres_m=8, coef_dtype=1 if prec == "mixed" else 0,
+                    krylov_poly=poly)
         st = rad.rad_step(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd), d["dt"],
                           d["dx"], d["bc"], p)
         _say(f"  {prec}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, res {st['scaled_residual']:.2e}")
