@@ -324,7 +324,11 @@ void rad_plan_destroy(rad_plan plan);
  * Per-kernel-class timing with HIP events recorded around every launch on
  * the launch stream, plus the algorithmic bytes each launch moves (the
  * minimum HBM traffic of its inputs and outputs).  Off by default; costs
- * two event records per launch when on.  Not thread-safe. */
+ * two event records per launch when on.  Not thread-safe.
+ * on: 0 off; 1 every class timed; 2 only the operator-apply classes
+ * (apply_fp32, apply_fp64) timed, the others counted (bytes and launches,
+ * zero milliseconds) with no event on the stream, so that the step runs at
+ * close to its unprofiled speed.  Any other nonzero value acts as 1. */
 void rad_profile_enable(int on);
 void rad_profile_reset(void);
 /* Number of kernel classes with at least one timed launch. */

@@ -76,6 +76,7 @@ struct Pending {
 };
 
 static bool g_prof_on = false;
+static bool g_prof_apply_only = false;   // events around the operator applies only
 static std::vector<Pending> g_pending;
 static std::vector<hipEvent_t> g_pool;
 static double g_ms[K_NCLASS], g_bytes[K_NCLASS];
@@ -97,6 +98,14 @@ int prof_begin(int kid, hipStream_t st)
 {
     if (!g_prof_on) return -1;
     Pending p;
+    if (g_prof_apply_only && kid != K_APPLY32 && kid != K_APPLY64) {
+        // counted (bytes, launches) but not timed: no event on the stream
+        p.a = p.b = nullptr;
+        p.kid = kid;
+        p.bytes = 0;
+        g_pending.push_back(p);
+        return (int)g_pending.size() - 1;
+    }
     p.a = get_event();
     p.b = get_event();
     if (!p.a || !p.b) return -1;
@@ -115,12 +124,18 @@ void prof_end(int token, hipStream_t st, double bytes)
 {
     if (token < 0 || token >= (int)g_pending.size()) return;
     g_pending[token].bytes = bytes;
+    if (!g_pending[token].b) return;
     if (hipEventRecord(g_pending[token].b, st) != hipSuccess) g_pending[token].kid = -1;
 }
 
 void prof_resolve()
 {
     for (auto &p : g_pending) {
+        if (!p.a) {
+            g_bytes[p.kid] += p.bytes;
+            g_launch[p.kid] += 1;
+            continue;
+        }
         float ms = 0;
         if (p.kid >= 0 && hipEventSynchronize(p.b) == hipSuccess &&
             hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -136,7 +151,11 @@ void prof_resolve()
 
 }  // namespace vr
 
-extern "C" void rad_profile_enable(int on) { vr::g_prof_on = on != 0; }
+extern "C" void rad_profile_enable(int on)
+{
+    vr::g_prof_on = on != 0;
+    vr::g_prof_apply_only = on == 2;
+}
 
 extern "C" void rad_profile_reset(void)
 {

@@ -433,7 +433,8 @@ def rad_closure(E, F, kind="m1", c=1.0, out_dtype=None, f=None, stream=None):
 
 
 def profile(on=True):
-    lib.rad_profile_enable(1 if on else 0)
+    """on: False/0 off, True/1 every kernel class timed, 2 only the operator applies timed."""
+    lib.rad_profile_enable(2 if on == 2 else (1 if on else 0))
 
 
 def profile_reset():
