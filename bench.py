@@ -214,13 +214,26 @@ def bench_amr(args, torch, np, rad, W):
     p = rad.params(prec="mixed", tol=args.tol, gmres_m=args.gmres_m, coef_dtype=1, krylov_poly=args.krylov_poly)
     ws = rad.alloc_workspace(rad.workspace_bytes_amr2(geom, p))
     E, F, T = (t.clone() for t in state0)
+    share = None
     for s in range(args.warmup):
+        # the last warm-up step (from the same initial state as timed step 0) times every kernel class
+        full = not args.no_profile and s == args.warmup - 1
+        if full:
+            rad.profile(True)
+            rad.profile_reset()
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
         st = rad.rad_step_amr2(geom, E, F, T, *coefs, d["dt"], d["dx"], d["bc"], p, workspace=ws, check=False)
+        if full:
+            torch.cuda.synchronize()
+            share = (time.perf_counter() - w0, rad.profile_read())
+            rad.profile(False)
         log(f"  [amr] warmup step {s}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, "
             f"{st['t_total_ms']:.0f} ms, res {st['scaled_residual']:.2e}")
     for dst, src in zip((E, F, T), state0):
         dst.copy_(src)
-    rad.profile(not args.no_profile)
+    # timed steps: events around the operator applies only (the roofline's kernel)
+    rad.profile(2 if not args.no_profile else False)
     rad.profile_reset()
     stats, prev = [], None
     torch.cuda.synchronize()
@@ -260,8 +273,13 @@ def bench_amr(args, torch, np, rad, W):
         tot_b = sum(v["bytes"] for v in prof.values())
         res["step_roofline"] = {"achieved": tot_b / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": tot_b / sec / 1e9 / HBM_PEAK_GBS}
-        res["kernel_time_share"] = {k: v["ms"] / (sec * 1e3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
-        res["kernel_gbs"] = {k: v["bytes"] / (v["ms"] * 1e-3) / 1e9 for k, v in prof.items() if v["ms"] > 0}
+    if share:
+        # from the fully profiled warm-up step (events around every launch), not the timed steps
+        wsec, sp = share
+        res["kernel_time_share"] = {k: v["ms"] / (wsec * 1e3) for k, v in sorted(sp.items(), key=lambda kv: -kv[1]["ms"])}
+        res["kernel_gbs"] = {k: v["bytes"] / (v["ms"] * 1e-3) / 1e9 for k, v in sp.items() if v["ms"] > 0}
+        res["kernel_share_note"] = (f"one warm-up step with HIP events around every launch ({wsec * 1e3:.0f} ms); "
+                                    "the timed steps carry events around the operator applies only")
     if not args.no_oracle_check:
         log("composite oracle: residual of the last step on sampled leaf cells (jump cells included) ...")
         pb = TwoLevel(d["nc"], d["lo"], d["hi"], d["rho"], d["kP"], d["kR"], d["f"], d["dt"], d["dx"], d["bc"])
