@@ -64,8 +64,22 @@ GAS_MUTANTS = [
 ]
 
 
+# caught by the scaled-residual pins (the convergence measure and full-size checker)
+RESIDUAL_MUTANTS = [
+    ("double half = 0.5 * g->dt / g->h * sumC;", "double half = g->dt / g->h * sumC;"),
+    ("double dFn = sqrt(nF) + g->c * sqrt(nE);", "double dFn = sqrt(nF) + 10.0 * g->c * sqrt(nE);"),
+    ("*WT = gas_C(g, alpha_of(g, cf, c), T[c]) + 4.0 * sP", "*WT = gas_C(g, alpha_of(g, cf, c), T[c]) + 3.0 * sP"),
+    ("double RT = (T[c] == 0.0 && R[4][c] > 0.0) ? 0.0 : R[4][c];", "double RT = R[4][c];"),
+    ("*WF = 1.0 + s_R(g, cf, c) + half;", "*WF = 1.0 + sP + half;"),
+    ("sumC += C[d][c] + C[d][c + step(g, d)];", "sumC += 2.0 * C[d][c];"),
+    ("for (int q = 1; q < 4; ++q) rF +=", "for (int q = 0; q < 4; ++q) rF +="),
+    ("if (out[1] > out[3]) out[3] = out[1];", ";"),
+]
+
+
 CASES = ([(m, "test_oracle_pins.py") for m in MUTANTS] + [(m, "test_oracle_velocity_pins.py") for m in VEL_MUTANTS] +
-         [(m, "test_oracle_gas_pins.py") for m in GAS_MUTANTS])
+         [(m, "test_oracle_gas_pins.py") for m in GAS_MUTANTS] +
+         [(m, "test_oracle_residual_pins.py") for m in RESIDUAL_MUTANTS])
 
 
 @pytest.mark.slow
@@ -84,4 +98,7 @@ def test_pins_catch_planted_mistake(k, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", pins),
                         "-x", "-q", "-p", "no:cacheprovider", "--timeout", "20"], env=env, capture_output=True,
                        text=True, cwd=ROOT, timeout=600)
-    assert r.returncode != 0, f"mutant survived: {after}"
+    # caught = the pins ran and at least one of them failed (exit code 1 with failures in the
+    # summary); a collection or usage error (exit codes 2-5) is no catch
+    assert r.returncode == 1 and " failed" in r.stdout, (
+        f"mutant not caught (rc {r.returncode}): {after}\n{r.stdout[-2000:]}\n{r.stderr[-2000:]}")
