@@ -49,13 +49,14 @@ class _Coef(ct.Structure):
 class _Params(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("lin_rtol", ct.c_double), ("max_picard", ct.c_int),
                 ("gmres_m", ct.c_int), ("max_krylov", ct.c_int), ("mode", ct.c_int),
-                ("eps_P", ct.c_double)]
+                ("eps_P", ct.c_double), ("eps_N", ct.c_double), ("energy_fix", ct.c_int)]
 
 
 class _Stats(ct.Structure):
     _fields_ = [("picard_iters", ct.c_int), ("krylov_iters", ct.c_int), ("converged", ct.c_int),
                 ("neg_cells", ct.c_int), ("scaled_residual", ct.c_double), ("res_E", ct.c_double),
-                ("res_F", ct.c_double), ("res_T", ct.c_double), ("rel_change", ct.c_double)]
+                ("res_F", ct.c_double), ("res_T", ct.c_double), ("rel_change", ct.c_double),
+                ("energy_defect", ct.c_double), ("dE_max", ct.c_double)]
 
 
 def lib():
@@ -206,13 +207,18 @@ class Problem:
         return tuple(out)
 
     def step(self, E, F, T, tol=1e-13, mode="linearised", max_picard=200, gmres_m=100,
-             max_krylov=200000, lin_rtol=1e-12, eps_P=0.0, allow_unconverged=False):
+             max_krylov=200000, lin_rtol=1e-12, eps_P=0.0, eps_N=0.0, energy_fix=False,
+             allow_unconverged=False):
         """One implicit radiation step; returns (E, F, T, stats).  Raises if the nonlinear
-        residual neither met tol nor settled at the FP64 floor, unless allow_unconverged."""
+        residual neither met tol nor settled at the FP64 floor, unless allow_unconverged.
+        eps_P > 0 also stops on the relative change of [E, F, T]; eps_N > 0 stops each
+        per-cell Newton solve at that relative change of T; energy_fix commits the gas
+        temperature with the energy correction of Sec. 2.3.4."""
         E, F, T = self.state(E, F, T)
         p = _Params()
         p.tol, p.lin_rtol, p.max_picard = tol, lin_rtol, max_picard
         p.gmres_m, p.max_krylov, p.mode, p.eps_P = gmres_m, max_krylov, MODE[mode], eps_P
+        p.eps_N, p.energy_fix = eps_N, 1 if energy_fix else 0
         st = _Stats()
         FP = (ct.c_void_p * 3)(*(F[q].ctypes.data for q in range(3)))
         lib().or_rad_step(ct.byref(self.g), ct.byref(self.cf), ct.byref(p), E.ctypes.data, FP,

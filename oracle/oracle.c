@@ -386,7 +386,7 @@ void or_scaled_residual(const or_grid *g, const or_coef *cf, const double *En, d
  * derivative, as the paper prescribes) started above the root descends
  * monotonically onto it; it stops once an iterate no longer decreases, i.e.
  * at round-off.  The start is the smaller of the two single-term bounds. */
-double or_exchange_T(double alpha, double Tn, double sP, double aR, double E, int *neg)
+static double exchange_newton(double alpha, double Tn, double sP, double aR, double E, double eps_N, int *neg)
 {
     if (sP == 0.0) return Tn;
     double rhs = alpha * Tn + sP * E;
@@ -402,9 +402,24 @@ double or_exchange_T(double alpha, double Tn, double sP, double aR, double E, in
         double dg = alpha + 4.0 * sP * aR * T3;
         double Tnew = T - gv / dg;
         if (!(Tnew < T)) break;
+        /* the paper's stop rule: relative change of T below eps_N */
+        int done = eps_N > 0.0 && T - Tnew <= eps_N * Tnew;
         T = Tnew;
+        if (done) break;
     }
     return T;
+}
+
+double or_exchange_T(double alpha, double Tn, double sP, double aR, double E, int *neg)
+{
+    return exchange_newton(alpha, Tn, sP, aR, E, 0.0, neg);
+}
+
+/* inverse of the gas internal energy e(T) (alpha T, or alpha T^4 / 4), clamped at T = 0 */
+static double gas_T_of_e(const or_grid *g, double alpha, double e)
+{
+    if (!(e > 0.0) || !(alpha > 0.0)) return 0.0;
+    return g->cv_cubic ? sqrt(sqrt(4.0 * e / alpha)) : e / alpha;
 }
 
 /* ------------------------------------------------------------------- GMRES */
@@ -582,7 +597,7 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
     o.pre[0] = (double *)malloc(N * sizeof(double));
     o.pre[1] = (double *)malloc(N * sizeof(double));
 
-    double *bE = alloc_padded(g), *Tstar = alloc_padded(g);
+    double *bE = alloc_padded(g), *Tstar = alloc_padded(g), *dE = alloc_padded(g);
     memcpy(Tstar, Tn, np * sizeof(double)); /* the first guess is the old temperature */
     double *x[4] = {E, F[0], F[1], F[2]};
     double *y[4];
@@ -687,11 +702,42 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                             Tb += X / a;
                         else if (sP > 0)
                             Eb += X / sP;
-                        T[c] = or_exchange_T(a, Tb, sP, g->aR, Eb, &flag);
+                        T[c] = exchange_newton(a, Tb, sP, g->aR, Eb, p->eps_N, &flag);
                     }
                     neg |= flag;
                 }
         st->neg_cells = neg;
+        /* Energy correction of Sec. 2.3.4.  The radiation solve took the emission at the guess
+         * T_o = Tstar, the gas solve at its root T_N, so the two exchange terms differ by
+         * dt dE = sP (aR T_N^4 - e_rad) per cell.  e_rad is read off the radiation row: with
+         * diagonal 1 + sP (1 - eta) and right-hand side bE that row equals the plain one
+         * (1 + sP) E - E_n - sP e_rad, so sP e_rad = sP eta E + bE - E_n (eta = 0 lagged). */
+        {
+            double defect = 0.0, scale = 0.0, dmax = 0.0;
+#pragma omp parallel for reduction(+ : defect, scale) reduction(max : dmax)
+            for (int kk = 0; kk < g->nz; ++kk)
+                for (int j = 0; j < g->ny; ++j)
+                    for (int i = 0; i < g->nx; ++i) {
+                        size_t c = idx(g, i, j, kk);
+                        double sP = s_P(g, cf, c), a = alpha_of(g, cf, c), eta = 0.0;
+                        if (p->mode != OR_LAGGED) {
+                            double Ts = Tstar[c], Ts3 = Ts * Ts * Ts;
+                            double den = gas_C(g, a, Ts) + 4.0 * sP * g->aR * Ts3;
+                            eta = den > 0 ? 4.0 * sP * g->aR * Ts3 / den : 0.0;
+                        }
+                        double TN4 = T[c] * T[c] * T[c] * T[c];
+                        double dEc = sP * g->aR * TN4 - (sP * eta * E[c] + bE[c] - En[c]);
+                        if (sP == 0.0) dEc = 0.0;
+                        dE[c] = dEc;
+                        defect += dEc;
+                        scale += En[c] + gas_e(g, a, Tn[c]);
+                        double loc = fabs(E[c]) + gas_e(g, a, T[c]);
+                        double r = loc > 0 ? fabs(dEc) / loc : (dEc != 0.0 ? INFINITY : 0.0);
+                        if (r > dmax) dmax = r;
+                    }
+            st->energy_defect = scale != 0.0 ? defect / scale : defect;
+            st->dE_max = dmax;
+        }
         /* relative change of x_P = [E, F, T] over the iteration (per field, max) */
         {
             double dE2 = 0, nE2 = 0, dF2 = 0, nF2 = 0, dT2 = 0, nT2 = 0;
@@ -732,8 +778,22 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
         last_res = res[3];
     }
 
+    if (p->energy_fix) {
+        /* commit the gas energy that makes the two exchange terms cancel: e(T) = e(T_N) + dt dE,
+         * T = 0 where that energy is not positive.  Fed back into the next Picard iteration this
+         * would be the gas update alpha (T - T_n) = sP (E - e_rad), which diverges where
+         * 4 sP aR T^3 > (1 + sP) alpha; applied once at the end it only moves the committed T. */
+#pragma omp parallel for
+        for (int kk = 0; kk < g->nz; ++kk)
+            for (int j = 0; j < g->ny; ++j)
+                for (int i = 0; i < g->nx; ++i) {
+                    size_t c = idx(g, i, j, kk);
+                    double a = alpha_of(g, cf, c);
+                    if (dE[c] != 0.0) T[c] = gas_T_of_e(g, a, gas_e(g, a, T[c]) + dE[c]);
+                }
+    }
     for (int q = 0; q < 4; ++q) or_fill_ghosts(g, x[q]);
-    free(En); free(Tn); free(bE); free(Tstar); free(rhs); free(dv); free(xprev);
+    free(En); free(Tn); free(bE); free(Tstar); free(dE); free(rhs); free(dv); free(xprev);
     for (int q = 0; q < 3; ++q) free(Fn[q]);
     for (int q = 0; q < 4; ++q) { free(o.px[q]); free(o.py[q]); free(y[q]); }
     for (int d = 0; d < 3; ++d) free(o.C[d]);

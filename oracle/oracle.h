@@ -73,6 +73,9 @@ typedef struct {
     int max_krylov;    /* per linear solve */
     int mode;          /* OR_LAGGED (paper) or OR_LINEARISED */
     double eps_P;      /* if > 0: also stop when the relative change of x_P < eps_P */
+    double eps_N;      /* relative tolerance of the per-cell Newton solve (0: iterate to round-off) */
+    int energy_fix;    /* 1: commit the gas temperature with the energy correction of Sec. 2.3.4 (see
+                          or_rad_step); 0: commit the last Newton root */
 } or_params;
 
 typedef struct {
@@ -83,6 +86,11 @@ typedef struct {
     double scaled_residual;
     double res_E, res_F, res_T;
     double rel_change;
+    /* energy correction of Sec. 2.3.4 in the last Picard iteration, per cell
+     * dt dE = sP (aR T_N^4 - e_rad): T_N the Newton root, e_rad the emission the radiation
+     * solve used (aR T_o^4 in the lagged mode, its linearisation about T_o otherwise) */
+    double energy_defect;  /* sum dt dE / sum (E_n + e(T_n)) */
+    double dE_max;         /* max over cells of |dt dE| / (|E| + e(T_N)) */
 } or_stats;
 
 /* Fill the ghost layer of one padded field by the face boundary conditions
@@ -119,7 +127,9 @@ void or_scaled_residual(const or_grid *g, const or_coef *cf,
 double or_exchange_T(double alpha, double Tn, double sP, double aR, double E, int *neg);
 
 /* One implicit radiation step.  On entry E, F, T hold the old state (their
- * ghosts hold Dirichlet data where used); on exit they hold the new state. */
+ * ghosts hold Dirichlet data where used); on exit they hold the new state.
+ * With p->energy_fix the committed gas energy is e(T_N) + dt dE (see or_stats),
+ * so that the exchange terms of the radiation and gas equations cancel. */
 int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                 double *E, double *const F[3], double *T, or_stats *st);
 

@@ -77,9 +77,20 @@ RESIDUAL_MUTANTS = [
 ]
 
 
+# caught by the energy-correction pins (Sec. 2.3.4)
+ENERGY_MUTANTS = [
+    ("double dEc = sP * g->aR * TN4 - (sP * eta * E[c] + bE[c] - En[c]);",
+     "double dEc = sP * g->aR * TN4 - (bE[c] - En[c]);"),
+    ("T[c] = gas_T_of_e(g, a, gas_e(g, a, T[c]) + dE[c]);", "T[c] = gas_T_of_e(g, a, gas_e(g, a, T[c]) - dE[c]);"),
+    ("scale += En[c] + gas_e(g, a, Tn[c]);", "scale += En[c];"),
+    ("return g->cv_cubic ? sqrt(sqrt(4.0 * e / alpha)) : e / alpha;", "return g->cv_cubic ? sqrt(sqrt(e / alpha)) : e / alpha;"),
+]
+
+
 CASES = ([(m, "test_oracle_pins.py") for m in MUTANTS] + [(m, "test_oracle_velocity_pins.py") for m in VEL_MUTANTS] +
          [(m, "test_oracle_gas_pins.py") for m in GAS_MUTANTS] +
-         [(m, "test_oracle_residual_pins.py") for m in RESIDUAL_MUTANTS])
+         [(m, "test_oracle_residual_pins.py") for m in RESIDUAL_MUTANTS] +
+         [(m, "test_oracle_energy_pins.py") for m in ENERGY_MUTANTS])
 
 
 @pytest.mark.slow
