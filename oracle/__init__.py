@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.environ.get("VETTAM_ORACLE_SO") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
+BC = {"periodic": 0, "outflow": 1, "dirichlet": 2, "open": 3, "marshak": 4, "reflect": 5}
 MODE = {"lagged": 0, "linearised": 1}
 
 
@@ -38,7 +38,8 @@ def build() -> str:
 class _Grid(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
                 ("h", ct.c_double), ("dt", ct.c_double), ("c", ct.c_double),
-                ("aR", ct.c_double), ("cv", ct.c_double), ("bc", ct.c_int * 6), ("cv_cubic", ct.c_int)]
+                ("aR", ct.c_double), ("cv", ct.c_double), ("bc", ct.c_int * 6), ("cv_cubic", ct.c_int),
+                ("finc", ct.c_double * 6)]
 
 
 class _Coef(ct.Structure):
@@ -68,6 +69,9 @@ def lib():
         L = ct.CDLL(_SO)
         P = ct.c_void_p
         L.or_fill_ghosts.argtypes = [ct.POINTER(_Grid), P]
+        L.or_fill_tensor_ghosts.argtypes = [ct.POINTER(_Grid), ct.POINTER(P)]
+        L.or_fill_state_ghosts.argtypes = [ct.POINTER(_Grid), ct.POINTER(_Coef), ct.POINTER(P), ct.c_void_p,
+                                           ct.c_int]
         L.or_face_speeds.argtypes = [ct.POINTER(_Grid), ct.POINTER(_Coef), P, P, P]
         L.or_apply.argtypes = [ct.POINTER(_Grid), ct.POINTER(_Coef), P, ct.POINTER(P), ct.POINTER(P)]
         L.or_residual.argtypes = [ct.POINTER(_Grid), ct.POINTER(_Coef), P, ct.POINTER(P), P, P,
@@ -119,10 +123,13 @@ class Problem:
     """Grid, constants and coefficient fields of one implicit step (padded internally)."""
 
     def __init__(self, rho, kP, kR, f, dt, dx, bc="periodic", c=1.0, aR=1.0, cv=1.0, padded=False, beta=None,
-                 vel_implicit=False, cv_cubic=False):
+                 vel_implicit=False, cv_cubic=False, finc=None):
         """beta: gas velocity over c, shape (3,) + field shape (None: v = 0); vel_implicit: the O(v/c)
         gas-energy term implicit (else left to the explicit hydro update, the paper's default);
-        cv_cubic: heat capacity rho cv T^3 (E_int = rho cv T^4 / 4) instead of rho cv."""
+        cv_cubic: heat capacity rho cv T^3 (E_int = rho cv T^4 / 4) instead of rho cv.
+        bc: one kind for all faces, three (per axis) or six (-x,+x,-y,+y,-z,+z) of periodic,
+        outflow, dirichlet, open, marshak, reflect; finc: the incident flux of each Marshak face
+        (six values, or one for all)."""
         self.padded = padded
         P = (lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64))) if padded else _pad
         self.rho, self.kP, self.kR = P(rho), P(kP), P(kR)
@@ -136,11 +143,15 @@ class Problem:
         for i, code in enumerate(_bc_codes(bc)):
             g.bc[i] = code
         g.cv_cubic = 1 if cv_cubic else 0
+        fi = [0.0] * 6 if finc is None else ([float(finc)] * 6 if np.isscalar(finc) else [float(v) for v in finc])
+        for i in range(6):
+            g.finc[i] = fi[i]
         self.g = g
         self.c, self.aR, self.cv, self.dt, self.dx = float(c), float(aR), float(cv), float(dt), float(dx)
         L = lib()
-        for a in (self.rho, self.kP, self.kR, *self.f, *(self.beta if self.beta is not None else ())):
+        for a in (self.rho, self.kP, self.kR, *(self.beta if self.beta is not None else ())):
             L.or_fill_ghosts(ct.byref(g), a.ctypes.data)
+        L.or_fill_tensor_ghosts(ct.byref(g), (ct.c_void_p * 6)(*(self.f[q].ctypes.data for q in range(6))))
         cf = _Coef()
         cf.rho, cf.kP, cf.kR = self.rho.ctypes.data, self.kP.ctypes.data, self.kR.ctypes.data
         for q in range(6):
@@ -169,8 +180,8 @@ class Problem:
     def apply(self, x, dE):
         """y = dE*E + (dt/h) div Phi (E rows), (1+sR) F + (dt/h) div Phi (F rows).
 
-        x: (4, nz, ny, nx) interior (ghosts filled by the face conditions, with
-        Dirichlet ghosts zero) unless the problem is padded, in which case x is
+        x: (4, nz, ny, nx) interior (ghosts filled as for the linear operator: the face
+        conditions with their data dropped) unless the problem is padded, in which case x is
         padded and its ghosts are used as given."""
         if self.padded:
             xp = np.array(x, dtype=np.float64, copy=True)
@@ -178,8 +189,8 @@ class Problem:
         else:
             xp = _pad(x)
             dEp = _pad(dE)
-            for q in range(4):
-                lib().or_fill_ghosts(ct.byref(self.g), xp[q].ctypes.data)
+            XG = (ct.c_void_p * 4)(*(xp[q].ctypes.data for q in range(4)))
+            lib().or_fill_state_ghosts(ct.byref(self.g), ct.byref(self.cf), XG, None, 1)
         yp = np.zeros_like(xp)
         XP = (ct.c_void_p * 4)(*(xp[q].ctypes.data for q in range(4)))
         YP = (ct.c_void_p * 4)(*(yp[q].ctypes.data for q in range(4)))

@@ -64,7 +64,7 @@ static double *alloc_padded(const or_grid *g)
 
 /* ----------------------------------------------------------- ghost layers */
 
-/* Fill one face's ghost layer.  face = 2*d + side (side 0: low, 1: high). */
+/* Fill one face's ghost layer of a coefficient field.  face = 2*d + side (side 0: low, 1: high). */
 static void fill_face(const or_grid *g, double *a, int face, int zero_dirichlet)
 {
     int d = face / 2, side = face % 2;
@@ -95,10 +95,74 @@ void or_fill_ghosts(const or_grid *g, double *a)
     for (int f = 0; f < 6; ++f) fill_face(g, a, f, 0);
 }
 
-/* ghosts of a Krylov correction: Dirichlet data is not part of the linear operator */
-static void fill_ghosts_linear(const or_grid *g, double *a)
+/* component index of the symmetric tensor f_{ab} in the (xx,yy,zz,xy,xz,yz) order */
+static int tens(int a, int b);
+
+void or_fill_tensor_ghosts(const or_grid *g, double *const f[6])
 {
-    for (int f = 0; f < 6; ++f) fill_face(g, a, f, 1);
+    for (int q = 0; q < 6; ++q) or_fill_ghosts(g, f[q]);
+    int n[3] = {g->nx, g->ny, g->nz};
+    for (int face = 0; face < 6; ++face) {
+        if (g->bc[face] != OR_REFLECT) continue;
+        int d = face / 2, side = face % 2, a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        for (int q2 = 0; q2 < n[a2]; ++q2)
+            for (int q1 = 0; q1 < n[a1]; ++q1) {
+                int gh[3];
+                gh[a1] = q1;
+                gh[a2] = q2;
+                gh[d] = side ? n[d] : -1;
+                size_t gi = (size_t)(gh[0] + 1) + (size_t)(g->nx + 2) * ((size_t)(gh[1] + 1) + (size_t)(g->ny + 2) * (size_t)(gh[2] + 1));
+                for (int j = 0; j < 3; ++j)
+                    if (j != d) f[tens(d, j)][gi] = -f[tens(d, j)][gi];
+            }
+    }
+}
+
+void or_fill_state_ghosts(const or_grid *g, const or_coef *cf, double *const x[4], double *const xo[4],
+                          int linear)
+{
+    int n[3] = {g->nx, g->ny, g->nz};
+    for (int face = 0; face < 6; ++face) {
+        int kind = g->bc[face];
+        int d = face / 2, side = face % 2, a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        /* sign of the incoming direction along d: +1 at the low face, -1 at the high one */
+        double sin_ = side ? -1.0 : 1.0;
+        for (int q2 = 0; q2 < n[a2]; ++q2)
+            for (int q1 = 0; q1 < n[a1]; ++q1) {
+                int gh[3], src[3];
+                gh[a1] = src[a1] = q1;
+                gh[a2] = src[a2] = q2;
+                gh[d] = side ? n[d] : -1;
+                if (kind == OR_PERIODIC)
+                    src[d] = side ? 0 : n[d] - 1;
+                else
+                    src[d] = side ? n[d] - 1 : 0;
+                size_t gi = idx(g, gh[0], gh[1], gh[2]), c = idx(g, src[0], src[1], src[2]);
+                if (kind == OR_PERIODIC || kind == OR_OUTFLOW) {
+                    for (int q = 0; q < 4; ++q) x[q][gi] = x[q][c];
+                } else if (kind == OR_DIRICHLET) {
+                    if (linear)
+                        for (int q = 0; q < 4; ++q) x[q][gi] = 0.0;
+                } else if (kind == OR_OPEN) {
+                    double fdd = cf->f[d][c];
+                    for (int q = 0; q < 4; ++q) x[q][gi] = x[q][c];
+                    if (fdd > 0.0) {
+                        double a = g->c * sqrt(fdd);
+                        double in_now = 0.5 * (x[0][c] + sin_ * x[1 + d][c] / a);
+                        double in_old = (linear || !xo) ? 0.0 : 0.5 * (xo[0][c] + sin_ * xo[1 + d][c] / a);
+                        double delta = in_old - in_now;
+                        x[0][gi] += delta;
+                        for (int j = 0; j < 3; ++j) x[1 + j][gi] += delta * sin_ * g->c * g->c * cf->f[tens(d, j)][c] / a;
+                    }
+                } else if (kind == OR_MARSHAK) {
+                    for (int q = 1; q < 4; ++q) x[q][gi] = x[q][c];
+                    x[0][gi] = (linear ? 0.0 : 8.0 * g->finc[face] / g->c) - 4.0 * sin_ * x[1 + d][c] / g->c - x[0][c];
+                } else if (kind == OR_REFLECT) {
+                    for (int q = 0; q < 4; ++q) x[q][gi] = x[q][c];
+                    x[1 + d][gi] = -x[1 + d][c];
+                }
+            }
+    }
 }
 
 /* ------------------------------------------------------ local coefficients */
@@ -296,7 +360,8 @@ void or_residual(const or_grid *g, const or_coef *cf, const double *En, double *
                  const double *Tn, double *E, double *const F[3], const double *T, double *const R[5])
 {
     double *x[4] = {E, F[0], F[1], F[2]};
-    for (int q = 0; q < 4; ++q) or_fill_ghosts(g, x[q]);
+    double *xo[4] = {(double *)En, Fn[0], Fn[1], Fn[2]};
+    or_fill_state_ghosts(g, cf, x, xo, 0);
     double *dE = alloc_padded(g);
 #pragma omp parallel for
     for (int k = 0; k < g->nz; ++k)
@@ -481,7 +546,7 @@ static void lin_apply_prec(lin_ctx *o, const double *v, double *out)
     to_physical(o, u);
     unpack(o, u, o->px);
     free(u);
-    for (int q = 0; q < 4; ++q) fill_ghosts_linear(o->g, o->px[q]);
+    or_fill_state_ghosts(o->g, o->cf, o->px, NULL, 1);
     transport_apply(o->g, o->cf, (const double *const *)o->C, o->dE, o->px, o->py, o->vscale);
     pack(o, o->py, out);
     to_scaled(o, out);
@@ -600,6 +665,7 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
     double *bE = alloc_padded(g), *Tstar = alloc_padded(g), *dE = alloc_padded(g);
     memcpy(Tstar, Tn, np * sizeof(double)); /* the first guess is the old temperature */
     double *x[4] = {E, F[0], F[1], F[2]};
+    double *xo_state[4] = {En, Fn[0], Fn[1], Fn[2]};
     double *y[4];
     for (int q = 0; q < 4; ++q) y[q] = alloc_padded(g);
     double *rhs = (double *)malloc(4 * N * sizeof(double));
@@ -647,8 +713,8 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                         o.pre[1][n] = 1.0 / (1.0 + s_R(g, cf, c) + 0.5 * lam * sumC);
                     }
         }
-        /* residual of the linear system at the current iterate (Dirichlet data in ghosts) */
-        for (int q = 0; q < 4; ++q) or_fill_ghosts(g, x[q]);
+        /* residual of the linear system at the current iterate (boundary data in the ghosts) */
+        or_fill_state_ghosts(g, cf, x, xo_state, 0);
         transport_apply(g, cf, (const double *const *)o.C, o.dE, x, y, o.vscale);
         {
             size_t n = 0;
@@ -792,7 +858,7 @@ int or_rad_step(const or_grid *g, const or_coef *cf, const or_params *p,
                     if (dE[c] != 0.0) T[c] = gas_T_of_e(g, a, gas_e(g, a, T[c]) + dE[c]);
                 }
     }
-    for (int q = 0; q < 4; ++q) or_fill_ghosts(g, x[q]);
+    or_fill_state_ghosts(g, cf, x, xo_state, 0);
     free(En); free(Tn); free(bE); free(Tstar); free(dE); free(rhs); free(dv); free(xprev);
     for (int q = 0; q < 3; ++q) free(Fn[q]);
     for (int q = 0; q < 4; ++q) { free(o.px[q]); free(o.py[q]); free(y[q]); }

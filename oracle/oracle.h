@@ -38,7 +38,8 @@
 extern "C" {
 #endif
 
-enum { OR_PERIODIC = 0, OR_OUTFLOW = 1, OR_DIRICHLET = 2 };
+/* Face boundary kinds (see or_fill_state_ghosts for what each puts in the ghost cell). */
+enum { OR_PERIODIC = 0, OR_OUTFLOW = 1, OR_DIRICHLET = 2, OR_OPEN = 3, OR_MARSHAK = 4, OR_REFLECT = 5 };
 enum { OR_LAGGED = 0, OR_LINEARISED = 1 };
 
 typedef struct {
@@ -50,6 +51,7 @@ typedef struct {
     double cv;     /* gas heat capacity per unit mass: alpha = rho * cv */
     int bc[6];     /* faces -x,+x,-y,+y,-z,+z */
     int cv_cubic;  /* 0: E_int = alpha T; 1: C_v = alpha T^3, E_int = alpha T^4 / 4 (the Marshak-wave gas) */
+    double finc[6];/* OR_MARSHAK faces: the incident flux F_inc (Sec. 3.4) */
 } or_grid;
 
 /* Padded input fields (see header comment). f holds xx,yy,zz,xy,xz,yz.
@@ -93,10 +95,31 @@ typedef struct {
     double dE_max;         /* max over cells of |dt dE| / (|E| + e(T_N)) */
 } or_stats;
 
-/* Fill the ghost layer of one padded field by the face boundary conditions
- * (periodic: wrap, outflow: copy of the adjacent interior cell, Dirichlet:
- * untouched). */
+/* Fill the ghost layer of one padded coefficient field by the face boundary
+ * conditions (periodic: wrap; Dirichlet: untouched; every other kind: copy of
+ * the adjacent interior cell). */
 void or_fill_ghosts(const or_grid *g, double *a);
+
+/* The same for the six tensor planes; at a reflecting face the components
+ * f_dj (j != d) of the mirrored cell change sign. */
+void or_fill_tensor_ghosts(const or_grid *g, double *const f[6]);
+
+/* Ghost cells of the radiation state x = (E, Fx, Fy, Fz), by face kind:
+ *   periodic   wrap;
+ *   outflow    zero gradient (Sec. 3.3): the ghost is the boundary cell;
+ *   Dirichlet  data (left as given), or 0 for the linear operator;
+ *   open       characteristic outflow: the boundary cell's state with the
+ *              amplitude of the incoming characteristic of the d-flux
+ *              (speed c sqrt(f_dd), left eigenvector (1/2, +-e_d / (2 c sqrt(f_dd))))
+ *              replaced by its value in the old state xo (0 for the linear operator);
+ *   Marshak    c E_w + 2 F_w,in = 4 F_inc at the wall (Sec. 3.4) with E_w, F_w the
+ *              means of ghost and cell and F_in the flux component into the domain:
+ *              F_ghost = F_cell, E_ghost = 8 F_inc / c -+ 4 F_d,cell / c - E_cell
+ *              (F_inc dropped for the linear operator);
+ *   reflect    mirror: E and the tangential F copied, F_d negated.
+ * linear != 0 fills the ghosts of the linear operator (the affine parts dropped). */
+void or_fill_state_ghosts(const or_grid *g, const or_coef *cf, double *const x[4], double *const xo[4],
+                          int linear);
 
 /* Corrected HLLE wave speed at all low faces: Cd[index(i,j,k)] is the speed
  * of the face between cell (i,j,k) - e_d and (i,j,k), for i_d in [0, n_d].

@@ -1,12 +1,16 @@
-"""Why the large mixed-depth workloads use periodic boundaries.
+"""Why the large mixed-depth workloads use the open (characteristic) boundary.
 
 The zero-gradient outflow condition (Sec. 3.3) read implicitly -- the ghost cell equals the
 current boundary cell -- makes the boundary face flux the cell's own physical flux, which couples
-E and F of that cell with weight nu/2 and no dissipation.  With dt of tens of light-crossing
-times and thick/thin contrast at the boundary, the Jacobi-scaled operator of one Picard iteration
-then has eigenvalues with negative real part (a growing boundary mode).  The same medium with
-periodic faces, or with outflow faces at a few crossing times, is positive definite in that
-sense.  Dense operators are assembled from the oracle's apply on a 6^3 grid."""
+E and F of that cell with weight nu/2 and no dissipation.  In the characteristic variables of the
+d-flux that boundary block is (C I + a J)/2 (a = c sqrt(f_dd), J the swap), whose eigenvalues
+(C -+ a)/2 have one negative sign wherever the corrected speed C is below a, i.e. in every
+optically thick boundary cell.  With dt of tens of light-crossing times the Jacobi-scaled operator
+of one Picard iteration then has eigenvalues with negative real part (a growing boundary mode).
+The open reading holds the incoming characteristic at its old value, which turns that block into
+diag((a + C)/2, C): positive for any dt.  Periodic faces, and outflow faces at a few crossing
+times, are positive definite in that sense too.  Dense operators are assembled from the oracle's
+apply on a 6^3 grid."""
 import numpy as np
 import pytest
 
@@ -31,7 +35,8 @@ def _min_real_eig(d):
 
 
 @pytest.mark.parametrize("bc,dt_cross,stable", [("outflow", 50.0, False), ("periodic", 50.0, True),
-                                                ("outflow", 2.0, True)])
+                                                ("outflow", 2.0, True), ("open", 2.0, True), ("open", 50.0, True),
+                                                ("open", 200.0, True), ("open", 1e4, True)])
 def test_implicit_outflow_operator_definiteness(bc, dt_cross, stable):
     d = W.mixed_depth(shape=(6, 6, 6), seed=2, steps=1, bc=bc, dt_cross=dt_cross)
     lam = _min_real_eig(d)

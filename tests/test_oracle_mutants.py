@@ -87,10 +87,23 @@ ENERGY_MUTANTS = [
 ]
 
 
+# caught by the boundary pins (open, Marshak, reflecting faces)
+BOUNDARY_MUTANTS = [
+    ("double in_now = 0.5 * (x[0][c] + sin_ * x[1 + d][c] / a);", "double in_now = 0.5 * (x[0][c] - sin_ * x[1 + d][c] / a);"),
+    ("x[1 + j][gi] += delta * sin_ * g->c * g->c * cf->f[tens(d, j)][c] / a;",
+     "x[1 + j][gi] += delta * sin_ * g->c * cf->f[tens(d, j)][c] / a;"),
+    ("x[0][gi] = (linear ? 0.0 : 8.0 * g->finc[face] / g->c) - 4.0 * sin_", "x[0][gi] = (linear ? 0.0 : 4.0 * g->finc[face] / g->c) - 4.0 * sin_"),
+    ("- 4.0 * sin_ * x[1 + d][c] / g->c - x[0][c];", "+ 4.0 * sin_ * x[1 + d][c] / g->c - x[0][c];"),
+    ("x[1 + d][gi] = -x[1 + d][c];", "x[1 + d][gi] = x[1 + d][c];"),
+    ("if (j != d) f[tens(d, j)][gi] = -f[tens(d, j)][gi];", "if (j != d) f[tens(d, j)][gi] = f[tens(d, j)][gi];"),
+]
+
+
 CASES = ([(m, "test_oracle_pins.py") for m in MUTANTS] + [(m, "test_oracle_velocity_pins.py") for m in VEL_MUTANTS] +
          [(m, "test_oracle_gas_pins.py") for m in GAS_MUTANTS] +
          [(m, "test_oracle_residual_pins.py") for m in RESIDUAL_MUTANTS] +
-         [(m, "test_oracle_energy_pins.py") for m in ENERGY_MUTANTS])
+         [(m, "test_oracle_energy_pins.py") for m in ENERGY_MUTANTS] +
+         [(m, "test_oracle_boundary_pins.py") for m in BOUNDARY_MUTANTS])
 
 
 @pytest.mark.slow
