@@ -56,7 +56,15 @@ typedef enum {
     RAD_EDATA = -5     /* invalid coefficient data found on the device */
 } rad_status;
 
-typedef enum { RAD_BC_PERIODIC = 0, RAD_BC_OUTFLOW = 1, RAD_BC_DIRICHLET = 2 } rad_bc_kind;
+/* Face kinds (see rad_step for what each does at a wall). */
+typedef enum {
+    RAD_BC_PERIODIC = 0,
+    RAD_BC_OUTFLOW = 1,    /* zero-gradient outflow (Sec. 3.3): the ghost is the boundary cell */
+    RAD_BC_DIRICHLET = 2,  /* fixed ghost data: the batched blocks */
+    RAD_BC_OPEN = 3,       /* characteristic outflow: incoming characteristic held at its old value */
+    RAD_BC_MARSHAK = 4,    /* c E + 2 F_in = 4 F_inc at the wall (Sec. 3.4), F_inc in params->F_inc */
+    RAD_BC_REFLECT = 5     /* mirror */
+} rad_bc_kind;
 typedef enum { RAD_FP64 = 0, RAD_MIXED = 1 } rad_precision;
 typedef enum { RAD_PICARD_LAGGED = 0, RAD_PICARD_LINEARISED = 1 } rad_picard_mode;
 typedef enum { RAD_F64 = 0, RAD_F32 = 1 } rad_dtype;
@@ -98,6 +106,15 @@ typedef struct {
                              switches the rest of the step to the Neumann operator.  rad_step only,
                              on grids whose extents halve at least once (RAD_EINVAL otherwise); its
                              levels enlarge the workspace */
+    double F_inc[6];      /* incident flux of each RAD_BC_MARSHAK face (-x,+x,-y,+y,-z,+z); ignored elsewhere */
+    double eps_N;         /* relative tolerance of the per-cell Newton solve of eq. PicardTemp (Sec. 2.3.4);
+                             0 (default): iterate to round-off */
+    int energy_fix;       /* 0 (default): commit T as the last Newton root.  1: commit the gas energy
+                             e(T_N) + dt dE of the energy correction of Sec. 2.3.4 (see rad_stats_t), so the
+                             exchange terms of the radiation and gas equations cancel and the step conserves
+                             energy for any eps_P.  rad_step only, with anderson_m = 0 */
+    int max_refine;       /* most FP64 residual evaluations (GMRES restarts) per linear solve; 0: no limit
+                             beyond max_krylov */
 } rad_params_t;
 
 typedef struct {
@@ -114,19 +131,40 @@ typedef struct {
     double res_T;          /* || R_T / W_T || / ||T||,  W_T = alpha + 4 sP aR T^3 */
     double rel_change;     /* relative change of [E, F, T] over the last Picard iteration */
     double t_total_ms;     /* wall time of the call (host clock) */
+    /* Energy correction of Sec. 2.3.4 in the last Picard iteration: the radiation solve took the
+     * emission e_rad at the guess T_o (aR T_o^4 lagged, its linearisation about T_o linearised),
+     * the gas solve at its root T_N, so per cell the exchange terms differ by
+     * dt dE = sP (aR T_N^4 - e_rad).  Zero at the solution.  Single-grid steps only (0 elsewhere). */
+    double energy_defect;  /* sum dt dE / sum (E_n + e(T_n)): the relative energy the mismatch creates */
+    double dE_max;         /* max over cells of |dt dE| / (|E| + e(T_N)) */
+    double bytes_moved;    /* algorithmic HBM bytes of the step's kernels (inputs and outputs once each) */
 } rad_stats_t;
 
 /* Fill *p with defaults: c = aR = cv = 1, tol 1e-10, eps_R 1e-2, eps_P 0,
  * max_picard 50, max_krylov 20000, gmres_m 12, FP64, linearised, FP64 coefficients,
- * anderson_m 0, vel_implicit 0, cv_cubic 0, krylov_poly 1. */
+ * anderson_m 0, vel_implicit 0, cv_cubic 0, krylov_poly 1, F_inc 0, eps_N 0,
+ * energy_fix 0, max_refine 0. */
 void rad_default_params(rad_params_t *p);
 
 /* Device workspace (bytes) rad_step needs for an nx*ny*nz grid. */
 size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t *p);
 
 /* One implicit radiation step on a uniform grid (Sec. 2.3.1 steps iv-vi).
- * bc[6]: faces -x,+x,-y,+y,-z,+z, each RAD_BC_PERIODIC (in pairs) or
- * RAD_BC_OUTFLOW (zero-gradient ghost, Sec. 3.3).  dt > 0, dx > 0.
+ * bc[6]: faces -x,+x,-y,+y,-z,+z, each RAD_BC_PERIODIC (in pairs) or one of
+ * the walls, whose ghost cell (coefficients: the boundary cell's) holds
+ *   RAD_BC_OUTFLOW  the boundary cell's state (zero gradient, Sec. 3.3): uniform states
+ *                   stay uniform, but where the corrected speed is below c sqrt(f_dd)
+ *                   (optically thick boundary cells) the wall's block is indefinite, so
+ *                   at tens of light-crossing times the step may not be well posed;
+ *   RAD_BC_OPEN     the boundary cell's state with the amplitude of the incoming
+ *                   characteristic of the normal flux, (E +- F_d / (c sqrt(f_dd))) / 2, held
+ *                   at its value at the start of the step: well posed at any dt;
+ *                   stationary states at the wall are kept, a streaming pulse leaves
+ *                   without reflection;
+ *   RAD_BC_MARSHAK  F = F_cell, E = 8 F_inc / c -+ 4 F_d,cell / c - E_cell, so that the
+ *                   means of ghost and cell satisfy c E + 2 F_in = 4 F_inc (Sec. 3.4);
+ *   RAD_BC_REFLECT  the mirror image (F_d and the tensor's f_dj, j != d, negated).
+ * dt > 0, dx > 0.
  * workspace: device memory of at least rad_workspace_bytes(), 256-byte aligned.
  * stats: host pointer, may be NULL.  The call returns after the step completed. */
 int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,

@@ -9,11 +9,13 @@
 // and each load has two planes of work to arrive (the halo rows are read by the
 // neighbouring tile too and hit in L2, since tiles are assigned to XCDs in
 // contiguous ranges).  Every LDS slot and every z neighbour is first mapped
-// through the boundary rule (periodic: wrap, outflow: the boundary cell
+// through the boundary rule (periodic: wrap, any wall: the boundary cell
 // itself), so boundary faces and ragged tile edges need no special cases: a
-// face whose mapped neighbour is the cell itself carries the cell's physical
-// flux and no dissipation.  The per-cell epilogue is a functor: the Krylov
-// operator apply and the FP64 residual of one Picard iteration share the sweep.
+// zero-gradient wall's face carries the cell's physical flux and no
+// dissipation; at an open, Marshak or reflecting wall the cell's own values are
+// then replaced by the wall's ghost (a per-lane branch taken by boundary lanes
+// only).  The per-cell epilogue is a functor: the Krylov operator apply and
+// the FP64 residual of one Picard iteration share the sweep.
 #pragma once
 #include "rad_device.h"
 #include "rad_amr.h"
@@ -111,25 +113,30 @@ struct Rec {
 };
 
 // Transport sums of one cell: dEs = sum_faces +-PhiE, dF likewise (without the
-// factor nu), the face speeds of the non-self faces (Jacobi diagonal) and of
-// all six faces (residual weights; a self face takes the cell's own speed).
+// factor nu), the face speeds of the faces between two cells (Jacobi diagonal)
+// and of all six faces (residual weights; a wall face takes the cell's own
+// speed), and the walls' own shares of the Jacobi diagonal per row (wE, wF;
+// zero away from open, Marshak and reflecting walls).
 template <class AT>
 struct CellSums {
-    AT Ec, Fc[3], sc, dEs, dF[3], sumC_nb, sumC_all;
+    AT Ec, Fc[3], sc, dEs, dF[3], sumC_nb, sumC_all, wE, wF[3];
 };
 
 // The sweep.  PRE: sR is precomputed, otherwise derived from rho and kR.  CST
 // (PRE only): the low-face speeds Cf (divided by c, planes x|y|z) are
 // precomputed too; otherwise each face's speed is formed from f and sR.
 // lex(k, pb, o, e) loads the NE per-cell extras of the epilogue (plane k, its
-// base pb, in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell.
+// base pb, in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell;
+// wall(kind, d, side, Ec, Fc, fcr, e, En, Fn, fnr) overwrites the neighbour
+// values across an open, Marshak or reflecting wall with the wall's ghost.
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
-template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, class LEX, class EPI>
+template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, class LEX, class EPI, class WALL>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
                                            const AT *__restrict__ x, AT s, AT sF,
-                                           AT (&lds)[2][Rec<CST>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi)
+                                           AT (&lds)[2][Rec<CST>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi,
+                                           WALL wall)
 {
     constexpr int TYT = TileShape<AT>::TYT, CPT = TileShape<AT>::CPT;
     constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
@@ -271,6 +278,8 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
             S.dF[0] = S.dF[1] = S.dF[2] = 0;
             S.sumC_nb = 0;
             S.sumC_all = 0;
+            S.wE = 0;
+            S.wF[0] = S.wF[1] = S.wF[2] = 0;
             // a self face's speed for the residual weights: the cell with itself
             auto self_speed = [&](AT fdd) { return face_speed<AT>(fdd, fdd, S.sc, S.sc, tk); };
             // x and y faces
@@ -282,10 +291,10 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                 for (int side = 0; side < 2; ++side) {
                     const int ny_ = d == 1 ? sy + (side ? 1 : -1) : sy;
                     const int nx_ = d == 0 ? sxx + (side ? 1 : -1) : sxx;
-                    const AT En = lds[a][IX][ny_][nx_];
-                    const AT Fn[3] = {lds[a][IX + 1][ny_][nx_], lds[a][IX + 2][ny_][nx_], lds[a][IX + 3][ny_][nx_]};
-                    const AT fnr[3] = {lds[a][IF + tens_row(d, 0)][ny_][nx_], lds[a][IF + tens_row(d, 1)][ny_][nx_],
-                                       lds[a][IF + tens_row(d, 2)][ny_][nx_]};
+                    AT En = lds[a][IX][ny_][nx_];
+                    AT Fn[3] = {lds[a][IX + 1][ny_][nx_], lds[a][IX + 2][ny_][nx_], lds[a][IX + 3][ny_][nx_]};
+                    AT fnr[3] = {lds[a][IF + tens_row(d, 0)][ny_][nx_], lds[a][IF + tens_row(d, 1)][ny_][nx_],
+                                 lds[a][IF + tens_row(d, 2)][ny_][nx_]};
                     // low face: own value; high face: the neighbour's low face
                     AT Cface;
                     if constexpr (CST)
@@ -293,6 +302,12 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                     else
                         Cface = face_speed<AT>(fcr[d], fnr[d], S.sc, lds[a][IS][ny_][nx_], tk);
                     const bool self = d == 0 ? (side ? selfx_hi : selfx_lo) : (side ? selfy_hi[c] : selfy_lo[c]);
+                    const int wk = self ? wall_kind(g, d, side) : BC_PERIODIC;
+                    if (wk >= BC_OPEN) {   // boundary lanes only: the wall's ghost, at the cell's own speed
+                        wall(wk, d, side, S.Ec, S.Fc, fcr, ex[c], En, Fn, fnr);
+                        Cface = self_speed(fcr[d]);
+                        wall_diag<AT>(wk, d, fcr, Cface, S.wE, S.wF);
+                    }
                     S.sumC_nb += self ? AT(0) : Cface;
                     if constexpr (CALL) {
                         if (CST && side && self)
@@ -308,26 +323,40 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                lds[a][IF + tens_row(2, 2)][sy][sxx]};
             {
                 const ZRow &P = prev[c];
-                const AT Fn[3] = {P.x[1], P.x[2], P.x[3]};
+                AT En = P.x[0];
+                AT Fn[3] = {P.x[1], P.x[2], P.x[3]};
+                AT fnr[3] = {P.f[0], P.f[1], P.f[2]};
                 AT Cface;
                 if constexpr (CST)
                     Cface = lds[a][IC + 2][sy][sxx];
                 else
                     Cface = face_speed<AT>(fcr[2], P.f[2], S.sc, P.s, tk);
+                const int wk = selfz_lo ? wall_kind(g, 2, 0) : BC_PERIODIC;
+                if (wk >= BC_OPEN) {
+                    wall(wk, 2, 0, S.Ec, S.Fc, fcr, ex[c], En, Fn, fnr);
+                    Cface = self_speed(fcr[2]);
+                    wall_diag<AT>(wk, 2, fcr, Cface, S.wE, S.wF);
+                }
                 S.sumC_nb += selfz_lo ? AT(0) : Cface;
                 if constexpr (CALL) S.sumC_all += Cface;
-                face_flux_acc<AT>(2, 0, Cface, S.Ec, S.Fc, fcr, P.x[0], Fn, P.f, S.dEs, S.dF);
+                face_flux_acc<AT>(2, 0, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
             }
             {
-                const AT En = lds[b][IX][sy][sxx];
-                const AT Fn[3] = {lds[b][IX + 1][sy][sxx], lds[b][IX + 2][sy][sxx], lds[b][IX + 3][sy][sxx]};
-                const AT fnr[3] = {lds[b][IF + tens_row(2, 0)][sy][sxx], lds[b][IF + tens_row(2, 1)][sy][sxx],
-                                   lds[b][IF + tens_row(2, 2)][sy][sxx]};
+                AT En = lds[b][IX][sy][sxx];
+                AT Fn[3] = {lds[b][IX + 1][sy][sxx], lds[b][IX + 2][sy][sxx], lds[b][IX + 3][sy][sxx]};
+                AT fnr[3] = {lds[b][IF + tens_row(2, 0)][sy][sxx], lds[b][IF + tens_row(2, 1)][sy][sxx],
+                             lds[b][IF + tens_row(2, 2)][sy][sxx]};
                 AT Cface;
                 if constexpr (CST)
                     Cface = lds[b][IC + 2][sy][sxx];
                 else
                     Cface = face_speed<AT>(fcr[2], fnr[2], S.sc, lds[b][IS][sy][sxx], tk);
+                const int wk = selfz_hi ? wall_kind(g, 2, 1) : BC_PERIODIC;
+                if (wk >= BC_OPEN) {
+                    wall(wk, 2, 1, S.Ec, S.Fc, fcr, ex[c], En, Fn, fnr);
+                    Cface = self_speed(fcr[2]);
+                    wall_diag<AT>(wk, 2, fcr, Cface, S.wE, S.wF);
+                }
                 S.sumC_nb += selfz_hi ? AT(0) : Cface;
                 if constexpr (CALL) {
                     if (CST && selfz_hi)
@@ -525,12 +554,14 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             }
         }
         if constexpr (PRE) {
-            yE *= AT(1) / (dEc + dtr);
-            const AT iDF = AT(1) / (AT(1) + S.sc + dtr);
-            for (int q = 0; q < 3; ++q) yFq[q] *= iDF;
-            if (dout && active) {   // the Jacobi diagonal itself (E row, F rows)
-                st_off(dout + pb, o, dEc + dtr);
-                st_off(dout + N + pb, o, AT(1) + S.sc + dtr);
+            const AT DE = dEc + dtr + nu * S.wE, DF0 = AT(1) + S.sc + dtr;
+            yE *= AT(1) / DE;
+            AT DF[3];
+            for (int q = 0; q < 3; ++q) DF[q] = DF0 + nu * S.wF[q];
+            for (int q = 0; q < 3; ++q) yFq[q] *= AT(1) / DF[q];
+            if (dout && active) {   // the Jacobi diagonal itself (E row, the F rows' mean)
+                st_off(dout + pb, o, DE);
+                st_off(dout + N + pb, o, (DF[0] + DF[1] + DF[2]) * AT(1.0 / 3.0));
             }
         }
         if (pg != AT(0)) {   // polynomial step: pg s x - B (s x), the centre of s x already in the sums
@@ -545,7 +576,13 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, o, yFq[q] * yF);
         }
     };
-    tile_sweep<AT, ST, PRE, false, NEX, CS>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi);
+    // the linear operator's walls: ghosts without their data
+    auto wall = [&](int kind, int d, int side, AT Ec, const AT(&Fc)[3], const AT(&fcr)[3], const AT(&)[NEX], AT &En,
+                    AT(&Fn)[3], AT(&fnr)[3]) __attribute__((always_inline)) {
+        const AT z3[3] = {AT(0), AT(0), AT(0)};
+        wall_ghost<AT>(kind, d, side, Ec, Fc, fcr, AT(0), z3, AT(0), En, Fn, fnr);
+    };
+    tile_sweep<AT, ST, PRE, false, NEX, CS>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi, wall);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

@@ -945,6 +945,7 @@ int plan_batched(int nblocks, const rad_block_desc_t *desc, const rad_params_t *
     if (p->anderson_m != 0) return fail(RAD_EINVAL, "the batched path runs plain Picard: anderson_m must be 0");
     if (p->cv_cubic != 0) return fail(RAD_EINVAL, "the batched path requires cv_cubic = 0");
     if (p->krylov_poly == 2) return fail(RAD_EINVAL, "the batched path has no multigrid Krylov operator");
+    if (p->energy_fix) return fail(RAD_EINVAL, "energy_fix: single-grid rad_step only");
     Geometry G;
     RAD_TRY(check_blocks(nblocks, desc, G));
     if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");

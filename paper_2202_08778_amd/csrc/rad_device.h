@@ -22,7 +22,11 @@ constexpr int kBlock = 256;   // threads per workgroup of the streaming kernels 
 constexpr int kMaxM = 64;     // largest GMRES restart length
 constexpr int kMaxAnderson = 5;  // most past iterates of the Anderson-accelerated Picard map
 
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2 };
+// Face kinds (the values of rad_bc_kind).  Every kind but periodic and
+// Dirichlet maps the neighbour across the wall to the boundary cell itself;
+// outflow keeps it (zero gradient), open, Marshak and reflect then replace its
+// state by their ghost (wall_ghost).
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2, BC_OPEN = 3, BC_MARSHAK = 4, BC_REFLECT = 5 };
 
 // Geometry and constants of one uniform grid.
 struct Grid {
@@ -35,7 +39,15 @@ struct Grid {
     double tau_k;     // tau_cell = tau_k * sR^2 / f_dd  with tau_k = 50 / nu^2
     double c, aR, cv;
     int cv_cubic;     // 0: E_int = alpha T; 1: C_v = alpha T^3, E_int = alpha T^4 / 4 (alpha = rho cv)
+    double finc8[6];  // Marshak faces (-x,+x,-y,+y,-z,+z): 8 F_inc / c, the ghost's affine part
+    double eps_N;     // relative tolerance of the per-cell Newton solve (0: to round-off)
 };
+
+// Kind of the wall on side `side` of axis d (periodic faces are no walls).
+__host__ __device__ __forceinline__ int wall_kind(const Grid &g, int d, int side)
+{
+    return side ? g.bchi[d] : g.bclo[d];
+}
 
 // row d of the symmetric tensor in the (xx,yy,zz,xy,xz,yz) plane order: f_d0, f_d1, f_d2
 __host__ __device__ constexpr int tens_row(int d, int j)
@@ -86,7 +98,7 @@ __device__ __forceinline__ void cell_ijk(const Grid &g, long long c, int &i, int
 }
 
 // Linear index of the neighbour across face (d, side) of cell c = (i,j,k):
-// periodic faces wrap, outflow faces return the cell itself (zero-gradient ghost).
+// periodic faces wrap, every other wall returns the cell itself (see wall_ghost).
 __device__ __forceinline__ long long neighbour(const Grid &g, int i, int j, int k, long long c, int d, int side)
 {
     int q = d == 0 ? i : (d == 1 ? j : k);
@@ -98,6 +110,72 @@ __device__ __forceinline__ long long neighbour(const Grid &g, int i, int j, int 
     }
     if (q > 0) return c - stride;
     return g.bclo[d] == BC_PERIODIC ? c + (long long)(n - 1) * stride : c;
+}
+
+// Ghost state across a wall face of kind open, Marshak or reflect, in the
+// scaled variables (E, Ft = F / c); (Eo, Fo, e8) are the affine data (the old
+// state at the cell and 8 F_inc / c), all zero for the linear operator.  With
+// s = +1 at a low face and -1 at a high one (the sign of the incoming
+// direction along d):
+//   open:    the cell's state with the amplitude of the incoming characteristic
+//            of the d-flux, (E + s Ft_d / sqrt(f_dd)) / 2 (speed c sqrt(f_dd)),
+//            replaced by its old value along the eigenvector
+//            (1, s f_d. / sqrt(f_dd)); no wave along d (f_dd = 0): the cell;
+//   Marshak: Ft_g = Ft, E_g = 8 F_inc / c - 4 s Ft_d - E, i.e. c E + 2 s F_d =
+//            4 F_inc for the means of ghost and cell (Sec. 3.4);
+//   reflect: E_g = E, Ft_g = Ft with Ft_d negated, tensor row with f_dj
+//            (j != d) negated.
+// The ghost's own tensor row is the cell's otherwise; its corrected speed is
+// the cell's own (both cells have the same f_dd and sR).
+template <class T>
+__device__ __forceinline__ void wall_ghost(int kind, int d, int side, T Ec, const T (&Fc)[3], const T (&fcr)[3],
+                                           T Eo, const T (&Fo)[3], T e8, T &Eg, T (&Fg)[3], T (&fg)[3])
+{
+    const T s = side ? T(-1) : T(1);
+    Eg = Ec;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        Fg[j] = Fc[j];
+        fg[j] = fcr[j];
+    }
+    if (kind == BC_OPEN) {
+        if (fcr[d] > T(0)) {
+            const T ia = T(1) / xsqrt(fcr[d]);
+            const T delta = T(0.5) * ((Eo + s * Fo[d] * ia) - (Ec + s * Fc[d] * ia));
+            Eg += delta;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Fg[j] += delta * s * fcr[j] * ia;
+        }
+    } else if (kind == BC_MARSHAK) {
+        Eg = e8 - T(4) * s * Fc[d] - Ec;
+    } else if (kind == BC_REFLECT) {
+        Fg[d] = -Fc[d];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j != d) fg[j] = -fcr[j];
+    }
+}
+
+// The wall face's share of the Jacobi diagonal (the derivative of its flux
+// contribution with respect to the cell's own unknowns, to be multiplied by
+// nu): open: (sqrt(f_dd) + C)/4 in the E and F_d rows; Marshak: C in the E row,
+// 2 f_dd in the F_d row; reflect: C in the F_d row.  The other rows get nothing
+// from a wall (their ghost values follow the cell's one to one).
+template <class T>
+__device__ __forceinline__ void wall_diag(int kind, int d, const T (&fcr)[3], T C, T &wE, T (&wF)[3])
+{
+    if (kind == BC_OPEN) {
+        if (fcr[d] > T(0)) {
+            const T q = T(0.25) * (xsqrt(fcr[d]) + C);
+            wE += q;
+            wF[d] += q;
+        }
+    } else if (kind == BC_MARSHAK) {
+        wE += C;
+        wF[d] += T(2) * fcr[d];
+    } else if (kind == BC_REFLECT) {
+        wF[d] += C;
+    }
 }
 
 // Accumulate the HLLE flux of the face on side `side` (0: low, 1: high) along
@@ -125,11 +203,15 @@ __device__ __forceinline__ void face_flux_acc(int d, int side, T C, T Ec, const 
 // Transport part of the operator at one cell of a uniform grid.  `ld(q, idx)`
 // returns component q (0: E, 1..3: Ft) of the operand at cell idx; `fl(t, idx)`
 // the tensor plane t; `sr(idx)` the cell's sR.  Returns nu * div(Phi) in
-// div[4], the sum of Ct over faces whose neighbour is another cell (the
-// transport part's diagonal is 0.5 nu times that) and over all six faces.
+// div[4], the sum of Ct over faces that carry dissipation (every face but a
+// zero-gradient wall; the transport part of the Jacobi diagonal is 0.5 nu
+// times that) and over all six faces.  Eo, Fo: the cell's old state and
+// `affine` whether the walls take their data (the nonlinear residual) or not
+// (the linear operator).
 template <class T, class LD, class FL, class SR>
 __device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, long long c, LD ld, FL fl, SR sr,
-                                          T div[4], T &sumC_nb, T &sumC_all)
+                                          T div[4], T &sumC_nb, T &sumC_all, bool affine = false, T Eo = T(0),
+                                          const T (&Fo)[3] = {T(0), T(0), T(0)})
 {
     const T tk = (T)g.tau_k;
     const T Ec = ld(0, c);
@@ -144,10 +226,16 @@ __device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, lo
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const long long nb = neighbour(g, i, j, k, c, d, side);
-            const T En = ld(0, nb);
-            const T Fn[3] = {ld(1, nb), ld(2, nb), ld(3, nb)};
-            const T fnr[3] = {fl(tens_row(d, 0), nb), fl(tens_row(d, 1), nb), fl(tens_row(d, 2), nb)};
+            T En = ld(0, nb);
+            T Fn[3] = {ld(1, nb), ld(2, nb), ld(3, nb)};
+            T fnr[3] = {fl(tens_row(d, 0), nb), fl(tens_row(d, 1), nb), fl(tens_row(d, 2), nb)};
             const T C = face_speed<T>(fcr[d], fnr[d], sRc, sr(nb), tk);
+            const int wk = nb == c ? wall_kind(g, d, side) : BC_PERIODIC;
+            if (wk >= BC_OPEN) {
+                const T zero3[3] = {T(0), T(0), T(0)};
+                wall_ghost<T>(wk, d, side, Ec, Fc, fcr, affine ? Eo : T(0), affine ? Fo : zero3,
+                              affine && wk == BC_MARSHAK ? (T)g.finc8[2 * d + side] : T(0), En, Fn, fnr);
+            }
             sumC_all += C;
             if (nb != c) sumC_nb += C;
             face_flux_acc<T>(d, side, C, Ec, Fc, fcr, En, Fn, fnr, dE, dF);
@@ -166,7 +254,8 @@ __device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, lo
 // at the smaller of the two one-term bounds, descends monotonically and stops
 // at round-off when an iterate no longer decreases.  With no non-negative root
 // (alpha Tn + sP E <= 0) it returns 0 and sets neg.
-__device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP, double aR, double E, bool &neg)
+__device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP, double aR, double E, bool &neg,
+                                             double eps_N = 0.0)
 {
     if (sP == 0.0) return Tn;
     const double rhs = alpha * Tn + sP * E;
@@ -184,7 +273,9 @@ __device__ __forceinline__ double exchange_T(double alpha, double Tn, double sP,
         const double dg = alpha + 4.0 * sP * aR * T3;
         const double Tnew = T - gv / dg;
         if (!(Tnew < T)) break;
+        const bool done = eps_N > 0.0 && T - Tnew <= eps_N * Tnew;   // relative change below eps_N
         T = Tnew;
+        if (done) break;
     }
     return T;
 }
@@ -221,7 +312,7 @@ __device__ __forceinline__ double gas_exchange(const Grid &g, double alpha, doub
         Tn += X / alpha;
     else if (sP > 0)
         E += X / sP;
-    return exchange_T(alpha, Tn, sP, aR, E, neg);
+    return exchange_T(alpha, Tn, sP, aR, E, neg, g.eps_N);
 }
 
 // Right-hand side of the energy row with the emission and the gas energy
@@ -286,23 +377,32 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
 // Sum NV per-thread values over the workgroup (NT threads, 1D) and store
-// them at partials[slot * NV + q].  Fixed order: reruns are bitwise identical.
-template <int NV, int NT = kBlock>
+// them at partials[slot * NV + q]; the last NMX columns take the maximum
+// instead of the sum.  Fixed order: reruns are bitwise identical.
+template <int NV, int NT = kBlock, int NMX = 0>
 __device__ __forceinline__ void block_store(double (&v)[NV], double *partials, long long slot)
 {
     __shared__ double sh[NV][NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        double s = wave_sum(v[q]);
+        double s = q >= NV - NMX ? wave_max(v[q]) : wave_sum(v[q]);
         if (lane == 0) sh[q][wid] = s;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
-        double s = 0;
+        const bool mx = (int)threadIdx.x >= NV - NMX;
+        double s = mx ? sh[threadIdx.x][0] : 0.0;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) s += sh[threadIdx.x][w];
+        for (int w = mx ? 1 : 0; w < NT / 64; ++w) s = mx ? fmax(s, sh[threadIdx.x][w]) : s + sh[threadIdx.x][w];
         partials[slot * NV + threadIdx.x] = s;
     }
 }

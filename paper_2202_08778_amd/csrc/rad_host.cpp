@@ -59,6 +59,12 @@ int check_params(const rad_params_t *p)
     if (p->vel_implicit != 0 && p->vel_implicit != 1) return fail(RAD_EINVAL, "vel_implicit must be 0 or 1");
     if (p->cv_cubic != 0 && p->cv_cubic != 1) return fail(RAD_EINVAL, "cv_cubic must be 0 or 1");
     if (p->krylov_poly < 0 || p->krylov_poly > 2) return fail(RAD_EINVAL, "krylov_poly must be 0, 1 or 2");
+    for (int f = 0; f < 6; ++f)
+        if (!std::isfinite(p->F_inc[f])) return fail(RAD_EINVAL, "F_inc[%d] must be finite", f);
+    if (!(p->eps_N >= 0) || !(p->eps_N < 1)) return fail(RAD_EINVAL, "eps_N must be in [0, 1)");
+    if (p->energy_fix != 0 && p->energy_fix != 1) return fail(RAD_EINVAL, "energy_fix must be 0 or 1");
+    if (p->energy_fix && p->anderson_m > 0) return fail(RAD_EINVAL, "energy_fix needs anderson_m = 0");
+    if (p->max_refine < 0) return fail(RAD_EINVAL, "max_refine must be >= 0");
     return RAD_OK;
 }
 
@@ -213,6 +219,10 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->vel_implicit = 0;
     p->cv_cubic = 0;
     p->krylov_poly = 1;
+    for (int f = 0; f < 6; ++f) p->F_inc[f] = 0.0;
+    p->eps_N = 0.0;
+    p->energy_fix = 0;
+    p->max_refine = 0;
 }
 
 // ------------------------------------------------------------------ autotune cache

@@ -36,6 +36,14 @@ bool cache_get(const std::string &key, std::string &value);
 void cache_put(const std::string &key, const std::string &value);
 std::string device_tag();
 
+// rad_step on a caller-chosen host staging buffer of kStagingDoubles doubles
+// for the reduction read-backs (nullptr: the library's pinned buffer).
+constexpr int kStagingDoubles = 256;
+int step_with_staging(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                      const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                      const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
+                      rad_stats_t *stats, double *host);
+
 enum {
     K_SETUP = 0, K_RESIDUAL, K_APPLY32, K_APPLY64, K_MULTIDOT32, K_MULTIDOT64, K_ORTH32, K_ORTH64,
     K_UPDATEX32, K_UPDATEX64, K_EXCHANGE, K_COMMIT, K_REDUCE, K_BATCHED, K_CLOSURE, K_AMR, K_MG, K_NCLASS

@@ -98,7 +98,8 @@ __global__ void __launch_bounds__(kBlock)
         auto fl = [&](int t, long long idx) -> double { return (double)f[t * N + idx]; };
         auto sr = [&](long long idx) -> double { return cdt * (double)rho[idx] * (double)kR[idx]; };
         double div[4], sC_nb, sC_all;
-        transport<double>(g, i, j, k, c, ld, fl, sr, div, sC_nb, sC_all);
+        const double Fo[3] = {Fn[c] / g.c, Fn[N + c] / g.c, Fn[2 * N + c] / g.c};
+        transport<double>(g, i, j, k, c, ld, fl, sr, div, sC_nb, sC_all, true, En[c], Fo);
 
         const double r_ = (double)rho[c];
         const double sP = cdt * r_ * (double)kP[c], sR = sr(c), alpha = r_ * g.cv, aR = g.aR;
@@ -230,13 +231,13 @@ __global__ void __launch_bounds__(tile_threads<double>())
             }
         }
         const double rE = bE - (dE * E + divE);
-        const double DE = dE + dtr, DF = 1.0 + sR + dtr;
+        const double DE = dE + dtr + nu * S.wE, DF = 1.0 + sR + dtr;
         const double WE = 1.0 + sP + half * S.sumC_all, WF = 1.0 + sR + half * S.sumC_all;
         const double zE = rE / DE;
         double zF[3], zz = zE * zE, wf = 0, fn = 0;
         for (int q = 0; q < 3; ++q) {
             const double rF = e[1 + q] * invc - ((1.0 + sR) * S.Fc[q] + divF[q]);
-            zF[q] = rF / DF;
+            zF[q] = rF / (DF + nu * S.wF[q]);
             zz += zF[q] * zF[q];
             wf += (rF / WF) * (rF / WF);
             fn += S.Fc[q] * S.Fc[q];
@@ -254,8 +255,14 @@ __global__ void __launch_bounds__(tile_threads<double>())
             acc[4] += zz;
         }
     };
+    // the walls' ghosts with their data: the old state (E_n, F_n / c) and 8 F_inc / c
+    auto wall = [&](int kind, int d, int side, double Ec, const double(&Fc)[3], const double(&fcr)[3],
+                    const double(&e)[NEX], double &En_, double(&Fn_)[3], double(&fnr)[3]) __attribute__((always_inline)) {
+        const double Fo[3] = {e[1] * invc, e[2] * invc, e[3] * invc};
+        wall_ghost<double>(kind, d, side, Ec, Fc, fcr, e[0], Fo, g.finc8[2 * d + side], En_, Fn_, fnr);
+    };
     tile_sweep<double, CT, true, true, NEX>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64, X, 1.0,
-                                            1.0, lds, lex, epi);
+                                            1.0, lds, lex, epi, wall);
     block_store<5, tile_threads<double>()>(acc, partials, blockIdx.x);
 }
 
@@ -469,19 +476,26 @@ __global__ void __launch_bounds__(kBlock)
 
 // Per-cell exchange solve (eq. PicardTemp) for T with E = X_E; then the
 // diagnostics of the Picard iteration, and X0 = X.  Partials:
-//   [sum (R_T/W_T)^2, sum T^2, sum dT^2, sum dE^2, sum E^2, sum dFt^2, sum Ft^2, neg]
+//   [sum (R_T/W_T)^2, sum T^2, sum dT^2, sum dE^2, sum E^2, sum dFt^2, sum Ft^2, neg,
+//    sum dt dE, sum (E_n + e(T_n)), max |dt dE| / (|E| + e(T))]
+// with dt dE = sP (aR T^4 - e_rad) the energy correction of Sec. 2.3.4: the
+// radiation row solved at the guess T_o (the T* it held) equals the plain row
+// (1 + sP) E - E_n - sP e_rad with sP e_rad = sP eta E + b_E - E_n (eta = 0 and
+// b_E = E_n + sP aR T_o^4 lagged).  Tfix (non-null): the gas temperature whose
+// energy is e(T) + dt dE (clamped at 0), committed by the energy fix.
 // VI (moving medium, implicit switch): the gas also receives the O(v/c) energy
 // X = VA E + VB.Ft of the new state.
 template <class CT, bool VI = false>
 __global__ void __launch_bounds__(kBlock)
     k_exchange(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kP, const double *__restrict__ Tn,
                double *__restrict__ Tc, double *__restrict__ X, double *__restrict__ X0, double *partials,
-               double *__restrict__ Gk, double *__restrict__ fk, const double *__restrict__ VA = nullptr,
-               const double *__restrict__ VB = nullptr)
+               double *__restrict__ Gk, double *__restrict__ fk, const double *__restrict__ VA,
+               const double *__restrict__ VB, const double *__restrict__ En, int picard_mode,
+               double *__restrict__ Tfix)
 {
     const long long N = g.N;
     long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (c < N) {
         const double r_ = (double)rho[c];
         const double sP = g.cdt * r_ * (double)kP[c], alpha = r_ * g.cv, aR = g.aR;
@@ -498,8 +512,31 @@ __global__ void __launch_bounds__(kBlock)
         const double RT0 = gas_e(g, alpha, T) - gas_e(g, alpha, Tn[c]) + sP * (aR * T3 * T - E) - Xv;
         const double RT = (T == 0.0 && RT0 > 0.0) ? 0.0 : RT0;
         const double WT = gas_C(g, alpha, T) + 4.0 * sP * aR * T3;
-        const double dT = T - Tc[c];
+        const double To = Tc[c];
+        const double dT = T - To;
         Tc[c] = T;
+        // energy correction: the emission the radiation solve used against the gas root's
+        double dEc = 0.0;
+        if (sP != 0.0) {
+            const double En_ = En[c];
+            double eta = 0.0, bE;
+            if (picard_mode == 0)
+                bE = En_ + sP * aR * To * To * To * To;
+            else
+                bE = lin_rhs(g, En_, alpha, Tn[c], To, sP, aR, eta);
+            dEc = sP * aR * T3 * T - (sP * eta * E + bE - En_);
+        }
+        const double eT = gas_e(g, alpha, T);
+        v[8] = dEc;
+        v[9] = En[c] + gas_e(g, alpha, Tn[c]);
+        const double loc = fabs(E) + eT;
+        v[10] = loc > 0.0 ? fabs(dEc) / loc : (dEc != 0.0 ? INFINITY : 0.0);
+        if (Tfix) {
+            const double e1 = eT + dEc;
+            Tfix[c] = !(e1 > 0.0) || !(alpha > 0.0) ? 0.0
+                      : (g.cv_cubic ? sqrt(sqrt(4.0 * e1 / alpha)) : e1 / alpha);
+            if (dEc == 0.0) Tfix[c] = T;
+        }
         if (Gk) {  // Picard map value and its residual for the Anderson history
             Gk[c] = T;
             fk[c] = dT;
@@ -519,7 +556,7 @@ __global__ void __launch_bounds__(kBlock)
         }
         v[7] = neg ? 1.0 : 0.0;
     }
-    block_store<8>(v, partials, blockIdx.x);
+    block_store<11, kBlock, 1>(v, partials, blockIdx.x);
 }
 
 // Moving medium, once per step: the O(v/c) coefficients of eq. G and G0 with
@@ -699,22 +736,25 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Sums the nv columns of partials[nblk][nv] in a fixed order: columns [0, na)
-// go to out_a, columns [na, nv) to out_b.  If sq_col >= 0, 1/sqrt of that
-// column's sum is also written to *sdev (scale of a new Krylov vector).
+// go to out_a, columns [na, nv) to out_b; columns q >= mx take the maximum
+// (of non-negative values) instead.  If sq_col >= 0, 1/sqrt of that column's
+// sum is also written to *sdev (scale of a new Krylov vector).
 __global__ void __launch_bounds__(kBlock)
     k_reduce(const double *__restrict__ partials, long long nblk, int nv, int na, double *out_a, double *out_b,
-             int sq_col, double *sdev)
+             int sq_col, double *sdev, int mx)
 {
     __shared__ double sh[kBlock / 64];
     for (int q = 0; q < nv; ++q) {
+        const bool m = q >= mx;
         double s = 0;
-        for (long long b = threadIdx.x; b < nblk; b += kBlock) s += partials[b * nv + q];
-        s = wave_sum(s);
+        for (long long b = threadIdx.x; b < nblk; b += kBlock)
+            s = m ? fmax(s, partials[b * nv + q]) : s + partials[b * nv + q];
+        s = m ? wave_max(s) : wave_sum(s);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0;
-            for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+            for (int w = 0; w < kBlock / 64; ++w) t = m ? fmax(t, sh[w]) : t + sh[w];
             if (q < na)
                 out_a[q] = t;
             else
@@ -728,18 +768,19 @@ __global__ void __launch_bounds__(kBlock)
 // First stage of a long reduction: block b sums rows [256 b, 256 b + 256) of
 // partials[nblk][nv] into out[b][nv] (fixed order, so reruns are bitwise equal).
 __global__ void __launch_bounds__(kBlock)
-    k_reduce_rows(const double *__restrict__ partials, long long nblk, int nv, double *__restrict__ out)
+    k_reduce_rows(const double *__restrict__ partials, long long nblk, int nv, double *__restrict__ out, int mx)
 {
     __shared__ double sh[kBlock / 64];
     const long long row = (long long)blockIdx.x * kBlock + threadIdx.x;
     for (int q = 0; q < nv; ++q) {
+        const bool m = q >= mx;
         double s = row < nblk ? partials[row * nv + q] : 0.0;
-        s = wave_sum(s);
+        s = m ? wave_max(s) : wave_sum(s);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0;
-            for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+            for (int w = 0; w < kBlock / 64; ++w) t = m ? fmax(t, sh[w]) : t + sh[w];
             out[(long long)blockIdx.x * nv + q] = t;
         }
         __syncthreads();
@@ -797,11 +838,14 @@ Grid make_grid(int nx, int ny, int nz, const int bc[6], double dt, double dx, co
     g.nu = p.c * dt / dx;
     g.tau_k = 50.0 / (g.nu * g.nu);
     g.cv_cubic = p.cv_cubic;
+    for (int f = 0; f < 6; ++f) g.finc8[f] = 8.0 * p.F_inc[f] / p.c;
+    g.eps_N = p.eps_N;
     return g;
 }
 
+// allow_walls: the open, Marshak and reflecting faces (uniform single grids)
 int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6], const rad_params_t *p,
-                    bool allow_dirichlet)
+                    bool allow_dirichlet, bool allow_walls = true)
 {
     if (!p) return fail(RAD_EINVAL, "params is NULL");
     if (nx < 1 || ny < 1 || nz < 1) return fail(RAD_EINVAL, "grid extents must be >= 1");
@@ -812,8 +856,10 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
     if (!(dx > 0) || !std::isfinite(dx)) return fail(RAD_EINVAL, "dx must be positive and finite");
     if (!bc) return fail(RAD_EINVAL, "bc is NULL");
     for (int f = 0; f < 6; ++f) {
-        if (bc[f] != RAD_BC_PERIODIC && bc[f] != RAD_BC_OUTFLOW && !(allow_dirichlet && bc[f] == RAD_BC_DIRICHLET))
-            return fail(RAD_EINVAL, "unsupported boundary kind on face %d", f);
+        const bool wall = bc[f] == RAD_BC_OPEN || bc[f] == RAD_BC_MARSHAK || bc[f] == RAD_BC_REFLECT;
+        if (bc[f] != RAD_BC_PERIODIC && bc[f] != RAD_BC_OUTFLOW && !(allow_dirichlet && bc[f] == RAD_BC_DIRICHLET) &&
+            !(allow_walls && wall))
+            return fail(RAD_EINVAL, "unsupported boundary kind %d on face %d", bc[f], f);
     }
     for (int a = 0; a < 3; ++a)
         if ((bc[2 * a] == RAD_BC_PERIODIC) != (bc[2 * a + 1] == RAD_BC_PERIODIC))
@@ -822,8 +868,8 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG, part, small,
-        total;
+    size_t X, X0, Tc, Tfix, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG, part,
+        small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
@@ -881,6 +927,7 @@ Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr 
     L.X = take(4 * N * 8);
     L.X0 = take(4 * N * 8);
     L.Tc = take(N * 8);
+    L.Tfix = take(p.energy_fix ? N * 8 : 0);   // the energy-corrected temperature of the last exchange
     L.sR = take(N * ksz);
     L.dEA = take(N * ksz);
     L.fA = (mixed && p.coef_dtype == RAD_F64) ? take(6 * N * ksz) : take(0);
@@ -958,18 +1005,19 @@ struct Solver {
     // Sum the nv columns of part()[nblk][nv]; past 4096 rows a first pass folds every 256
     // rows into one (written after the rows in use; the partials area holds 24 values per
     // cell block, so it has room whenever nv <= 23).
+    // columns q >= mx of the partials are maxima (non-negative), the others sums
     void reduce(long long nblk, int nv, int na, double *out_a, double *out_b = nullptr, int sq_col = -1,
-                double *sdev = nullptr)
+                double *sdev = nullptr, int mx = 1 << 30)
     {
         const double *src = part();
         if (nblk > 4096 && nv <= 23) {
             const long long nb2 = (nblk + kBlock - 1) / kBlock;
             double *dst = part() + nblk * nv;
-            hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)nb2), dim3(kBlock), 0, st, part(), nblk, nv, dst);
+            hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)nb2), dim3(kBlock), 0, st, part(), nblk, nv, dst, mx);
             src = dst;
             nblk = nb2;
         }
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, src, nblk, nv, na, out_a, out_b, sq_col, sdev);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, src, nblk, nv, na, out_a, out_b, sq_col, sdev, mx);
     }
     // launch under the kernel-class profiler (no-op when profiling is off)
     template <class F>
@@ -978,6 +1026,7 @@ struct Solver {
         const int tok = prof_begin(kid, st);
         launch();
         prof_end(tok, st, bytes);
+        stats.bytes_moved += bytes;
     }
     // copy sm()[off, off+count) to host[off...] and wait
     int read(int off, int count)
@@ -1002,6 +1051,8 @@ int run_step(Solver &S)
     const dim3 gv((unsigned)S.L.nblk_vec), gf((unsigned)S.L.nblk_cells), bl(kBlock);
     const CT *rho = (const CT *)S.rho, *kP = (const CT *)S.kP, *kR = (const CT *)S.kR, *f = (const CT *)S.f;
     double *X = S.at<double>(S.L.X), *X0 = S.at<double>(S.L.X0), *Tc = S.at<double>(S.L.Tc);
+    double *Tfix = p.energy_fix ? S.at<double>(S.L.Tfix) : nullptr;
+    bool exchanged = false;
     AT *sR = S.at<AT>(S.L.sR), *dEA = S.at<AT>(S.L.dEA);
     AT *fA = (p.prec == RAD_MIXED && p.coef_dtype == RAD_F64) ? S.at<AT>(S.L.fA) : nullptr;
     KT *V = S.at<KT>(S.L.V), *W = S.at<KT>(S.L.W);
@@ -1400,7 +1451,9 @@ int run_step(Solver &S)
         const double inner_floor = (sizeof(KT) == 4) ? 1e-5 : 0.0;  // FP32 Arnoldi resolves ~5 decades per cycle
         int its = 0;
         double beta_prev = INFINITY;
-        while (beta > target && beta > 0 && its < p.max_krylov && beta < 0.999 * beta_prev) {
+        int restarts = 0;
+        while (beta > target && beta > 0 && its < p.max_krylov && beta < 0.999 * beta_prev &&
+               (p.max_refine == 0 || restarts++ < p.max_refine)) {
             beta_prev = beta;
             const double cycle_target = std::max(target, beta * inner_floor);
             RAD_TRY(S.read(SM_S, 1));
@@ -1511,23 +1564,27 @@ int run_step(Solver &S)
         const int aslot = aa_m > 0 ? k % (aa_m + 1) : 0;
         double *Gk = aa_m > 0 ? AAG + (size_t)aslot * N : nullptr, *fk = aa_m > 0 ? AAf + (size_t)aslot * N : nullptr;
         long long xrows = 0;
-        S.timed(K_EXCHANGE, Nd * (2 * cb + 16 + 64 + 40 + (aa_m > 0 ? 16 : 0)), [&] {
+        S.timed(K_EXCHANGE, Nd * (2 * cb + 24 + 64 + 40 + (aa_m > 0 ? 16 : 0) + (Tfix ? 8 : 0)), [&] {
             for (int l = 0; l < NL; ++l) {
                 const long long o = S.c0[l];
                 if (vimp)   // one level: moving media run on the single grid only
                     hipLaunchKernelGGL((k_exchange<CT, true>), cell_grid(l), bl, 0, S.st, S.gl[l], rho, kP, S.Tn, Tc,
-                                       X, X0, part, Gk, fk, (const double *)VA, (const double *)VB);
+                                       X, X0, part, Gk, fk, (const double *)VA, (const double *)VB, S.En, p.mode,
+                                       Tfix);
                 else
                     hipLaunchKernelGGL((k_exchange<CT>), cell_grid(l), bl, 0, S.st, S.gl[l], rho + o, kP + o,
-                                       S.Tn + o, Tc + o, X + 4 * o, X0 + 4 * o, part + xrows * 8,
+                                       S.Tn + o, Tc + o, X + 4 * o, X0 + 4 * o, part + xrows * 11,
                                        Gk ? Gk + o : nullptr, fk ? fk + o : nullptr, (const double *)nullptr,
-                                       (const double *)nullptr);
+                                       (const double *)nullptr, S.En + o, p.mode, Tfix ? Tfix + o : nullptr);
                 xrows += cell_grid(l).x;
             }
         });
-        S.reduce(xrows, 8, 8, sm + SM_RED);
-        RAD_TRY(S.read(SM_RED, 8));
+        S.reduce(xrows, 11, 11, sm + SM_RED, nullptr, -1, nullptr, 10);
+        RAD_TRY(S.read(SM_RED, 11));
         const double *e = h + SM_RED;
+        st.energy_defect = e[9] != 0.0 ? e[8] / e[9] : e[8];
+        st.dE_max = e[10];
+        exchanged = true;
         resT = e[1] > 0 ? std::sqrt(e[0] / e[1]) : std::sqrt(e[0]);
         const double e1 = e[1], e2 = e[2], e3 = e[3], e4 = e[4], e5 = e[5], e6 = e[6], e7 = e[7];
         if (aa_m > 0) {
@@ -1595,10 +1652,12 @@ int run_step(Solver &S)
                          k, res, st.res_E, st.res_F, resT, its, st.krylov_iters, cycles, reorth, st.rel_change,
                          st.neg_cells);
     }
+    // the energy fix commits the gas temperature of the corrected energy (the last exchange's)
+    const double *Tcommit = (Tfix && exchanged) ? Tfix : Tc;
     S.timed(K_COMMIT, Nd * 80, [&] {
         for (int l = 0; l < NL; ++l) {
             const long long o = S.c0[l];
-            hipLaunchKernelGGL(k_commit, cell_grid(l), bl, 0, S.st, S.gl[l].N, g.c, X + 4 * o, Tc + o, S.E + o,
+            hipLaunchKernelGGL(k_commit, cell_grid(l), bl, 0, S.st, S.gl[l].N, g.c, X + 4 * o, Tcommit + o, S.E + o,
                                S.F + 3 * o, S.T + o);
         }
         if (S.amr) {
@@ -1706,7 +1765,7 @@ int dispatch_step(Solver &S)
 
 int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
                 const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6],
-                const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream)
+                const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream, double *host = nullptr)
 {
     RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
     if (!E || !F || !T_gas || !rho || !kappa_P || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
@@ -1717,7 +1776,7 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     RAD_TRY(mg_cells_for(nx, ny, nz, *p, mgc));
     S.L = layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc);
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
-    S.host = pinned_staging();
+    S.host = host ? host : pinned_staging();
     if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
     S.g = make_grid(nx, ny, nz, bc, dt, dx, *p);
     S.nlev = 1;
@@ -1751,17 +1810,19 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
 
 }  // namespace
 
-extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
-                        const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
-                        const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
-                        rad_stats_t *stats)
+namespace vr {
+int step_with_staging(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                      const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                      const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
+                      rad_stats_t *stats, double *host)
 {
+    static_assert(SM_TOTAL <= kStagingDoubles, "host staging too small");
     clear_error();
     auto t0 = std::chrono::steady_clock::now();
     if (stats) std::memset(stats, 0, sizeof(*stats));
     Solver S;
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
-                        stream));
+                        stream, host));
     int rc;
     try {  // small host vectors of the GMRES least-squares problem
         rc = dispatch_step(S);
@@ -1772,6 +1833,16 @@ extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_
     S.stats.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S.stats;
     return rc;
+}
+}  // namespace vr
+
+extern "C" int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
+                        const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx,
+                        const int bc[6], const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream,
+                        rad_stats_t *stats)
+{
+    return step_with_staging(nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace, ws_bytes,
+                             stream, stats, nullptr);
 }
 
 extern "C" size_t rad_workspace_bytes_moving(int nx, int ny, int nz, const rad_params_t *p)
@@ -1794,6 +1865,7 @@ extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, dou
     if (!beta) return fail(RAD_EINVAL, "beta (velocity) is NULL");
     if (p->vel_implicit && p->anderson_m > 0)
         return fail(RAD_EINVAL, "anderson_m must be 0 with vel_implicit = 1");
+    if (p->energy_fix) return fail(RAD_EINVAL, "energy_fix: rad_step (no velocity) only");
     if (p->krylov_poly == 2) return fail(RAD_EINVAL, "the moving-medium step has no multigrid Krylov operator");
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace,
                         (size_t)-1, stream));
@@ -1823,7 +1895,8 @@ int amr_setup(const rad_amr2_t *geom, const int bc[6], double dt, double dx, con
     if (p && p->cv_cubic) return fail(RAD_EINVAL, "the two-level grid requires cv_cubic = 0");
     if (p && p->krylov_poly == 2) return fail(RAD_EINVAL, "the two-level grid has no multigrid Krylov operator");
     const int nc[3] = {geom->nx, geom->ny, geom->nz};
-    RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, false));
+    RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, false, false));
+    if (p->energy_fix) return fail(RAD_EINVAL, "energy_fix: single-grid rad_step only");
     Amr &A = S.A;
     int fbc[6];
     for (int d = 0; d < 3; ++d) {

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libvettam_rad.so")
 
 RAD_OK, RAD_NOT_CONVERGED = 0, 1
 RAD_EINVAL, RAD_ENOMEM, RAD_EHIP, RAD_ENOTIMPL, RAD_EDATA = -1, -2, -3, -4, -5
-BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
+BC = {"periodic": 0, "outflow": 1, "dirichlet": 2, "open": 3, "marshak": 4, "reflect": 5}
 PREC = {"fp64": 0, "mixed": 1}
 MODE = {"lagged": 0, "linearised": 1}
 DTYPE = {"f64": 0, "f32": 1}
@@ -26,14 +26,16 @@ class Params(ct.Structure):
                 ("eps_R", ct.c_double), ("eps_P", ct.c_double), ("max_picard", ct.c_int),
                 ("max_krylov", ct.c_int), ("gmres_m", ct.c_int), ("prec", ct.c_int), ("mode", ct.c_int),
                 ("coef_dtype", ct.c_int), ("anderson_m", ct.c_int), ("vel_implicit", ct.c_int),
-                ("cv_cubic", ct.c_int), ("krylov_poly", ct.c_int)]
+                ("cv_cubic", ct.c_int), ("krylov_poly", ct.c_int), ("F_inc", ct.c_double * 6), ("eps_N", ct.c_double),
+                ("energy_fix", ct.c_int), ("max_refine", ct.c_int)]
 
 
 class Stats(ct.Structure):
     _fields_ = [("status", ct.c_int), ("picard_iters", ct.c_int), ("krylov_iters", ct.c_int),
                 ("refine_sweeps", ct.c_int), ("neg_cells", ct.c_int), ("bad_cells", ct.c_int),
                 ("scaled_residual", ct.c_double), ("res_E", ct.c_double), ("res_F", ct.c_double),
-                ("res_T", ct.c_double), ("rel_change", ct.c_double), ("t_total_ms", ct.c_double)]
+                ("res_T", ct.c_double), ("rel_change", ct.c_double), ("t_total_ms", ct.c_double),
+                ("energy_defect", ct.c_double), ("dE_max", ct.c_double), ("bytes_moved", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -144,6 +146,8 @@ def params(**kw) -> Params:
             v = MODE[v]
         elif k == "coef_dtype" and isinstance(v, str):
             v = DTYPE[v]
+        elif k == "F_inc":
+            v = (ct.c_double * 6)(*([float(v)] * 6 if isinstance(v, (int, float)) else [float(x) for x in v]))
         setattr(p, k, v)
     return p
 

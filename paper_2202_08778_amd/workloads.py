@@ -123,15 +123,15 @@ def _gaussian_source(shape, h, peak, width_cells, aR, T):
 
 
 def mixed_depth(n=128, seed=2, sigma_rho=1.5, lg_tau=(-3.0, 3.0), dt_cross=50.0, steps=10,
-                fp32_exact=False, shape=None, bc="periodic"):
+                fp32_exact=False, shape=None, bc="open"):
     """Cube with lognormal density, cell optical depth log-uniform over lg_tau and spatially
     correlated (Gaussian filter, 4 cells), random SPD unit-trace f, Gaussian source in E
     (peak 1e3, sigma 4 cells) on an equilibrium background, T = 0.1, F = 0, dt = dt_cross h / c.
 
-    The default boundary is periodic: with zero-gradient outflow faces taken implicitly (the
-    ghost equals the current boundary cell) and dt of tens of light-crossing times, the discrete
-    operator of this medium has eigenvalues with negative real part (a growing boundary mode),
-    so those steps are not a well-posed benchmark; outflow remains available for smaller dt."""
+    The outflow faces of this medium are open (characteristic) faces by default: with the
+    zero-gradient ghost (the current boundary cell) and dt of tens of light-crossing times the
+    discrete operator has eigenvalues with negative real part in optically thick boundary cells,
+    so that reading is not well posed here; it remains available as bc="outflow"."""
     rng = np.random.default_rng(seed)
     shape = shape or (n, n, n)
     h = 1.0 / shape[2]
