@@ -172,6 +172,24 @@ int rad_step(int nx, int ny, int nz, double *E, double *F, double *T_gas,
              double dt, double dx, const int bc[6], const rad_params_t *p,
              void *workspace, size_t ws_bytes, void *stream, rad_stats_t *stats);
 
+/* ----------------------------------------------- allocation-free variant
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  rad_step
+ * with the workspace taken from a static device array inside the library
+ * (one copy per GPU, held until the process ends; rad_noalloc_max_bytes()
+ * bytes, 64 MiB) instead of a caller buffer, and the reductions read back
+ * through a thread-local pageable host buffer: the call makes no device or
+ * pinned-host allocation.  Arguments, results and errors as rad_step; a step
+ * whose rad_workspace_bytes() exceeds the array returns RAD_ENOMEM before any
+ * device work.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (other threads, other streams) race.  Profiling
+ * (rad_profile_enable) must be off, since it creates HIP events. */
+size_t rad_noalloc_max_bytes(void);
+int rad_step_noalloc(int nx, int ny, int nz, double *E, double *F, double *T_gas,
+                     const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
+                     double dt, double dx, const int bc[6], const rad_params_t *p, void *stream,
+                     rad_stats_t *stats);
+
 /* ------------------------------------------------------- moving medium
  * rad_step with a gas velocity: the O(v/c) terms of the radiation four-force
  * (eq. G and G0, with kappa_E = kappa_P and kappa_F = kappa_R) enter the

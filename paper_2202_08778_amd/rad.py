@@ -71,6 +71,10 @@ def _load():
     L.rad_step.restype = I
     L.rad_workspace_bytes_moving.argtypes = [I, I, I, PP]
     L.rad_workspace_bytes_moving.restype = SZ
+    L.rad_noalloc_max_bytes.argtypes = []
+    L.rad_noalloc_max_bytes.restype = SZ
+    L.rad_step_noalloc.argtypes = [I, I, I, P, P, P, P, P, P, P, D, D, IA6, PP, P, ct.POINTER(Stats)]
+    L.rad_step_noalloc.restype = I
     L.rad_step_moving.argtypes = [I, I, I, P, P, P, P, P, P, P, P, D, D, IA6, PP, P, SZ, P, ct.POINTER(Stats)]
     L.rad_step_moving.restype = I
     L.rad_workspace_bytes_amr2.argtypes = [ct.POINTER(Amr2), PP]
@@ -121,7 +125,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_workspace_bytes_moving", "rad_step_moving",
+EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_noalloc_max_bytes", "rad_step_noalloc",
+            "rad_workspace_bytes_moving", "rad_step_moving",
             "rad_workspace_bytes_amr2", "rad_step_amr2",
             "rad_autotune_step", "rad_residual",
             "rad_face_speeds",
@@ -235,6 +240,28 @@ def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace
     rc = lib.rad_step(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p),
                       _ptr(workspace, name="workspace"), workspace.numel() * workspace.element_size(),
                       _stream(stream), ct.byref(st))
+    if check:
+        _check(rc)
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def rad_step_noalloc(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, stream=None, check=True):
+    """rad_step with the library's static device scratch as the workspace (no allocation in the call;
+    grids whose workspace exceeds rad_noalloc_max_bytes() are refused with RAD_ENOMEM)."""
+    torch = _torch()
+    nz, ny, nx = E.shape
+    N = nx * ny * nz
+    p = Params.from_buffer_copy(p)
+    p.coef_dtype = _coef_dtype(rho)
+    cd = rho.dtype
+    args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
+            _ptr(rho, cd, N, "rho"), _ptr(kappa_P, cd, N, "kappa_P"), _ptr(kappa_R, cd, N, "kappa_R"),
+            _ptr(f, cd, 6 * N, "f")]
+    st = Stats()
+    rc = lib.rad_step_noalloc(nx, ny, nz, *args, float(dt), float(dx), bc_array(bc), ct.byref(p), _stream(stream),
+                              ct.byref(st))
     if check:
         _check(rc)
     d = st.as_dict()
