@@ -3,8 +3,9 @@
 
 Workload: the mixed-depth medium at 256^3 (lognormal density sigma 1.5, cell optical depth
 log-uniform over 1e-3..1e3 and spatially correlated, random SPD unit-trace Eddington tensor,
-central Gaussian source in E, T = 0.1, dt = 50 light-crossing times, periodic faces, FP32-exact
-inputs), 5 implicit steps.  A "step" is one rad_step call (the whole hot path: coefficient
+central Gaussian source in E, T = 0.1, dt = 50 light-crossing times, open (characteristic outflow)
+faces, FP32-exact inputs), 5 implicit steps.  The default run adds two legs as extra keys: the 512^3
+scale recipe (mixed path, 1 warm-up + 3 steps) and the batched path (1024 blocks, 1 warm-up + 1 step).  A "step" is one rad_step call (the whole hot path: coefficient
 setup, Picard iterations of FP64 residual, Krylov solve, exchange solve, commit).
 
 The timed region starts with every input resident in HBM.  Both paths start from the same
@@ -89,12 +90,12 @@ def run_path(torch, rad, d, state0, coefs, prec, steps, warmup, tol, profile, m=
     return dict(seconds=t1 - t0, stats=stats, state=(E, F, T), prev=prev, profile=prof, tuned=tuned, share=share)
 
 
-def measured_traffic(kernel_class):
+def measured_traffic(kernel_class, n):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy) of one library kernel
-    class, from the committed rocprofv3 counter summary of the 256^3 mixed step, or None when the kernel
-    sources changed since the counters were taken."""
+    class, from the committed rocprofv3 counter summary of the n^3 mixed step, or None when there is none or
+    the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_mixed_256.json")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_mixed_{n}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -111,8 +112,10 @@ def relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def cpu_baseline(n_sample, tol):
-    """FP64 oracle on the same recipe at n_sample^3 (periodic), one step, timed on the host cores."""
+def cpu_baseline(n_sample, tol, n_full):
+    """FP64 oracle on the same recipe at n_sample^3, one step, timed on the host cores; with the time the
+    oracle would take for one n_full^3 step at the sample's per-cell rate (a lower bound: its Krylov count
+    grows with the grid)."""
     import oracle
     from paper_2202_08778_amd import workloads as W
     d = W.mixed_depth(n=n_sample, seed=3, steps=1, fp32_exact=True)
@@ -123,19 +126,25 @@ def cpu_baseline(n_sample, tol):
     sec = time.perf_counter() - t0
     cells = n_sample ** 3
     return {"value": cells / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"mixed-depth recipe at {n_sample}^3 (same generator, periodic, FP32-exact), 1 step, "
+            "sample": f"mixed-depth recipe at {n_sample}^3 (same generator, {d['bc']} faces, FP32-exact), 1 step, "
                       f"tol {tol:g}: {sec:.1f} s, {st['picard_iters']} Picard / {st['krylov_iters']} Krylov "
-                      f"iterations, converged={st['converged']}"}
+                      f"iterations, converged={st['converged']}",
+            "extrapolated_seconds_per_step": {f"{n_full}^3": n_full ** 3 / (cells / sec),
+                                              "note": "sample rate per cell; a lower bound (Krylov counts grow "
+                                                      "with the grid)"}}
 
 
-def bench_batched(args, torch, np, rad, W):
+def bench_batched(args, torch, np, rad, W, steps=None, warmup=None, emit=True):
     """The batched path: 1024 independent Dirichlet blocks (edges 8..32, per-block dt and kappa), mixed
-    precision, one persistent launch per step replayed from a HIP graph, inputs restored before each step."""
+    precision, one persistent launch per step replayed from a HIP graph, inputs restored before each step.
+    emit: print the JSON line (a run of its own); else return the result (a leg of the default run)."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     batch = W.batched_blocks(nblocks=1024, seed=4)
     descs, ar = rad.pack_blocks(batch["blocks"])
     cells = sum(b["n"] ** 3 for b in batch["blocks"])
-    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1, krylov_poly=args.krylov_poly)
-    if args.gmres_m is not None:
+    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1, krylov_poly=1 if args.krylov_poly == 2 else args.krylov_poly)
+    if args.gmres_m is not None and args.batched:
         p.gmres_m = args.gmres_m
     g = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
     dev = [g(ar["E"]), g(ar["F"]), g(ar["T"])] + [g(ar[k], torch.float32) for k in ("rho", "kP", "kR", "f")]
@@ -146,7 +155,7 @@ def bench_batched(args, torch, np, rad, W):
         plan.autotune(*dev)
     stats = None
     times = []
-    for s in range(args.warmup + args.steps):
+    for s in range(warmup + steps):
         for t, t0 in zip(dev[:3], init):
             t.copy_(t0)
         torch.cuda.synchronize()
@@ -154,28 +163,37 @@ def bench_batched(args, torch, np, rad, W):
         stats = plan.step(*dev)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        if s >= args.warmup:
+        if s >= warmup:
             times.append(dt)
-        log(f"  [batched] {'warmup ' if s < args.warmup else ''}step {s}: {1000 * dt:.0f} ms")
-        if s == args.warmup - 1 and args.reorder:
+        log(f"  [batched] {'warmup ' if s < warmup else ''}step {s}: {1000 * dt:.0f} ms")
+        if s == warmup - 1 and args.reorder:
             plan.reorder(stats)   # queue the timed steps by the warm-up step's block solve times
             log("  [batched] queue reordered by measured block solve times")
     st = rad.Plan.read_stats(stats)
     sec = sum(times)
     conv = int((st["status"] == 0).sum())
     res = {"metric": "batched implicit VET rad-step cell-updates/s (1024 AMR-like blocks, mixed precision)",
-           "value": cells * args.steps / sec, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": 1000.0 * sec / args.steps, "higher_is_better": True,
+           "value": cells * steps / sec, "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": 1000.0 * sec / steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "1024 Dirichlet blocks, edges uniform on {8,12,16,24,32}, dt 1..1000 crossings, "
                                   "kappa 1e-2..1e3 per block, one persistent graph-replayed launch per step",
                       "cells": cells, "gmres_m": p.gmres_m, "krylov_poly": p.krylov_poly,
                       "queue": ("longest measured solve first (warm-up step's block times)"
-                                if args.warmup > 0 and args.reorder else "largest block first"),
+                                if warmup > 0 and args.reorder else "largest block first"),
                       "launch": dict(zip(("threads", "per_cu", "largest_first"), plan.launch_shape()))},
            "blocks_converged": conv, "blocks": len(batch["blocks"]),
            "krylov_iters_max_block": int(st["krylov_iters"].max()),
-           "krylov_iters_total": int(st["krylov_iters"].sum())}
+           "krylov_iters_total": int(st["krylov_iters"].sum()),
+           "block_solve_ms_max": float(st["t_total_ms"].max()),
+           "block_solve_ms_sum": float(st["t_total_ms"].sum())}
+    # chip busy fraction: the blocks' summed workgroup time over (workgroups x step time)
+    shape = plan.launch_shape()
+    wgs = shape[1] * torch.cuda.get_device_properties(0).multi_processor_count
+    res["chip_busy_fraction"] = float(st["t_total_ms"].sum()) / (wgs * res["ms_per_step"])
+    del plan, dev, init
+    if not emit:
+        return res
     print(json.dumps(res), flush=True)
 
 
@@ -337,6 +355,10 @@ def main():
                     help="GMRES restart length (default 8 on the grids, where orthogonalisation grows with m "
                          "while the iteration count barely changes; the library's 12 for --batched)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-scale-leg", action="store_true",
+                    help="skip the 512^3 scale leg (mixed path, 1 warm-up + 3 steps) of the default run")
+    ap.add_argument("--no-batched-leg", action="store_true",
+                    help="skip the batched leg (1024 blocks, 1 warm-up + 1 step) of the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=24)
@@ -369,79 +391,106 @@ def main():
         return bench_amr(args, torch, np, rad, W)
     scale = args.workload == "scale"
     n = args.n or (512 if scale else 256)
-    log(f"generating the {args.workload} workload at {n}^3 ...")
-    d = W.mixed_depth_512(n=n, steps=args.steps) if scale else W.mixed_depth_256(n=n, steps=args.steps)
+    res = bench_grid(args, torch, np, rad, W, scale, n, args.steps, args.warmup, with_fp64=not args.no_fp64,
+                     with_closure=True)
+    if not scale and not args.no_scale_leg:
+        # the 512^3 scale recipe, mixed path only: one warm-up and three timed steps
+        torch.cuda.empty_cache()
+        log("scale leg: 512^3 mixed-depth recipe (sigma 2, optical depth 1e-4..1e4, 200 crossings), mixed path ...")
+        res["scale_512"] = bench_grid(args, torch, np, rad, W, True, 512, 3, 1, with_fp64=False, with_closure=False)
+    if not args.no_batched_leg:
+        torch.cuda.empty_cache()
+        log("batched leg: 1024 Dirichlet blocks, one warm-up and one timed graph replay ...")
+        res["batched_1024"] = bench_batched(args, torch, np, rad, W, steps=1, warmup=1, emit=False)
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline at {args.cpu_sample_n}^3 ...")
+        res["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.tol, n)
+    print(json.dumps(res), flush=True)
+
+
+def bench_grid(args, torch, np, rad, W, scale, n, steps, warmup, with_fp64, with_closure):
+    """One uniform-grid workload: the mixed path timed over `steps` steps after `warmup`, optionally the
+    FP64 path from the same state, the oracle's residual of the last mixed step and the roofline."""
+    log(f"generating the {'scale' if scale else 'precision'} workload at {n}^3 ...")
+    d = W.mixed_depth_512(n=n, steps=steps) if scale else W.mixed_depth_256(n=n, steps=steps)
     recipe = ("lognormal sigma 2, optical depth 1e-4..1e4, dt = 200 light-crossing times" if scale else
               "lognormal sigma 1.5, optical depth 1e-3..1e3, dt = 50 light-crossing times")
+    faces = d["bc"] if isinstance(d["bc"], str) else "/".join(d["bc"])
     dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
     state0 = (dev(d["E"]), dev(d["F"]), dev(d["T"]))
     c32 = tuple(dev(d[k], torch.float32) for k in ("rho", "kP", "kR", "f"))
     N = n ** 3
 
     log("mixed path (FP32 Krylov + FP64 residual/refinement/exchange, FP32 coefficient storage):")
-    mixed = run_path(torch, rad, d, state0, c32, "mixed", args.steps, args.warmup, args.tol, not args.no_profile,
+    mixed = run_path(torch, rad, d, state0, c32, "mixed", steps, warmup, args.tol, not args.no_profile,
                      args.gmres_m, args.autotune, args.eps_r, args.krylov_poly)
-    value = N * args.steps / mixed["seconds"]
+    value = N * steps / mixed["seconds"]
     out_m = [t.cpu().numpy() for t in mixed["state"]]
 
-    # local M1 closure (Sec. 4.1) from the final state, FP32 output as the mixed path consumes it
-    rad.profile_reset()
-    rad.profile(True)
-    fcl = torch.empty((6, n, n, n), dtype=torch.float32, device="cuda")
-    for _ in range(10):
-        rad.rad_closure(mixed["state"][0], mixed["state"][1], "m1", d["c"], f=fcl)
-    torch.cuda.synchronize()
-    cl = rad.profile_read().get("closure")
-    rad.profile(False)
-    del fcl
-    closure = None if not cl else {"kernel": "k_closure (M1, FP32 out)", "us_per_launch": 1000 * cl["ms"] / cl["launches"],
-                                   "algorithmic_bytes_per_launch": cl["bytes"] / cl["launches"],
-                                   "achieved_GBps": cl["bytes"] / (cl["ms"] * 1e-3) / 1e9}
+    closure = None
+    if with_closure:
+        # local M1 closure (Sec. 4.1) from the final state, FP32 output as the mixed path consumes it
+        rad.profile_reset()
+        rad.profile(True)
+        fcl = torch.empty((6, n, n, n), dtype=torch.float32, device="cuda")
+        for _ in range(10):
+            rad.rad_closure(mixed["state"][0], mixed["state"][1], "m1", d["c"], f=fcl)
+        torch.cuda.synchronize()
+        cl = rad.profile_read().get("closure")
+        rad.profile(False)
+        del fcl
+        closure = None if not cl else {"kernel": "k_closure (M1, FP32 out)",
+                                       "us_per_launch": 1000 * cl["ms"] / cl["launches"],
+                                       "algorithmic_bytes_per_launch": cl["bytes"] / cl["launches"],
+                                       "achieved_GBps": cl["bytes"] / (cl["ms"] * 1e-3) / 1e9}
 
     fp64 = None
-    if not args.no_fp64:
+    if with_fp64:
         log("FP64 path (FP64 Krylov, FP64 coefficient storage):")
         c64 = tuple(dev(d[k]) for k in ("rho", "kP", "kR", "f"))
-        fp64 = run_path(torch, rad, d, state0, c64, "fp64", args.steps, args.warmup, args.tol, False, args.gmres_m,
+        fp64 = run_path(torch, rad, d, state0, c64, "fp64", steps, warmup, args.tol, False, args.gmres_m,
                         args.autotune, args.eps_r, args.krylov_poly)
         del c64
 
     res = {
-        "metric": METRIC,
+        "metric": METRIC if not scale else "implicit VET rad-step cell-updates/s at 512^3 (scale recipe), mixed path",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * mixed["seconds"] / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1000.0 * mixed["seconds"] / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"mixed-depth medium {n}^3 ({recipe}), periodic, "
-                               f"FP32-exact inputs, {args.steps} implicit steps, tol {args.tol:g}",
+        "config": {"workload": f"mixed-depth medium {n}^3 ({recipe}), {faces} faces, "
+                               f"FP32-exact inputs, {steps} implicit steps, tol {args.tol:g}",
                    "cells": N, "gmres_m": (mixed["tuned"] or {}).get("gmres_m", args.gmres_m),
                    "krylov_poly": (mixed["tuned"] or {}).get("krylov_poly", args.krylov_poly),
                    "autotune": mixed["tuned"],
                    "precision": "FP32 Krylov/apply, FP64 residual, refinement and exchange"},
-        "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
+        "krylov_iters_per_step": sum(s["krylov_iters"] for s in mixed["stats"]) / steps,
         "krylov_iters_per_s": sum(s["krylov_iters"] for s in mixed["stats"]) / mixed["seconds"],
         "operator_applies_per_step": (1, 2, 3)[(mixed["tuned"] or {}).get("krylov_poly", args.krylov_poly)]
-                                     * sum(s["krylov_iters"] for s in mixed["stats"]) / args.steps,
-        "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / args.steps,
+                                     * sum(s["krylov_iters"] for s in mixed["stats"]) / steps,
+        "picard_iters_per_step": sum(s["picard_iters"] for s in mixed["stats"]) / steps,
         "converged_steps": sum(1 for s in mixed["stats"] if s["rc"] == 0),
         "final_scaled_residual": mixed["stats"][-1]["scaled_residual"],
+        "energy_defect_last_step": mixed["stats"][-1]["energy_defect"],
+        "algorithmic_bytes_per_step": sum(s["bytes_moved"] for s in mixed["stats"]) / steps,
     }
     if fp64 is not None:
-        v64 = N * args.steps / fp64["seconds"]
+        v64 = N * steps / fp64["seconds"]
         out_d = [t.cpu().numpy() for t in fp64["state"]]
         res["fp64_value"] = v64
-        res["fp64_ms_per_step"] = 1000.0 * fp64["seconds"] / args.steps
+        res["fp64_ms_per_step"] = 1000.0 * fp64["seconds"] / steps
         res["speedup_mixed_vs_fp64"] = value / v64
-        res["fp64_krylov_iters_per_step"] = sum(s["krylov_iters"] for s in fp64["stats"]) / args.steps
+        res["fp64_krylov_iters_per_step"] = sum(s["krylov_iters"] for s in fp64["stats"]) / steps
         res["fp64_converged_steps"] = sum(1 for s in fp64["stats"] if s["rc"] == 0)
         res["relerr_mixed_vs_fp64"] = {k: relerr(a, b) for k, a, b in zip(("E", "F", "T"), out_m, out_d)}
+        del out_d
 
     if not args.no_oracle_check:
         import oracle
@@ -451,6 +500,7 @@ def main():
         prev = [t.cpu().numpy() for t in mixed["prev"]]
         r = P.scaled_residual(*prev, *out_m)
         res["oracle_scaled_residual_last_step"] = r[3]
+        del P, prev
 
     if closure:
         res["closure_m1"] = closure
@@ -461,7 +511,7 @@ def main():
         gbs = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": gbs / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(dom) if (n == 256 and not scale) else None,
+                           "traffic": measured_traffic(dom, n),
                            "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
                            "avg_launch_us": 1000.0 * e["ms"] / e["launches"], "launches": e["launches"]}
         # the whole step: every kernel's algorithmic bytes over the step's wall time
@@ -488,11 +538,8 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
         del x, y
-
-    if not args.no_cpu_baseline:
-        log(f"CPU oracle baseline at {args.cpu_sample_n}^3 ...")
-        res["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.tol)
-    print(json.dumps(res), flush=True)
+    del mixed, state0, c32, d, out_m
+    return res
 
 
 if __name__ == "__main__":

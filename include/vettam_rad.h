@@ -396,6 +396,10 @@ int rad_profile_get(int idx, const char **name, double *ms, double *bytes, long 
 /* Message of the last non-OK return on this thread ("" if none). */
 const char *rad_last_error(void);
 
+/* Build id: a hash of the sources the library was built from (also part of
+ * every autotune cache key, so tuned entries of one build do not steer another). */
+const char *rad_build_id(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,14 +25,30 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"--off
           "-I", os.path.join(ROOT, "include")]
 
 
+def source_id() -> str:
+    """Build id of the library: a hash of every file under csrc/ and of the public header.  The library
+    reports the id it was built from (rad_build_id) and the binding refuses a library whose id differs
+    from that of the sources beside it."""
+    import hashlib
+    h = hashlib.sha256()
+    files = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))] + [os.path.join(ROOT, "include", "vettam_rad.h")]
+    for path in files:
+        if os.path.isfile(path):
+            h.update(os.path.basename(path).encode())
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def _compile(src):
+def _compile(src, build_id):
     out = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [_hipcc(), *COMMON, *DEVICE_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [_hipcc(), *COMMON, *DEVICE_FLAGS, f'-DVETTAM_BUILD_ID="{build_id}"', *lang, "-c",
+           os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -45,8 +61,9 @@ def _compile(src):
 def build(verbose=False) -> str:
     """Compile all sources and link libvettam_rad.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
+    bid = source_id()
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, bid), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

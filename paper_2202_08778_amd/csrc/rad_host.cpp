@@ -1,6 +1,10 @@
 // rad_host.cpp -- error state, defaults, parameter checks, profiler and autotune cache of the C ABI.
 #include "rad_host.h"
 
+#ifndef VETTAM_BUILD_ID
+#define VETTAM_BUILD_ID "unknown"
+#endif
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -200,6 +204,8 @@ extern "C" int rad_profile_get(int idx, const char **name, double *ms, double *b
 
 extern "C" const char *rad_last_error(void) { return vr::g_err.c_str(); }
 
+extern "C" const char *rad_build_id(void) { return VETTAM_BUILD_ID; }
+
 extern "C" void rad_default_params(rad_params_t *p)
 {
     if (!p) return;
@@ -278,7 +284,8 @@ std::string device_tag()
         arch = prop.gcnArchName;
         cus = prop.multiProcessorCount;
     }
-    return arch + "|cu" + std::to_string(cus);
+    // the build id keeps tuned entries of one build from steering another
+    return arch + "|cu" + std::to_string(cus) + "|" + VETTAM_BUILD_ID;
 }
 
 }  // namespace vr

@@ -120,6 +120,13 @@ def _load():
     L.rad_profile_get.restype = I
     L.rad_last_error.argtypes = []
     L.rad_last_error.restype = ct.c_char_p
+    L.rad_build_id.argtypes = []
+    L.rad_build_id.restype = ct.c_char_p
+    from .build import source_id
+    built, here = L.rad_build_id().decode(), source_id()
+    if built != here:
+        raise ImportError(f"{LIB_PATH} was built from other sources (build id {built}, sources {here}): "
+                          "rebuild it with paper_2202_08778_amd.build.build()")
     return L
 
 
@@ -133,7 +140,8 @@ EXPORTED = ("rad_default_params", "rad_workspace_bytes", "rad_step", "rad_noallo
             "rad_apply", "rad_exchange", "rad_closure", "rad_batched_workspace_bytes", "rad_plan_batched",
             "rad_autotune_scratch_bytes", "rad_autotune_batched", "rad_step_batched", "rad_plan_launch_shape",
             "rad_plan_reorder", "rad_plan_destroy",
-            "rad_profile_enable", "rad_profile_reset", "rad_profile_count", "rad_profile_get", "rad_last_error")
+            "rad_profile_enable", "rad_profile_reset", "rad_profile_count", "rad_profile_get", "rad_last_error",
+            "rad_build_id")
 
 
 def last_error() -> str:
