@@ -354,6 +354,8 @@ def main():
     ap.add_argument("--gmres-m", type=int, default=None,
                     help="GMRES restart length (default 8 on the grids, where orthogonalisation grows with m "
                          "while the iteration count barely changes; the library's 12 for --batched)")
+    ap.add_argument("--bc", choices=("open", "outflow", "periodic"), default=None,
+                    help="faces of the uniform-grid workloads (default: open, the characteristic outflow)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-scale-leg", action="store_true",
                     help="skip the 512^3 scale leg (mixed path, 1 warm-up + 3 steps) of the default run")
@@ -413,6 +415,8 @@ def bench_grid(args, torch, np, rad, W, scale, n, steps, warmup, with_fp64, with
     FP64 path from the same state, the oracle's residual of the last mixed step and the roofline."""
     log(f"generating the {'scale' if scale else 'precision'} workload at {n}^3 ...")
     d = W.mixed_depth_512(n=n, steps=steps) if scale else W.mixed_depth_256(n=n, steps=steps)
+    if args.bc:
+        d["bc"] = args.bc
     recipe = ("lognormal sigma 2, optical depth 1e-4..1e4, dt = 200 light-crossing times" if scale else
               "lognormal sigma 1.5, optical depth 1e-3..1e3, dt = 50 light-crossing times")
     faces = d["bc"] if isinstance(d["bc"], str) else "/".join(d["bc"])

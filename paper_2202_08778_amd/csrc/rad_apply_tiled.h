@@ -12,10 +12,13 @@
 // through the boundary rule (periodic: wrap, any wall: the boundary cell
 // itself), so boundary faces and ragged tile edges need no special cases: a
 // zero-gradient wall's face carries the cell's physical flux and no
-// dissipation; at an open, Marshak or reflecting wall the cell's own values are
-// then replaced by the wall's ghost (a per-lane branch taken by boundary lanes
-// only).  The per-cell epilogue is a functor: the Krylov operator apply and
-// the FP64 residual of one Picard iteration share the sweep.
+// dissipation.  An open, Marshak or reflecting wall adds the difference to the
+// flux against its ghost, which is local to the cell (the HLLE flux is linear
+// in the neighbour's state): tiles holding wall cells compute it in uniform
+// branches on every lane and keep it on the wall's lanes, so the sweep carries
+// no per-lane branch and no ghost data.  The per-cell epilogue is a functor:
+// the Krylov operator apply and the FP64 residual of one Picard iteration
+// share the sweep.
 #pragma once
 #include "rad_device.h"
 #include "rad_amr.h"
@@ -127,10 +130,12 @@ struct CellSums {
 // precomputed too; otherwise each face's speed is formed from f and sR.
 // lex(k, pb, o, e) loads the NE per-cell extras of the epilogue (plane k, its
 // base pb, in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell;
-// wall(kind, d, side, Ec, Fc, fcr, e, En, Fn, fnr) overwrites the neighbour
-// values across an open, Marshak or reflecting wall with the wall's ghost.
+// wall(kind, d, side, Ec, Fc, fcr, e, Eg, Fg, fg) forms the ghost across an
+// open, Marshak or reflecting wall from the cell's values (and its extras e);
+// WL: the grid has such walls (the sweep without them has no wall code at all).
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
-template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, class LEX, class EPI, class WALL>
+template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, bool WL = false, class LEX, class EPI,
+          class WALL>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
@@ -141,6 +146,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     constexpr int TYT = TileShape<AT>::TYT, CPT = TileShape<AT>::CPT;
     constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
     static_assert(PRE || !CST, "stored face speeds come with stored sR");
+    static_assert(!CALL || CST, "the nonlinear residual reads stored face speeds");
     constexpr int NC = CST ? 3 : 0;
     constexpr int IX = Rec<CST>::IX, IF = Rec<CST>::IF, IS = Rec<CST>::IS, IC = Rec<CST>::IC, NL = Rec<CST>::NL;
 
@@ -172,9 +178,9 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     }
     int hly = -1, hlx = -1;
     unsigned hoff = 0;
+    int gxh = 0, gyh = 0;
     if (threadIdx.x < kHalo) {
         const int h = threadIdx.x;
-        int gxh, gyh;
         if (h < kTX) { hlx = h + 1; hly = 0; gxh = x0 + h; gyh = y0 - 1; }
         else if (h < 2 * kTX) { hlx = h - kTX + 1; hly = kLY - 1; gxh = x0 + h - kTX; gyh = y0 + kTY; }
         else if (h < 2 * kTX + kTY) { hlx = 0; hly = h - 2 * kTX + 1; gxh = x0 - 1; gyh = y0 + h - 2 * kTX; }
@@ -193,6 +199,24 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         selfy_hi[c] = map_axis(gy + 1, g.ny, g.bclo[1], g.bchi[1]) == my;
     }
     auto mapz = [&](int q) { return map_axis(q, g.nz, g.bclo[2], g.bchi[2]); };
+    // the six faces' kinds packed 4 bits each (face 2 d + side), and the faces of the thread's cells on
+    // open, Marshak or reflecting walls (bits: x lo, x hi, y lo, y hi)
+    unsigned kinds = 0;
+    for (int fi = 0; fi < 6; ++fi) kinds |= (unsigned)((fi & 1) ? g.bchi[fi >> 1] : g.bclo[fi >> 1]) << (4 * fi);
+    auto kind_of = [&](int d, int side) { return (int)((kinds >> (4 * (2 * d + side))) & 15u); };
+    const bool zwall_lo = WL && kind_of(2, 0) >= BC_OPEN, zwall_hi = WL && kind_of(2, 1) >= BC_OPEN;
+    unsigned wmask[CPT];
+    for (int c = 0; c < CPT; ++c)
+        wmask[c] = !(WL && active[c]) ? 0u
+                   : (selfx_lo && kind_of(0, 0) >= BC_OPEN ? 1u : 0u) | (selfx_hi && kind_of(0, 1) >= BC_OPEN ? 2u : 0u) |
+                         (selfy_lo[c] && kind_of(1, 0) >= BC_OPEN ? 4u : 0u) |
+                         (selfy_hi[c] && kind_of(1, 1) >= BC_OPEN ? 8u : 0u);
+    // tiles holding cells on such walls (uniform; bits as wmask)
+    const unsigned twall = !WL ? 0u
+                           : (x0 == 0 && kind_of(0, 0) >= BC_OPEN ? 1u : 0u) |
+                                 (x0 + kTX >= g.nx && kind_of(0, 1) >= BC_OPEN ? 2u : 0u) |
+                                 (y0 == 0 && kind_of(1, 0) >= BC_OPEN ? 4u : 0u) |
+                                 (y0 + kTY >= g.ny && kind_of(1, 1) >= BC_OPEN ? 8u : 0u);
 
     // one cell's record in registers (in flight from HBM)
     struct Full {
@@ -257,9 +281,44 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
             lds[sl][IS][hly][hlx] = u.v[7];
     };
 
+    const AT tk = (AT)g.tau_k;
+    // The correction that turns the flux of wall face (d, side) of a cell from the self-mapped one
+    // the sweep computed (neighbour = the cell itself: the cell's physical flux, whatever the speed)
+    // into the flux against the wall's ghost, which the wall functor forms from the cell's state,
+    // tensor row and (the nonlinear residual) the walls' data; plus the wall's shares of the Jacobi
+    // diagonal.  Cw: the wall's speed (the cell's own).  m: 1 for a cell on the wall, else 0 -- the
+    // correction is computed by every lane of a tile holding such cells (uniform branches, no
+    // per-lane ones) and kept by those on the wall.
+    // (d is a constant once the face loops are unrolled)
+    auto wall_fix_k = [&](auto K, int d, int side, AT m, AT Cw, const AT(&fr)[3], const AT(&e)[NE > 0 ? NE : 1],
+                          CellSums<AT> &S) __attribute__((always_inline)) {
+        constexpr int kind = decltype(K)::value;
+        AT Eg, Fg[3], fg[3];
+        wall(kind, d, side, S.Ec, S.Fc, fr, e, Eg, Fg, fg);
+        const AT sg = side ? AT(1) : AT(-1), ms = m * sg, hc = AT(-0.5) * sg * Cw;
+        S.dEs += ms * (AT(0.5) * (Fg[d] - S.Fc[d]) + hc * (Eg - S.Ec));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S.dF[q] += ms * (AT(0.5) * (fg[q] * Eg - fr[q] * S.Ec) + hc * (Fg[q] - S.Fc[q]));
+        if constexpr (PRE) {
+            AT qE, qF;
+            wall_diag_q<AT>(kind, d, fr, Cw, qE, qF);
+            S.wE += m * qE;
+            S.wF[d] += m * qF;
+        }
+    };
+    // the kind is uniform: a scalar branch to code specialised for it
+    auto wall_fix = [&](int kind, int d, int side, AT m, AT Cw, const AT(&fr)[3], const AT(&e)[NE > 0 ? NE : 1],
+                        CellSums<AT> &S) __attribute__((always_inline)) {
+        if (kind == BC_OPEN)
+            wall_fix_k(std::integral_constant<int, BC_OPEN>{}, d, side, m, Cw, fr, e, S);
+        else if (kind == BC_MARSHAK)
+            wall_fix_k(std::integral_constant<int, BC_MARSHAK>{}, d, side, m, Cw, fr, e, S);
+        else
+            wall_fix_k(std::integral_constant<int, BC_REFLECT>{}, d, side, m, Cw, fr, e, S);
+    };
+
     ZRow prev[CPT];
     AT ex[CPT][NE > 0 ? NE : 1];
-    const AT tk = (AT)g.tau_k;
 
     // Plane k of the tile from LDS slot a, its upper z neighbour from slot b,
     // the lower one from registers.
@@ -302,12 +361,6 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                     else
                         Cface = face_speed<AT>(fcr[d], fnr[d], S.sc, lds[a][IS][ny_][nx_], tk);
                     const bool self = d == 0 ? (side ? selfx_hi : selfx_lo) : (side ? selfy_hi[c] : selfy_lo[c]);
-                    const int wk = self ? wall_kind(g, d, side) : BC_PERIODIC;
-                    if (wk >= BC_OPEN) {   // boundary lanes only: the wall's ghost, at the cell's own speed
-                        wall(wk, d, side, S.Ec, S.Fc, fcr, ex[c], En, Fn, fnr);
-                        Cface = self_speed(fcr[d]);
-                        wall_diag<AT>(wk, d, fcr, Cface, S.wE, S.wF);
-                    }
                     S.sumC_nb += self ? AT(0) : Cface;
                     if constexpr (CALL) {
                         if (CST && side && self)
@@ -316,6 +369,13 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                             S.sumC_all += Cface;
                     }
                     face_flux_acc<AT>(d, side, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
+                    // an open, Marshak or reflecting wall (y: the lowest row only holds the first cell);
+                    // its speed: a low face's stored speed is the cell's own, a high face's is formed
+                    if (WL && (twall & (1u << (2 * d + side))) && !(d == 1 && side == 0 && c > 0)) {
+                        const AT m = AT((wmask[c] >> (2 * d + side)) & 1u);
+                        const AT Cw = (CST && side) ? self_face_speed<AT>(fcr[d], S.sc, tk) : Cface;
+                        wall_fix(kind_of(d, side), d, side, m, Cw, fcr, ex[c], S);
+                    }
                 }
             }
             // z faces: lower from registers, upper from slot b
@@ -331,15 +391,11 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                     Cface = lds[a][IC + 2][sy][sxx];
                 else
                     Cface = face_speed<AT>(fcr[2], P.f[2], S.sc, P.s, tk);
-                const int wk = selfz_lo ? wall_kind(g, 2, 0) : BC_PERIODIC;
-                if (wk >= BC_OPEN) {
-                    wall(wk, 2, 0, S.Ec, S.Fc, fcr, ex[c], En, Fn, fnr);
-                    Cface = self_speed(fcr[2]);
-                    wall_diag<AT>(wk, 2, fcr, Cface, S.wE, S.wF);
-                }
                 S.sumC_nb += selfz_lo ? AT(0) : Cface;
                 if constexpr (CALL) S.sumC_all += Cface;
                 face_flux_acc<AT>(2, 0, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
+                if (WL && selfz_lo && zwall_lo)   // uniform: the grid's bottom plane
+                    wall_fix(kind_of(2, 0), 2, 0, AT(1), Cface, fcr, ex[c], S);
             }
             {
                 AT En = lds[b][IX][sy][sxx];
@@ -351,12 +407,6 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                     Cface = lds[b][IC + 2][sy][sxx];
                 else
                     Cface = face_speed<AT>(fcr[2], fnr[2], S.sc, lds[b][IS][sy][sxx], tk);
-                const int wk = selfz_hi ? wall_kind(g, 2, 1) : BC_PERIODIC;
-                if (wk >= BC_OPEN) {
-                    wall(wk, 2, 1, S.Ec, S.Fc, fcr, ex[c], En, Fn, fnr);
-                    Cface = self_speed(fcr[2]);
-                    wall_diag<AT>(wk, 2, fcr, Cface, S.wE, S.wF);
-                }
                 S.sumC_nb += selfz_hi ? AT(0) : Cface;
                 if constexpr (CALL) {
                     if (CST && selfz_hi)
@@ -365,6 +415,9 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                         S.sumC_all += Cface;
                 }
                 face_flux_acc<AT>(2, 1, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
+                if (WL && selfz_hi && zwall_hi)   // uniform: the grid's top plane
+                    wall_fix(kind_of(2, 1), 2, 1, AT(1),
+                             CST ? self_face_speed<AT>(fcr[2], S.sc, tk) : Cface, fcr, ex[c], S);
             }
             epi(k, c, off[c], active[c], S, ex[c]);
             // this plane becomes the lower neighbour of the next one
@@ -492,7 +545,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // is *xs times xm.  qv (PRE, pg = 0): y = s x + qm (qs qv - D^-1 A (s x)), a damped
 // Jacobi sweep on B e = qs qv.  dout (PRE): also write the Jacobi diagonal D (E
 // row, then the F rows' common value; two planes).  Used by the multigrid cycle.
-template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true>
+template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true, bool WL = false>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
@@ -554,11 +607,19 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             }
         }
         if constexpr (PRE) {
-            const AT DE = dEc + dtr + nu * S.wE, DF0 = AT(1) + S.sc + dtr;
+            AT DE = dEc + dtr, DF[3];
+            DF[0] = DF[1] = DF[2] = AT(1) + S.sc + dtr;
+            if constexpr (WL) {   // the walls' shares, per row
+                DE += nu * S.wE;
+                for (int q = 0; q < 3; ++q) DF[q] += nu * S.wF[q];
+            }
             yE *= AT(1) / DE;
-            AT DF[3];
-            for (int q = 0; q < 3; ++q) DF[q] = DF0 + nu * S.wF[q];
-            for (int q = 0; q < 3; ++q) yFq[q] *= AT(1) / DF[q];
+            if constexpr (WL) {
+                for (int q = 0; q < 3; ++q) yFq[q] *= AT(1) / DF[q];
+            } else {
+                const AT iDF = AT(1) / DF[0];
+                for (int q = 0; q < 3; ++q) yFq[q] *= iDF;
+            }
             if (dout && active) {   // the Jacobi diagonal itself (E row, the F rows' mean)
                 st_off(dout + pb, o, DE);
                 st_off(dout + N + pb, o, (DF[0] + DF[1] + DF[2]) * AT(1.0 / 3.0));
@@ -582,7 +643,7 @@ __global__ void __launch_bounds__(tile_threads<AT>())
         const AT z3[3] = {AT(0), AT(0), AT(0)};
         wall_ghost<AT>(kind, d, side, Ec, Fc, fcr, AT(0), z3, AT(0), En, Fn, fnr);
     };
-    tile_sweep<AT, ST, PRE, false, NEX, CS>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi, wall);
+    tile_sweep<AT, ST, PRE, false, NEX, CS, WL>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi, wall);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

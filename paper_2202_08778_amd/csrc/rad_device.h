@@ -131,28 +131,22 @@ template <class T>
 __device__ __forceinline__ void wall_ghost(int kind, int d, int side, T Ec, const T (&Fc)[3], const T (&fcr)[3],
                                            T Eo, const T (&Fo)[3], T e8, T &Eg, T (&Fg)[3], T (&fg)[3])
 {
+    // d and kind may be run-time values (divergent among lanes): components and kinds are
+    // selected, never indexed or branched on
     const T s = side ? T(-1) : T(1);
-    Eg = Ec;
+    const T fdd = d == 0 ? fcr[0] : (d == 1 ? fcr[1] : fcr[2]);
+    const T Fcd = d == 0 ? Fc[0] : (d == 1 ? Fc[1] : Fc[2]);
+    const T Fod = d == 0 ? Fo[0] : (d == 1 ? Fo[1] : Fo[2]);
+    const bool op = kind == BC_OPEN && fdd > T(0), ms = kind == BC_MARSHAK, rf = kind == BC_REFLECT;
+    const T ia = op ? T(1) / xsqrt(fdd) : T(0);
+    const T delta = op ? T(0.5) * ((Eo + s * Fod * ia) - (Ec + s * Fcd * ia)) : T(0);
+    const T Em = e8 - T(4) * s * Fcd - Ec;
+    Eg = ms ? Em : Ec + delta;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        Fg[j] = Fc[j];
-        fg[j] = fcr[j];
-    }
-    if (kind == BC_OPEN) {
-        if (fcr[d] > T(0)) {
-            const T ia = T(1) / xsqrt(fcr[d]);
-            const T delta = T(0.5) * ((Eo + s * Fo[d] * ia) - (Ec + s * Fc[d] * ia));
-            Eg += delta;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Fg[j] += delta * s * fcr[j] * ia;
-        }
-    } else if (kind == BC_MARSHAK) {
-        Eg = e8 - T(4) * s * Fc[d] - Ec;
-    } else if (kind == BC_REFLECT) {
-        Fg[d] = -Fc[d];
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            if (j != d) fg[j] = -fcr[j];
+        const T Fj = Fc[j] + delta * s * fcr[j] * ia;
+        Fg[j] = (rf && j == d) ? -Fc[j] : Fj;
+        fg[j] = (rf && j != d) ? -fcr[j] : fcr[j];
     }
 }
 
@@ -160,22 +154,39 @@ __device__ __forceinline__ void wall_ghost(int kind, int d, int side, T Ec, cons
 // contribution with respect to the cell's own unknowns, to be multiplied by
 // nu): open: (sqrt(f_dd) + C)/4 in the E and F_d rows; Marshak: C in the E row,
 // 2 f_dd in the F_d row; reflect: C in the F_d row.  The other rows get nothing
-// from a wall (their ghost values follow the cell's one to one).
+// from a wall (their ghost values follow the cell's one to one).  qE, qF: the
+// shares of the E row and of the F_d row.
+template <class T>
+__device__ __forceinline__ void wall_diag_q(int kind, int d, const T (&fcr)[3], T C, T &qE, T &qF)
+{
+    const T fdd = d == 0 ? fcr[0] : (d == 1 ? fcr[1] : fcr[2]);
+    const bool op = kind == BC_OPEN && fdd > T(0);
+    const T qo = T(0.25) * (xsqrt(op ? fdd : T(0)) + C);
+    qE = op ? qo : (kind == BC_MARSHAK ? C : T(0));
+    qF = op ? qo : (kind == BC_MARSHAK ? T(2) * fdd : (kind == BC_REFLECT ? C : T(0)));
+}
 template <class T>
 __device__ __forceinline__ void wall_diag(int kind, int d, const T (&fcr)[3], T C, T &wE, T (&wF)[3])
 {
-    if (kind == BC_OPEN) {
-        if (fcr[d] > T(0)) {
-            const T q = T(0.25) * (xsqrt(fcr[d]) + C);
-            wE += q;
-            wF[d] += q;
-        }
-    } else if (kind == BC_MARSHAK) {
-        wE += C;
-        wF[d] += T(2) * fcr[d];
-    } else if (kind == BC_REFLECT) {
-        wF[d] += C;
-    }
+    T qE, qF;
+    wall_diag_q<T>(kind, d, fcr, C, qE, qF);
+    wE += qE;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) wF[j] += j == d ? qF : T(0);
+}
+
+// face_speed of a face between a cell and itself (a wall's speed), without branches; the same
+// operations, so the same value.
+template <class T>
+__device__ __forceinline__ T self_face_speed(T fdd, T sR, T tau_k)
+{
+    T t = tau_k * sR * sR / fdd;
+    t = fdd == T(0) ? T(INFINITY) : t;
+    t = sR == T(0) ? T(0) : t;
+    const T tau = T(0.5) * (t + t);
+    const T r = xsqrt(-xexpm1(-tau) / tau);
+    const T corr = tau == T(0) ? T(1) : (isinf(tau) ? T(0) : r);
+    return xsqrt(fdd) * corr;
 }
 
 // Accumulate the HLLE flux of the face on side `side` (0: low, 1: high) along

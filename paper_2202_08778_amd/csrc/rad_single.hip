@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kBlock)
 // emission keeps the fraction 1 - eta of the energy row's O(v/c) terms (the gas
 // energy eliminated, as for the emission) and writes that row's coupling to Ft
 // for the Krylov apply (vbw).
-template <class CT, class KT, class DT, bool AMR = false, int VEL = 0>
+template <class CT, class KT, class DT, bool AMR = false, int VEL = 0, bool WL = false>
 __global__ void __launch_bounds__(tile_threads<double>())
     k_residual_tiled(Grid g, TileGeom tg, int picard_mode, const double *__restrict__ En,
                      const double *__restrict__ Fn, const double *__restrict__ Tn, const double *__restrict__ Ts,
@@ -231,13 +231,13 @@ __global__ void __launch_bounds__(tile_threads<double>())
             }
         }
         const double rE = bE - (dE * E + divE);
-        const double DE = dE + dtr + nu * S.wE, DF = 1.0 + sR + dtr;
+        const double DE = dE + dtr + (WL ? nu * S.wE : 0.0), DF = 1.0 + sR + dtr;
         const double WE = 1.0 + sP + half * S.sumC_all, WF = 1.0 + sR + half * S.sumC_all;
         const double zE = rE / DE;
         double zF[3], zz = zE * zE, wf = 0, fn = 0;
         for (int q = 0; q < 3; ++q) {
             const double rF = e[1 + q] * invc - ((1.0 + sR) * S.Fc[q] + divF[q]);
-            zF[q] = rF / (DF + nu * S.wF[q]);
+            zF[q] = rF / (WL ? DF + nu * S.wF[q] : DF);
             zz += zF[q] * zF[q];
             wf += (rF / WF) * (rF / WF);
             fn += S.Fc[q] * S.Fc[q];
@@ -261,8 +261,8 @@ __global__ void __launch_bounds__(tile_threads<double>())
         const double Fo[3] = {e[1] * invc, e[2] * invc, e[3] * invc};
         wall_ghost<double>(kind, d, side, Ec, Fc, fcr, e[0], Fo, g.finc8[2 * d + side], En_, Fn_, fnr);
     };
-    tile_sweep<double, CT, true, true, NEX>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64, X, 1.0,
-                                            1.0, lds, lex, epi, wall);
+    tile_sweep<double, CT, true, true, NEX, true, WL>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64,
+                                                      X, 1.0, 1.0, lds, lex, epi, wall);
     block_store<5, tile_threads<double>()>(acc, partials, blockIdx.x);
 }
 
@@ -977,6 +977,7 @@ struct Solver {
     Grid mg[kMaxMg];      // their grids (mg[0] = g)
     long long c0[2] = {0, 0};
     bool amr = false;
+    bool walls = false;   // an open, Marshak or reflecting face (uniform single grids only)
     Amr A{};
     long long nshell = 0, ncoarse = 0;  // threads of the level-jump kernel
     long long Ntot = 0;                 // cells of all levels
@@ -1113,6 +1114,7 @@ int run_step(Solver &S)
         });
     // moving medium: the O(v/c) coefficients, once per step
     const bool vel = S.beta != nullptr;
+    const bool walls = S.walls;
     const int vimp = vel && p.vel_implicit;
     double *VA = vel ? S.at<double>(S.L.VA) : nullptr, *VB = vel ? S.at<double>(S.L.VB) : nullptr;
     double *VC = vel ? S.at<double>(S.L.VC) : nullptr;
@@ -1156,8 +1158,27 @@ int run_step(Solver &S)
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
             const long long o = S.c0[l];
+            // grids with open, Marshak or reflecting walls take the sweep with the wall code
+            auto go_w = [&](auto amr_c, auto vel_c, auto lc_c) {
+                constexpr bool VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
+                if constexpr (!decltype(amr_c)::value) {
+                    if (fA)
+                        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, false, VL, LC, true>), tiles(tg[l]), bt, 0,
+                                           S.st, S.gl[l], tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
+                                           (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
+                                           y + 4 * o, AT(1), AT(1), AmrLv{}, (const AT *)VBA, (const AT *)VCA, pg, xm,
+                                           qv, qm, qs, dout);
+                    else
+                        hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, false, VL, LC, true>), tiles(tg[l]), bt, 0,
+                                           S.st, S.gl[l], tg[l], f + 6 * o, sR + o, (const CT *)nullptr,
+                                           (const CT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
+                                           y + 4 * o, AT(1), AT(1), AmrLv{}, (const AT *)VBA, (const AT *)VCA, pg, xm,
+                                           qv, qm, qs, dout);
+                }
+            };
             auto go = [&](auto amr_c, auto vel_c, auto lc_c) {
                 constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
+                if (walls) return go_w(std::bool_constant<AM>{}, std::bool_constant<VL>{}, std::bool_constant<LC>{});
                 if (fA)
                     hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
                                        tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
@@ -1250,11 +1271,12 @@ int run_step(Solver &S)
     // (profiled as the multigrid class, so the grid's apply keeps its own class)
     auto mg_apply = [&](int l, const AT *x, AT xm, AT *y, AT pg, const AT *qv, AT qm, AT *dout) {
         const int tok = prof_begin(K_MG, S.st);
-        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, false, false, true>), tiles(ml[l].tg), bt, 0, S.st, S.mg[l],
-                           ml[l].tg, (const AT *)ml[l].f, (const AT *)ml[l].sR, (const AT *)nullptr,
-                           (const AT *)nullptr, (const AT *)ml[l].Cf, (const AT *)ml[l].dE, x,
-                           (const double *)nullptr, y, AT(1), AT(1), AmrLv{}, (const AT *)nullptr,
-                           (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout);
+        auto kern = walls ? k_apply_tiled<AT, AT, true, false, false, true, true>
+                          : k_apply_tiled<AT, AT, true, false, false, true, false>;
+        hipLaunchKernelGGL(kern, tiles(ml[l].tg), bt, 0, S.st, S.mg[l], ml[l].tg, (const AT *)ml[l].f,
+                           (const AT *)ml[l].sR, (const AT *)nullptr, (const AT *)nullptr, (const AT *)ml[l].Cf,
+                           (const AT *)ml[l].dE, x, (const double *)nullptr, y, AT(1), AT(1), AmrLv{},
+                           (const AT *)nullptr, (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout);
         prof_end(tok, S.st, (double)S.mg[l].N * (8 * kb + 6 * kb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
     };
     // this Picard iteration's Jacobi diagonals of every level (dE changes with T*)
@@ -1322,11 +1344,13 @@ int run_step(Solver &S)
                 auto go = [&](auto amr_c, auto vel_c) {
                     constexpr bool AM = decltype(amr_c)::value;
                     constexpr int VL = decltype(vel_c)::value;
-                    hipLaunchKernelGGL((k_residual_tiled<CT, KT, AT, AM, VL>), tiles(tgr[l]), bt64, 0, S.st, S.gl[l],
-                                       tgr[l], p.mode, S.En + o, S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o,
-                                       f + 6 * o, sR64 + o, Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o,
-                                       part + rrows * 5, level_view(l, corr, sizeof(double)), (const double *)VA,
-                                       (const double *)VB, (const double *)VC, VBA);
+                    auto kern = (walls && !AM) ? k_residual_tiled<CT, KT, AT, false, VL, true>
+                                               : k_residual_tiled<CT, KT, AT, AM, VL, false>;
+                    hipLaunchKernelGGL(kern, tiles(tgr[l]), bt64, 0, S.st, S.gl[l], tgr[l], p.mode, S.En + o,
+                                       S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o, f + 6 * o, sR64 + o,
+                                       Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o, part + rrows * 5,
+                                       level_view(l, corr, sizeof(double)), (const double *)VA, (const double *)VB,
+                                       (const double *)VC, VBA);
                 };
                 if (S.amr)
                     go(std::true_type{}, std::integral_constant<int, 0>{});
@@ -1689,10 +1713,14 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
                        const void *f, double c, hipStream_t st)
 {
     const TileGeom tg = tile_geom<AT>(g);
-    hipLaunchKernelGGL((k_apply_tiled<AT, CT, false>), dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)),
+    bool walls = false;
+    for (int a = 0; a < 3; ++a) walls |= g.bclo[a] >= BC_OPEN || g.bchi[a] >= BC_OPEN;
+    auto kern = walls ? k_apply_tiled<AT, CT, false, false, false, true, true> : k_apply_tiled<AT, CT, false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)),
                        dim3(tile_threads<AT>()), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
                        (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
-                       (AT)(1.0 / c), (AT)c);
+                       (AT)(1.0 / c), (AT)c, AmrLv{}, (const AT *)nullptr, (const AT *)nullptr, AT(0), AT(1),
+                       (const AT *)nullptr, AT(0), AT(1), (AT *)nullptr);
 }
 
 }  // namespace
@@ -1779,6 +1807,7 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     S.host = host ? host : pinned_staging();
     if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
     S.g = make_grid(nx, ny, nz, bc, dt, dx, *p);
+    for (int a = 0; a < 6; ++a) S.walls |= bc[a] >= BC_OPEN;
     S.nlev = 1;
     S.gl[0] = S.g;
     S.mgL = 1;
