@@ -1,8 +1,8 @@
 // rad_apply_tiled.h -- the transport stencil as a 2.5D z-marching tile sweep (gfx950).
 //
 // A workgroup owns a 64 x 8 cell column of the grid over a range of z planes
-// (FP32: 256 threads, two cells each along y; FP64: 512 threads, one cell
-// each).  Two LDS slots hold the planes k and k+1 of the tile with a one-cell
+// (FP32: 256 threads, each with two cells adjacent along y; FP64: 512 threads,
+// one cell each).  Two LDS slots hold the planes k and k+1 of the tile with a one-cell
 // x/y halo (state, tensor, sR, low-face speeds); the plane k-1 of the thread's
 // own cells lives in registers.  Planes k+2 and k+3 are in flight in two
 // register sets used alternately, so every HBM value is read once per z-range
@@ -115,6 +115,22 @@ struct Rec {
     static constexpr int IX = 0, IF = 4, IS = 10, IC = 11, NL = 11 + (PRE ? 3 : 0);
 };
 
+// The coarse level of a multigrid pair, for sweeps fused with the transfers
+// between the two levels (FP32 tiles, whose threads hold y-pairs of cells):
+// restriction (the sweep's output t accumulates into the parents' right-hand
+// side qc = Dc^-1 mean_children(D t), D the Jacobi diagonal) and injection (the
+// sweep's operand is a x + ec(parent), the parents' coarse correction added as
+// the operand is loaded).
+template <class AT>
+struct MgFuse {
+    AT *qc = nullptr;         // restriction: the parents' right-hand side (4 planes)
+    const AT *Dc = nullptr;   // restriction: the parents' Jacobi diagonal (E row, F rows)
+    const AT *ec = nullptr;   // injection: the parents' correction (4 planes)
+    AT a = AT(1);             // injection: the operand's factor
+    long long Nc = 0;         // cells of the coarse level
+    int ncx = 0, ncy = 0;     // its extents in x and y
+};
+
 // Transport sums of one cell: dEs = sum_faces +-PhiE, dF likewise (without the
 // factor nu), the face speeds of the faces between two cells (Jacobi diagonal)
 // and of all six faces (residual weights; a wall face takes the cell's own
@@ -134,19 +150,20 @@ struct CellSums {
 // open, Marshak or reflecting wall from the cell's values (and its extras e);
 // WL: the grid has such walls (the sweep without them has no wall code at all).
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
-template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, bool WL = false, class LEX, class EPI,
-          class WALL>
+template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, bool WL = false, bool INJ = false,
+          class LEX, class EPI, class WALL>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
                                            const AT *__restrict__ x, AT s, AT sF,
                                            AT (&lds)[2][Rec<CST>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi,
-                                           WALL wall)
+                                           WALL wall, const MgFuse<AT> &mf = MgFuse<AT>{})
 {
-    constexpr int TYT = TileShape<AT>::TYT, CPT = TileShape<AT>::CPT;
+    constexpr int CPT = TileShape<AT>::CPT;   // a thread's cells: rows CPT ly + c of the tile
     constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
     static_assert(PRE || !CST, "stored face speeds come with stored sR");
     static_assert(!CALL || CST, "the nonlinear residual reads stored face speeds");
+    static_assert(!INJ || TileShape<AT>::CPT == 2, "the fused injection takes FP32 tiles");
     constexpr int NC = CST ? 3 : 0;
     constexpr int IX = Rec<CST>::IX, IF = Rec<CST>::IF, IS = Rec<CST>::IS, IC = Rec<CST>::IC, NL = Rec<CST>::NL;
 
@@ -169,15 +186,17 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     // in-plane offsets of the thread's (mapped) cells and of its LDS halo cell
     const int gx = x0 + lx;
     const int mx = map_axis(gx, g.nx, g.bclo[0], g.bchi[0]);
-    unsigned off[CPT];
+    unsigned off[CPT], poff[CPT];   // poff (injection): the parents' in-plane offsets
     bool active[CPT];
     for (int c = 0; c < CPT; ++c) {
-        const int gy = y0 + ly + TYT * c;
-        off[c] = (unsigned)mx + (unsigned)g.nx * (unsigned)map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
+        const int gy = y0 + CPT * ly + c;
+        const int my = map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
+        off[c] = (unsigned)mx + (unsigned)g.nx * (unsigned)my;
+        poff[c] = INJ ? (unsigned)(mx >> 1) + (unsigned)mf.ncx * (unsigned)(my >> 1) : 0u;
         active[c] = gx < g.nx && gy < g.ny;  // then off[c] is the cell's own offset
     }
     int hly = -1, hlx = -1;
-    unsigned hoff = 0;
+    unsigned hoff = 0, phoff = 0;
     int gxh = 0, gyh = 0;
     if (threadIdx.x < kHalo) {
         const int h = threadIdx.x;
@@ -185,15 +204,16 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         else if (h < 2 * kTX) { hlx = h - kTX + 1; hly = kLY - 1; gxh = x0 + h - kTX; gyh = y0 + kTY; }
         else if (h < 2 * kTX + kTY) { hlx = 0; hly = h - 2 * kTX + 1; gxh = x0 - 1; gyh = y0 + h - 2 * kTX; }
         else { hlx = kLX - 1; hly = h - 2 * kTX - kTY + 1; gxh = x0 + kTX; gyh = y0 + h - 2 * kTX - kTY; }
-        hoff = (unsigned)map_axis(gxh, g.nx, g.bclo[0], g.bchi[0]) +
-               (unsigned)g.nx * (unsigned)map_axis(gyh, g.ny, g.bclo[1], g.bchi[1]);
+        const int mxh = map_axis(gxh, g.nx, g.bclo[0], g.bchi[0]), myh = map_axis(gyh, g.ny, g.bclo[1], g.bchi[1]);
+        hoff = (unsigned)mxh + (unsigned)g.nx * (unsigned)myh;
+        if (INJ) phoff = (unsigned)(mxh >> 1) + (unsigned)mf.ncx * (unsigned)(myh >> 1);
     }
     // self-faces (mapped neighbour is the cell itself): excluded from the Jacobi diagonal
     const bool selfx_lo = map_axis(gx - 1, g.nx, g.bclo[0], g.bchi[0]) == mx;
     const bool selfx_hi = map_axis(gx + 1, g.nx, g.bclo[0], g.bchi[0]) == mx;
     bool selfy_lo[CPT], selfy_hi[CPT];
     for (int c = 0; c < CPT; ++c) {
-        const int gy = y0 + ly + TYT * c;
+        const int gy = y0 + CPT * ly + c;
         const int my = map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
         selfy_lo[c] = map_axis(gy - 1, g.ny, g.bclo[1], g.bchi[1]) == my;
         selfy_hi[c] = map_axis(gy + 1, g.ny, g.bclo[1], g.bchi[1]) == my;
@@ -226,11 +246,23 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     struct ZRow {
         AT x[4], f[3], s;
     };
-    auto load_full = [&](int kp, unsigned o, Full &u) __attribute__((always_inline)) {
+    // the operand's 4 values of the cell at plane kp, offset o (parent offset po)
+    auto load_x = [&](int kp, unsigned o, unsigned po, AT *v) __attribute__((always_inline)) {
         const long long pb = plane * kp;
-        u.v[IX] = s * ld_off(x + pb, o);
+        if constexpr (INJ) {
+            const long long pp = (long long)(kp >> 1) * mf.ncx * mf.ncy;
+            v[0] = s * (mf.a * ld_off(x + pb, o) + ld_off(mf.ec + pp, po));
 #pragma unroll
-        for (int q = 1; q < 4; ++q) u.v[IX + q] = sF * ld_off(x + q * N + pb, o);
+            for (int q = 1; q < 4; ++q) v[q] = sF * (mf.a * ld_off(x + q * N + pb, o) + ld_off(mf.ec + q * mf.Nc + pp, po));
+        } else {
+            v[0] = s * ld_off(x + pb, o);
+#pragma unroll
+            for (int q = 1; q < 4; ++q) v[q] = sF * ld_off(x + q * N + pb, o);
+        }
+    };
+    auto load_full = [&](int kp, unsigned o, unsigned po, Full &u) __attribute__((always_inline)) {
+        const long long pb = plane * kp;
+        load_x(kp, o, po, u.v + IX);
 #pragma unroll
         for (int t = 0; t < 6; ++t) u.v[IF + t] = (AT)ld_off(f + t * N + pb, o);
         if constexpr (PRE) {
@@ -256,11 +288,9 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     struct Halo {
         AT v[8];
     };
-    auto load_halo = [&](int kp, unsigned o, Halo &u) __attribute__((always_inline)) {
+    auto load_halo = [&](int kp, unsigned o, unsigned po, Halo &u) __attribute__((always_inline)) {
         const long long pb = plane * kp;
-        u.v[0] = s * ld_off(x + pb, o);
-#pragma unroll
-        for (int q = 1; q < 4; ++q) u.v[q] = sF * ld_off(x + q * N + pb, o);
+        load_x(kp, o, po, u.v);
 #pragma unroll
         for (int q = 0; q < 3; ++q) u.v[4 + q] = (AT)ld_off(f + tens_row(hax, q) * N + pb, o);
         if constexpr (CST)
@@ -328,7 +358,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         for (int c = 0; c < CPT; ++c) {
             // ragged-edge cells are computed from their mapped (in-range) values
             // and not stored, so the arithmetic has no divergent branch
-            const int sy = ly + TYT * c + 1, sxx = lx + 1;
+            const int sy = CPT * ly + c + 1, sxx = lx + 1;
             CellSums<AT> S;
             S.Ec = lds[a][IX][sy][sxx];
             for (int q = 0; q < 3; ++q) S.Fc[q] = lds[a][IX + 1 + q][sy][sxx];
@@ -437,13 +467,13 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     // wait counts stay a full set deep.  The epilogue's per-cell extras of plane
     // k are issued ahead of the prefetch, so waiting for them leaves it in flight.
     constexpr int DEPTH = TileShape<AT>::DEPTH;
-    const unsigned hsrc = hly >= 0 ? hoff : off[0];
+    const unsigned hsrc = hly >= 0 ? hoff : off[0], phsrc = hly >= 0 ? phoff : poff[0];
     using HT = std::conditional_t<SLIM, Halo, Full>;
-    auto load_h = [&](int kp, unsigned o, HT &u) __attribute__((always_inline)) {
+    auto load_h = [&](int kp, HT &u) __attribute__((always_inline)) {
         if constexpr (SLIM)
-            load_halo(kp, o, u);
+            load_halo(kp, hsrc, phsrc, u);
         else
-            load_full(kp, o, u);
+            load_full(kp, hsrc, phsrc, u);
     };
     auto put_h = [&](int sl, const HT &u) __attribute__((always_inline)) {
         if constexpr (SLIM)
@@ -456,30 +486,30 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     {
         Full t;
         for (int c = 0; c < CPT; ++c) {
-            load_full(mapz(z0 - 1), off[c], t);
+            load_full(mapz(z0 - 1), off[c], poff[c], t);
             prev[c].x[0] = t.v[IX];
             for (int q = 0; q < 3; ++q) prev[c].x[1 + q] = t.v[IX + 1 + q];
             for (int q = 0; q < 3; ++q) prev[c].f[q] = t.v[IF + tens_row(2, q)];
             prev[c].s = t.v[IS];
         }
         for (int c = 0; c < CPT; ++c) {
-            load_full(z0, off[c], t);
-            put(0, ly + TYT * c + 1, lx + 1, t);
+            load_full(z0, off[c], poff[c], t);
+            put(0, CPT * ly + c + 1, lx + 1, t);
         }
         if constexpr (SLIM) {
             Halo th;
-            load_halo(z0, hsrc, th);
+            load_halo(z0, hsrc, phsrc, th);
             if (hly >= 0) put_halo(0, th);
         } else {
-            load_full(z0, hsrc, t);
+            load_full(z0, hsrc, phsrc, t);
             if (hly >= 0) put(0, hly, hlx, t);
         }
     }
-    for (int c = 0; c < CPT; ++c) load_full(mapz(z0 + 1), off[c], S0[c]);
-    load_h(mapz(z0 + 1), hsrc, H0);
+    for (int c = 0; c < CPT; ++c) load_full(mapz(z0 + 1), off[c], poff[c], S0[c]);
+    load_h(mapz(z0 + 1), H0);
     if constexpr (DEPTH == 2) {
-        for (int c = 0; c < CPT; ++c) load_full(mapz(min(z0 + 2, z1)), off[c], S1[c]);
-        load_h(mapz(min(z0 + 2, z1)), hsrc, H1);
+        for (int c = 0; c < CPT; ++c) load_full(mapz(min(z0 + 2, z1)), off[c], poff[c], S1[c]);
+        load_h(mapz(min(z0 + 2, z1)), H1);
     }
 
     // one plane: LOAD issues plane k+1+DEPTH (needed when k+1+DEPTH <= z1)
@@ -487,14 +517,14 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         const int k = z0 + t;
         const int a = t & 1, b = a ^ 1;
         // plane k+1 (issued DEPTH planes ago) into the free slot
-        for (int c = 0; c < CPT; ++c) put(b, ly + TYT * c + 1, lx + 1, S[c]);
+        for (int c = 0; c < CPT; ++c) put(b, CPT * ly + c + 1, lx + 1, S[c]);
         if (hly >= 0) put_h(b, H);
         if constexpr (NE > 0)
             for (int c = 0; c < CPT; ++c) lex(k, plane * k, off[c], ex[c]);
         if constexpr (decltype(LOAD)::value) {
             const int kp = mapz(k + 1 + DEPTH);
-            for (int c = 0; c < CPT; ++c) load_full(kp, off[c], S[c]);
-            load_h(kp, hsrc, H);
+            for (int c = 0; c < CPT; ++c) load_full(kp, off[c], poff[c], S[c]);
+            load_h(kp, H);
         }
         lds_barrier();
         compute(k, a, b);
@@ -545,15 +575,20 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // is *xs times xm.  qv (PRE, pg = 0): y = s x + qm (qs qv - D^-1 A (s x)), a damped
 // Jacobi sweep on B e = qs qv.  dout (PRE): also write the Jacobi diagonal D (E
 // row, then the F rows' common value; two planes).  Used by the multigrid cycle.
-template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true, bool WL = false>
+// MGM (multigrid, FP32 tiles, even z-ranges): 1 fuses the restriction of the
+// output into mf (y is not written), 2 the injection of mf's coarse correction
+// into the operand (see MgFuse).
+template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true, bool WL = false,
+          int MGM = 0>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
                   AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{}, const AT *__restrict__ vb = nullptr,
                   const AT *__restrict__ vc = nullptr, AT pg = AT(0), AT xm = AT(1), const AT *__restrict__ qv = nullptr,
-                  AT qm = AT(0), AT qs = AT(1), AT *__restrict__ dout = nullptr)
+                  AT qm = AT(0), AT qs = AT(1), AT *__restrict__ dout = nullptr, MgFuse<AT> mf = MgFuse<AT>{})
 {
+    static_assert(MGM == 0 || (PRE && !AMR && !VEL && TileShape<AT>::CPT == 2), "multigrid fusion: FP32 Krylov apply");
     constexpr bool CS = PRE && LC;
     __shared__ AT lds[2][Rec<CS>::NL][TileShape<AT>::LY][kLX];
     const long long N = g.N;
@@ -580,7 +615,10 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             for (int q = 0; q < 3; ++q) e[4 + q] = ld_off(vc + q * N + pb, o);
         }
     };
-    auto epi = [&](int k, int, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[NEX])
+    // restriction: the children's D t summed per thread (its y-pair) over a z-pair, then over the
+    // x-pair of lanes; the parents' diagonal is loaded on the pair's first plane
+    AT racc[4] = {AT(0), AT(0), AT(0), AT(0)}, rDc[2] = {AT(1), AT(1)};
+    auto epi = [&](int k, int c, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[NEX])
                    __attribute__((always_inline)) {
         const long long pb = (long long)g.nx * g.ny * k;
         const AT dEc = e[0];
@@ -632,7 +670,32 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             yE = S.Ec + qm * (qs * ld_off(qv + pb, o) - yE);
             for (int q = 0; q < 3; ++q) yFq[q] = S.Fc[q] + qm * (qs * ld_off(qv + (1 + q) * N + pb, o) - yFq[q]);
         }
-        if (active) {
+        if constexpr (MGM == 1) {
+            // the diagonal of the restriction: E row, the F rows' mean (as dout holds it)
+            AT DEr = dEc + dtr, DFr = AT(1) + S.sc + dtr;
+            if constexpr (WL) {
+                DEr += nu * S.wE;
+                DFr += nu * (S.wF[0] + S.wF[1] + S.wF[2]) * AT(1.0 / 3.0);
+            }
+            racc[0] += DEr * yE;
+            for (int q = 0; q < 3; ++q) racc[1 + q] += DFr * yFq[q];
+            if (c == 1) {   // the thread's y-pair is in
+                const unsigned gxo = o % (unsigned)g.nx, gyo = o / (unsigned)g.nx;
+                const long long pc = (long long)(k >> 1) * mf.ncx * mf.ncy + (gxo >> 1) + (long long)mf.ncx * (gyo >> 1);
+                if (!(k & 1)) {   // first plane of the z-pair: the parents' diagonal
+                    rDc[0] = mf.Dc[pc];
+                    rDc[1] = mf.Dc[mf.Nc + pc];
+                } else {          // the z-pair is in: add the x-pair's, store, start over
+                    for (int q = 0; q < 4; ++q) racc[q] += __shfl_xor(racc[q], 1);
+                    if (active && !(gxo & 1)) {
+                        mf.qc[pc] = racc[0] * (AT(0.125) / rDc[0]);
+                        const AT iF = AT(0.125) / rDc[1];
+                        for (int q = 1; q < 4; ++q) mf.qc[q * mf.Nc + pc] = racc[q] * iF;
+                    }
+                    for (int q = 0; q < 4; ++q) racc[q] = AT(0);
+                }
+            }
+        } else if (active) {
             st_off(y + pb, o, yE);
             for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, o, yFq[q] * yF);
         }
@@ -643,7 +706,8 @@ __global__ void __launch_bounds__(tile_threads<AT>())
         const AT z3[3] = {AT(0), AT(0), AT(0)};
         wall_ghost<AT>(kind, d, side, Ec, Fc, fcr, AT(0), z3, AT(0), En, Fn, fnr);
     };
-    tile_sweep<AT, ST, PRE, false, NEX, CS, WL>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi, wall);
+    tile_sweep<AT, ST, PRE, false, NEX, CS, WL, MGM == 2>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi,
+                                                         wall, mf);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

@@ -1152,57 +1152,63 @@ int run_step(Solver &S)
                                (const double *)sR64, (const FT *)Cc, out);
         });
     };
+    // mgm, mf: the multigrid transfer fused into the sweep (1: restriction of y into mf, which is then
+    // not written; 2: injection of mf's coarse correction into the operand; FP32 only)
     auto apply = [&](const KT *x, const double *xs, KT *y, AT pg = AT(0), AT xm = AT(1), const AT *qv = nullptr,
-                     AT qm = AT(0), AT qs = AT(1), AT *dout = nullptr) {
+                     AT qm = AT(0), AT qs = AT(1), AT *dout = nullptr, int mgm = 0,
+                     const MgFuse<AT> &mf = MgFuse<AT>{}) {
         if (S.amr) jump(x, xs, (const AT *)Cf, corrA);
         const int tok = prof_begin(kApply, S.st);
         for (int l = 0; l < NL; ++l) {
             const long long o = S.c0[l];
-            // grids with open, Marshak or reflecting walls take the sweep with the wall code
-            auto go_w = [&](auto amr_c, auto vel_c, auto lc_c) {
-                constexpr bool VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
-                if constexpr (!decltype(amr_c)::value) {
+            auto go = [&](auto amr_c, auto vel_c, auto lc_c, auto wl_c, auto mg_c) {
+                constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
+                constexpr bool WLc = decltype(wl_c)::value;
+                constexpr int MG = decltype(mg_c)::value;
+                // not built: walls on the two-level grid, fused transfers outside the plain FP32 apply
+                if constexpr (!(AM && WLc) && (MG == 0 || (!AM && !VL && std::is_same<AT, float>::value))) {
                     if (fA)
-                        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, false, VL, LC, true>), tiles(tg[l]), bt, 0,
+                        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bt, 0,
                                            S.st, S.gl[l], tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
                                            (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
-                                           y + 4 * o, AT(1), AT(1), AmrLv{}, (const AT *)VBA, (const AT *)VCA, pg, xm,
-                                           qv, qm, qs, dout);
+                                           y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)),
+                                           (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf);
                     else
-                        hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, false, VL, LC, true>), tiles(tg[l]), bt, 0,
+                        hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bt, 0,
                                            S.st, S.gl[l], tg[l], f + 6 * o, sR + o, (const CT *)nullptr,
                                            (const CT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
-                                           y + 4 * o, AT(1), AT(1), AmrLv{}, (const AT *)VBA, (const AT *)VCA, pg, xm,
-                                           qv, qm, qs, dout);
+                                           y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)),
+                                           (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf);
                 }
             };
-            auto go = [&](auto amr_c, auto vel_c, auto lc_c) {
-                constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
-                if (walls) return go_w(std::bool_constant<AM>{}, std::bool_constant<VL>{}, std::bool_constant<LC>{});
-                if (fA)
-                    hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
-                                       tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
-                                       (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
-                                       y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)), (const AT *)VBA,
-                                       (const AT *)VCA, pg, xm, qv, qm, qs, dout);
-                else
-                    hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC>), tiles(tg[l]), bt, 0, S.st, S.gl[l],
-                                       tg[l], f + 6 * o, sR + o, (const CT *)nullptr, (const CT *)nullptr,
-                                       (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs, y + 4 * o, AT(1), AT(1),
-                                       level_view(l, corrA, sizeof(AT)), (const AT *)VBA, (const AT *)VCA, pg, xm,
-                                       qv, qm, qs, dout);
+            // grids with open, Marshak or reflecting walls take the sweep with the wall code
+            auto go2 = [&](auto amr_c, auto vel_c, auto lc_c) {
+                using I0 = std::integral_constant<int, 0>;
+                using I1 = std::integral_constant<int, 1>;
+                using I2 = std::integral_constant<int, 2>;
+                if (walls) {
+                    if (mgm == 1) go(amr_c, vel_c, lc_c, std::true_type{}, I1{});
+                    else if (mgm == 2) go(amr_c, vel_c, lc_c, std::true_type{}, I2{});
+                    else go(amr_c, vel_c, lc_c, std::true_type{}, I0{});
+                } else {
+                    if (mgm == 1) go(amr_c, vel_c, lc_c, std::false_type{}, I1{});
+                    else if (mgm == 2) go(amr_c, vel_c, lc_c, std::false_type{}, I2{});
+                    else go(amr_c, vel_c, lc_c, std::false_type{}, I0{});
+                }
             };
             if (S.amr)
-                go(std::true_type{}, std::false_type{}, std::true_type{});
+                go2(std::true_type{}, std::false_type{}, std::true_type{});
             else if (vel)
-                go(std::false_type{}, std::true_type{}, std::true_type{});
+                go2(std::false_type{}, std::true_type{}, std::true_type{});
             else if (S.loadc)
-                go(std::false_type{}, std::false_type{}, std::true_type{});
+                go2(std::false_type{}, std::false_type{}, std::true_type{});
             else
-                go(std::false_type{}, std::false_type{}, std::false_type{});
+                go2(std::false_type{}, std::false_type{}, std::false_type{});
         }
-        // the smoothing form also reads q (4 planes), the diagonal form writes D (2 planes)
-        prof_end(tok, S.st, Nd * (8 * kb + 6 * fb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
+        // the smoothing form also reads q (4 planes), the diagonal form writes D (2 planes); the fused
+        // restriction writes an eighth of y, the fused injection reads an eighth more operand
+        const double ybytes = mgm == 1 ? 0.5 * kb : 4 * kb, xbytes = mgm == 2 ? 4.5 * kb : 4 * kb;
+        prof_end(tok, S.st, Nd * (xbytes + ybytes + 6 * fb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
     };
     // ---- multigrid cycle (krylov_poly = 2): levels l >= 1 halve the grid; each carries the
     // children's mean sR, tensor and E diagonal, its own corrected face speeds and Jacobi
@@ -1269,19 +1275,51 @@ int run_step(Solver &S)
     }
     // the operator of level l >= 1 (same sweep as the grid's apply, coarse coefficients)
     // (profiled as the multigrid class, so the grid's apply keeps its own class)
-    auto mg_apply = [&](int l, const AT *x, AT xm, AT *y, AT pg, const AT *qv, AT qm, AT *dout) {
+    auto mg_apply = [&](int l, const AT *x, AT xm, AT *y, AT pg, const AT *qv, AT qm, AT *dout, int mgm = 0,
+                        const MgFuse<AT> &mf = MgFuse<AT>{}) {
         const int tok = prof_begin(K_MG, S.st);
-        auto kern = walls ? k_apply_tiled<AT, AT, true, false, false, true, true>
-                          : k_apply_tiled<AT, AT, true, false, false, true, false>;
+        auto pick = [&](auto wl_c, auto mg_c) {
+            constexpr bool WLc = decltype(wl_c)::value;
+            constexpr int MG = decltype(mg_c)::value;
+            if constexpr (MG == 0 || std::is_same<AT, float>::value)
+                return &k_apply_tiled<AT, AT, true, false, false, true, WLc, MG>;
+            else
+                return &k_apply_tiled<AT, AT, true, false, false, true, WLc, 0>;
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        auto kern = walls ? (mgm == 1 ? pick(std::true_type{}, I1{}) : mgm == 2 ? pick(std::true_type{}, I2{})
+                                                                               : pick(std::true_type{}, I0{}))
+                          : (mgm == 1 ? pick(std::false_type{}, I1{}) : mgm == 2 ? pick(std::false_type{}, I2{})
+                                                                                : pick(std::false_type{}, I0{}));
         hipLaunchKernelGGL(kern, tiles(ml[l].tg), bt, 0, S.st, S.mg[l], ml[l].tg, (const AT *)ml[l].f,
                            (const AT *)ml[l].sR, (const AT *)nullptr, (const AT *)nullptr, (const AT *)ml[l].Cf,
                            (const AT *)ml[l].dE, x, (const double *)nullptr, y, AT(1), AT(1), AmrLv{},
-                           (const AT *)nullptr, (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout);
-        prof_end(tok, S.st, (double)S.mg[l].N * (8 * kb + 6 * kb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
+                           (const AT *)nullptr, (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout, mf);
+        const double ybytes = mgm == 1 ? 0.5 * kb : 4 * kb, xbytes = mgm == 2 ? 4.5 * kb : 4 * kb;
+        prof_end(tok, S.st,
+                 (double)S.mg[l].N * (xbytes + ybytes + 6 * kb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
+    };
+    // the transfers between levels l and l+1 fused into level l's sweeps: FP32 tiles over even z-ranges
+    auto fusable = [&](int l) {
+        return std::is_same<AT, float>::value && (l == 0 ? tg[0].kz : ml[l].tg.kz) % 2 == 0;
+    };
+    auto fuse_to = [&](int l) {   // the coarse level l + 1 as the fused transfers see it
+        MgFuse<AT> m;
+        const Grid &gc = S.mg[l + 1];
+        m.qc = ml[l + 1].q;
+        m.Dc = ml[l + 1].D;
+        m.ec = ml[l + 1].e;
+        m.Nc = gc.N;
+        m.ncx = gc.nx;
+        m.ncy = gc.ny;
+        return m;
     };
     // this Picard iteration's Jacobi diagonals of every level (dE changes with T*)
     auto mg_diagonals = [&]() {
-        apply(V, nullptr, mgE0, AT(0), AT(1), nullptr, AT(0), AT(1), ml[0].D);
+        // (the grid's own diagonal only serves the unfused restriction)
+        if (!fusable(0)) apply(V, nullptr, mgE0, AT(0), AT(1), nullptr, AT(0), AT(1), ml[0].D);
         for (int l = 1; l < mgL; ++l) {
             const Grid &gf = S.mg[l - 1], &gc = S.mg[l];
             hipLaunchKernelGGL((k_mg_average<AT, AT>), mg_cells(gc), bl, 0, S.st, gf, gc, 1,
@@ -1303,10 +1341,12 @@ int run_step(Solver &S)
             hipLaunchKernelGGL((k_mg_inject<AT>), mg_cells(gf), bl, 0, S.st, gf, gc, q, qs, ec, e);
         });
     };
-    // V-cycle on level l >= 1 for B_l e = q_l; returns the buffer holding e
+    // V-cycle on level l >= 1 for B_l e = q_l; returns the buffer holding e.  The coarse correction
+    // is always left in ml[l].e (the fused injection reads it there).
     std::function<AT *(int)> mg_cycle = [&](int l) -> AT * {
         if (l == mgL - 1) {   // coarsest: kCoarse sweeps after e = om q
-            AT *cur = ml[l].e, *nxt = ml[l].t;
+            AT *cur = ml[l].t, *nxt = ml[l].e;
+            if (kCoarse % 2) std::swap(cur, nxt);
             mg_apply(l, ml[l].q, AT(kOm), cur, AT(0), ml[l].q, AT(kOm), nullptr);
             for (int k = 1; k < kCoarse; ++k) {
                 mg_apply(l, cur, AT(1), nxt, AT(0), ml[l].q, AT(kOm), nullptr);
@@ -1314,16 +1354,37 @@ int run_step(Solver &S)
             }
             return cur;
         }
+        AT *out = ml[l].e;
+        if (fusable(l)) {
+            const MgFuse<AT> mf = fuse_to(l);
+            // t = q - B (om q), restricted into q_{l+1} as it is formed
+            mg_apply(l, ml[l].q, AT(kOm), ml[l].t, AT(1.0 / kOm), nullptr, AT(0), nullptr, 1, mf);
+            mg_cycle(l + 1);
+            // the sweep on e = om q + P e_{l+1}, injected as it is loaded
+            MgFuse<AT> mi = mf;
+            mi.a = AT(kOm);
+            mg_apply(l, ml[l].q, AT(1), out, AT(0), ml[l].q, AT(kOm), nullptr, 2, mi);
+            return out;
+        }
         // t = q - B (om q): the residual after the first sweep from zero
         mg_apply(l, ml[l].q, AT(kOm), ml[l].t, AT(1.0 / kOm), nullptr, AT(0), nullptr);
         mg_restrict(l, ml[l].t, ml[l].D);
         AT *ec = mg_cycle(l + 1);
-        mg_inject(l, ml[l].q, AT(kOm), ec, ml[l].e);
-        mg_apply(l, ml[l].e, AT(1), ml[l].t, AT(0), ml[l].q, AT(kOm), nullptr);
-        return ml[l].t;
+        mg_inject(l, ml[l].q, AT(kOm), ec, ml[l].t);
+        mg_apply(l, ml[l].t, AT(1), out, AT(0), ml[l].q, AT(kOm), nullptr);
+        return out;
     };
     // out = M^-1 (sx x) on the grid; xs: the device copy of the scale sx (or null for 1)
     auto mg_precond = [&](const KT *x, const double *xs, double sx, KT *out) {
+        if (fusable(0)) {
+            const MgFuse<AT> mf = fuse_to(0);
+            apply(x, xs, W, AT(1.0 / kOm), AT(kOm), nullptr, AT(0), AT(1), nullptr, 1, mf);   // q_1 from q - B (om q)
+            mg_cycle(1);
+            MgFuse<AT> mi = mf;
+            mi.a = AT(kOm * sx);   // the sweep on e = om sx x + P e_1
+            apply(x, nullptr, out, AT(0), AT(1), (const AT *)x, AT(kOm), AT(sx), nullptr, 2, mi);
+            return;
+        }
         apply(x, xs, W, AT(1.0 / kOm), AT(kOm));   // W = q - B (om q), q = sx x
         mg_restrict(0, W, ml[0].D);
         AT *ec = mg_cycle(1);
@@ -1720,7 +1781,7 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
                        dim3(tile_threads<AT>()), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
                        (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
                        (AT)(1.0 / c), (AT)c, AmrLv{}, (const AT *)nullptr, (const AT *)nullptr, AT(0), AT(1),
-                       (const AT *)nullptr, AT(0), AT(1), (AT *)nullptr);
+                       (const AT *)nullptr, AT(0), AT(1), (AT *)nullptr, MgFuse<AT>{});
 }
 
 }  // namespace
