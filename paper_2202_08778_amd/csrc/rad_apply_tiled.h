@@ -192,7 +192,11 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         const int gy = y0 + CPT * ly + c;
         const int my = map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
         off[c] = (unsigned)mx + (unsigned)g.nx * (unsigned)my;
-        poff[c] = INJ ? (unsigned)(mx >> 1) + (unsigned)mf.ncx * (unsigned)(my >> 1) : 0u;
+        // (the thread's two cells, rows 2j and 2j+1, share their parents: one load serves both;
+        // a ragged row past the grid is not stored)
+        poff[c] = INJ ? (unsigned)(mx >> 1) + (unsigned)mf.ncx * (unsigned)(map_axis(y0 + CPT * ly, g.ny, g.bclo[1],
+                                                                                      g.bchi[1]) >> 1)
+                      : 0u;
         active[c] = gx < g.nx && gy < g.ny;  // then off[c] is the cell's own offset
     }
     int hly = -1, hlx = -1;

@@ -884,9 +884,11 @@ long long tile_bound(int nx, int ny, int nz)
 }
 
 // Multigrid levels below an nx x ny x nz grid: halve while every extent is even and
-// the halves stay >= 4 cells, at most 6 levels in all.  Returns the level count
-// (1: no coarse level) and the cells of the coarse levels.
-constexpr int kMaxMg = 6;
+// the halves stay >= 4 cells, at most 5 levels in all (at 256^3 the coarsest is 16^3:
+// a sixth level of 8^3 kept the iteration count and added two latency-bound sweeps to
+// every cycle; four levels took more iterations).  Returns the level count (1: no
+// coarse level) and the cells of the coarse levels.
+constexpr int kMaxMg = 5;
 int mg_levels(int nx, int ny, int nz, long long &coarse_cells)
 {
     int L = 1;
@@ -1215,7 +1217,7 @@ int run_step(Solver &S)
     // diagonal, and a right-hand side q, residual t and correction e.  One V-cycle with one
     // damped Jacobi sweep (weight kOm) before and after the coarse correction, and kCoarse + 1
     // sweeps from zero on the coarsest level (the first is e = om q; more did not pay at 256^3,
-    // whose coarsest level is 8^3), is the (fixed, linear) right preconditioner M^-1 of B.
+    // whose coarsest level is 16^3), is the (fixed, linear) right preconditioner M^-1 of B.
     // The weight is small because the scaled operator has eigenvalues far off the real axis
     // in optically thin media, which larger weights amplify.
     constexpr double kOm = 0.4;
