@@ -1,0 +1,153 @@
+"""Text summaries of rocprofv3 runs of bench.py, for the committed profile records.
+
+  trace:  per-kernel dispatch counts and durations from a --kernel-trace CSV;
+  hbm:    per-kernel HBM bytes per dispatch from a FETCH_SIZE pass and a WRITE_SIZE pass
+          (counter_collection CSVs), each scaled by what the same counter reads for the run's plain
+          device copies of 256 MiB (bench.py --copy-calibration), grouped into the library's kernel
+          classes; also a JSON record that bench.py reads for its roofline's traffic, tied to the
+          kernel sources by their hash.
+
+Kernels are told apart by name and grid size; an apply sweep whose grid is smaller than the largest
+one is a multigrid coarse level.
+
+  python -m paper_2202_08778_amd.prof_summary trace TRACE_CSV OUT_MD --cmd CMD --title TITLE
+  python -m paper_2202_08778_amd.prof_summary hbm FETCH_CSV WRITE_CSV OUT_MD OUT_JSON --n N --cmds CMD...
+"""
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# the sources bench.py hashes to decide whether a traffic record still describes the kernels
+HASHED = ("rad_single.hip", "rad_device.h", "rad_apply_tiled.h", "rad_amr.h")
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def short_name(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("vr::", "")
+    return re.split(r"\((?!anonymous)", name)[0].strip()
+
+
+def grid_of(r):
+    for k in ("Grid_Size", "Grid_Size_X", "Grid_X"):
+        if r.get(k):
+            return int(r[k])
+    return 0
+
+
+def kernel_class(name, grid, fine_grid):
+    if name.startswith("k_apply_tiled"):
+        return "apply_fp32" if grid >= fine_grid else "multigrid_levels"
+    for prefix, cls in (("k_mg_average", "setup"), ("k_mg_face", "setup"), ("k_mg_", "multigrid_levels"),
+                        ("k_residual", "residual_fp64"), ("k_multidot", "multidot_fp32"),
+                        ("k_orth_update", "orth_update_fp32"), ("k_update_x", "update_x_fp32"),
+                        ("k_combine", "update_x_fp32"), ("k_exchange", "exchange_fp64"), ("k_commit", "commit"),
+                        ("k_setup", "setup"), ("k_face_coef", "setup"), ("k_closure", "closure")):
+        if name.startswith(prefix):
+            return cls
+    return None
+
+
+def trace(args):
+    agg = collections.defaultdict(lambda: [0, 0.0, float("inf"), 0.0])
+    for r in csv.DictReader(open(args.csv)):
+        key = (short_name(r["Kernel_Name"]), grid_of(r))
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = agg[key]
+        a[0] += 1
+        a[1] += dt
+        a[2] = min(a[2], dt)
+        a[3] = max(a[3], dt)
+    tot = sum(a[1] for a in agg.values())
+    lines = [f"# {args.title}", "", "Command (repository root):", "", f"    {args.cmd}", "",
+             f"Kernel time in the run: {tot / 1e3:.1f} ms over {sum(a[0] for a in agg.values())} dispatches.", "",
+             "| kernel | grid (threads) | dispatches | total ms | share | mean us | min us | max us |",
+             "|---|---|---|---|---|---|---|---|"]
+    for (k, g), (n, t, lo, hi) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:args.top]:
+        lines.append(f"| {k} | {g} | {n} | {t / 1e3:.2f} | {100 * t / tot:.1f}% | {t / n:.1f} | {lo:.1f} | {hi:.1f} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def counters(path, counter):
+    per = collections.defaultdict(lambda: [0, 0.0])
+    copies = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        name, g, v = short_name(r["Kernel_Name"]), grid_of(r), float(r["Counter_Value"])
+        if "copyBuffer" in name or "copy_kernel" in name or "elementwise_kernel" in name:
+            copies.append(v)
+        per[(name, g)][0] += 1
+        per[(name, g)][1] += v
+    return per, copies
+
+
+def hbm(args):
+    fetch, fcopy = counters(args.fetch, "FETCH_SIZE")
+    write, wcopy = counters(args.write, "WRITE_SIZE")
+    # the calibration copies are the largest copy dispatches of the run (KiB per dispatch)
+    fc, wc = max(fcopy), max(wcopy)
+    rs, ws = COPY_BYTES / (fc * 1024), COPY_BYTES / (wc * 1024)
+    fine = max(g for (k, g) in fetch if k.startswith("k_apply_tiled"))
+    rows, cls = [], collections.defaultdict(lambda: [0, 0.0, 0.0])
+    kernels = {}
+    for key in sorted(fetch, key=lambda k: -fetch[k][1]):
+        k, g = key
+        c = kernel_class(k, g, fine)
+        if c is None:
+            continue
+        n, fkib = fetch[key]
+        wn, wkib = write.get(key, (n, 0.0))
+        rb, wb = rs * 1024 * fkib / n, ws * 1024 * wkib / max(wn, 1)
+        rows.append(f"| {k} | {g} | {c} | {n} | {fkib / n:.0f} | {wkib / max(wn, 1):.0f} | {rb / 1e6:.1f} | {wb / 1e6:.1f} |")
+        kernels[f"{k} [grid {g}]"] = {"read_bytes": rb, "write_bytes": wb, "dispatches": n, "class": c}
+        cl = cls[c]
+        cl[0] += n
+        cl[1] += rb * n
+        cl[2] += wb * n
+    classes = {c: {"read_bytes": v[1] / v[0], "write_bytes": v[2] / v[0], "dispatches": v[0]} for c, v in cls.items()}
+    lines = [f"# {args.title}: HBM bytes per dispatch", "", "Commands (two passes, repository root):", ""]
+    lines += [f"    {c}" for c in args.cmds]
+    lines += ["", f"Calibration: a plain device copy of 256 MiB reads {fc:.0f} KiB FETCH_SIZE and {wc:.0f} KiB "
+                  f"WRITE_SIZE per dispatch: read scale {rs:.3f}, write scale {ws:.3f}.  Scaled values are bytes "
+                  "per dispatch.", "",
+              "| kernel | grid (threads) | class | dispatches | FETCH KiB/disp (raw) | WRITE KiB/disp (raw) | "
+              "scaled read MB | scaled write MB |", "|---|---|---|---|---|---|---|---|"] + rows
+    lines += ["", "Per kernel class (dispatch-weighted), scaled bytes per dispatch:", "",
+              "| class | dispatches | read MB | write MB |", "|---|---|---|---|"]
+    for c, v in sorted(classes.items()):
+        lines.append(f"| {c} | {v['dispatches']} | {v['read_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} |")
+    open(args.out_md, "w").write("\n".join(lines) + "\n")
+    src = b"".join(open(os.path.join(HERE, "csrc", f), "rb").read() for f in HASHED)
+    rec = {"source_sha256": hashlib.sha256(src).hexdigest(), "workload": args.title, "n": args.n,
+           "commands": args.cmds, "read_scale": rs, "write_scale": ws, "kernels": kernels, "classes": classes}
+    json.dump(rec, open(args.out_json, "w"), indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("csv")
+    t.add_argument("out")
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--title", required=True)
+    t.add_argument("--top", type=int, default=30)
+    h = sub.add_parser("hbm")
+    h.add_argument("fetch")
+    h.add_argument("write")
+    h.add_argument("out_md")
+    h.add_argument("out_json")
+    h.add_argument("--n", type=int, required=True)
+    h.add_argument("--title", required=True)
+    h.add_argument("--cmds", nargs="+", required=True)
+    args = ap.parse_args()
+    trace(args) if args.mode == "trace" else hbm(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,6 +2,8 @@
 checked block by block against the FP64 oracle (<= 1e-10 FP64, <= 1e-8 mixed), at full batch
 size on sampled blocks and through the oracle's residual, across graph replays and after
 autotuning."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -65,11 +67,13 @@ def _relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1, poly=1):
+def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1, poly=1, m=None):
     descs, ar = rad.pack_blocks(batch["blocks"])
     c32 = prec == "mixed"
     p = rad.params(c=batch["c"], a_R=batch["aR"], c_v=batch["cv"], prec=prec, tol=tol,
                    coef_dtype=1 if c32 else 0, krylov_poly=poly)
+    if m is not None:
+        p.gmres_m = m
     dev = _upload(torch, ar, c32)
     plan = rad.Plan(descs, p)
     if autotune:
@@ -163,33 +167,27 @@ def test_reorder_by_measured_times_keeps_results(torch, rad):
 
 
 def test_full_batch_1024_blocks(torch, rad):
-    """1024 blocks with edges 8..32, dt 1..1000 crossings, kappa 1e-2..1e3, mixed precision: every
-    block converges; sampled blocks match the oracle (small ones exactly to 1e-8, the largest
-    through the oracle's residual)."""
+    """1024 blocks with edges 8..32, dt 1..1000 crossings, kappa 1e-2..1e3, mixed precision, GMRES(48):
+    every block converges except those on which the FP64 oracle fails too (the linearised Picard
+    iteration cycles there, with cells of E < 0 held at the T >= 0 bound; recorded by
+    tests/golden/make_batched_flagged.py, which ran the oracle with GMRES(64), tight inner solves and 50
+    Picard iterations on every block GMRES(12) leaves unconverged); sampled blocks match the oracle
+    (small ones exactly to 1e-8, the largest through the oracle's residual)."""
     _say("batched full 1024")
     batch = W.batched_blocks(nblocks=1024, seed=4)
-    descs, outs, stats = _run(torch, rad, batch, "mixed", tol=1e-10)
+    descs, outs, stats = _run(torch, rad, batch, "mixed", tol=1e-10, m=48)
     st = stats[0]
     _say("  status counts", np.unique(st["status"], return_counts=True))
     _say("  krylov per block: mean %.1f max %d" % (st["krylov_iters"].mean(), st["krylov_iters"].max()))
-    # A few blocks at hundreds of crossing times per step have cells with E < 0 where the T >= 0
-    # bound is active; the Picard iteration (either form) cycles there and the oracle fails on
-    # them too.  They must be flagged, and be rare.
+    flagged = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batched_1024_flagged.json")))
+    hopeless = {r["block"] for r in flagged["blocks"] if not r["converged"]}
+    solvable = {r["block"] for r in flagged["blocks"] if r["converged"]}
+    assert hopeless and solvable, flagged
     assert np.all((st["status"] == 0) | (st["status"] == 1))
-    assert np.mean(st["status"] == 0) >= 0.99
-    bad = [b for b in np.nonzero(st["status"] == 1)[0]]
-    if bad:
-        b = min(bad, key=lambda b: batch["blocks"][b]["n"])
-        blk = batch["blocks"][b]
-        ng = blk["ng"]
-        s = (slice(ng - 1, -(ng - 1) or None),) * 3
-        cut = lambda a: np.ascontiguousarray(a[(Ellipsis,) + s])
-        P = oracle.Problem(cut(blk["rho"]), cut(blk["kP"]), cut(blk["kR"]), cut(blk["f"]), blk["dt"], blk["dx"],
-                           "dirichlet", c=batch["c"], aR=batch["aR"], cv=batch["cv"], padded=True)
-        _, _, _, ost = P.step(cut(blk["E"]), cut(blk["F"]), cut(blk["T"]), tol=1e-10, mode="lagged",
-                              max_picard=200, allow_unconverged=True)
-        _say(f"  non-converged block {b} (n={blk['n']}): oracle {ost}")
-        assert ost["converged"] == 0
+    bad = {int(b) for b in np.nonzero(st["status"] == 1)[0]}
+    _say(f"  unconverged {sorted(bad)}; the oracle's own failures {sorted(hopeless)}, solved {sorted(solvable)}")
+    assert bad <= hopeless, bad - hopeless
+    assert not (bad & solvable)
     rng = np.random.default_rng(0)
     small = [b for b, blk in enumerate(batch["blocks"]) if blk["n"] == 8]
     for b in rng.choice(small, 3, replace=False):
@@ -199,7 +197,8 @@ def test_full_batch_1024_blocks(torch, rad):
         _say(f"  block {b} errs", ["%.1e" % e for e in errs])
         assert max(errs) <= 1e-8
     big = [b for b, blk in enumerate(batch["blocks"]) if blk["n"] == 32]
-    for b in rng.choice(big, 2, replace=False):
+    # two sampled 32^3 blocks and the stiff blocks that only converge with the longer restart
+    for b in list(rng.choice(big, 2, replace=False)) + sorted(solvable):
         blk = batch["blocks"][b]
         ng = blk["ng"]
         s = (slice(ng - 1, -(ng - 1) or None),) * 3
@@ -212,5 +211,5 @@ def test_full_batch_1024_blocks(torch, rad):
         Ep[inner], Tp[inner] = E, T
         Fp[(slice(None),) + inner] = F
         r = P.scaled_residual(cut(blk["E"]), cut(blk["F"]), cut(blk["T"]), Ep, Fp, Tp)
-        _say(f"  block {b} (32^3) oracle residual {r[3]:.2e}")
+        _say(f"  block {b} ({blk['n']}^3) oracle residual {r[3]:.2e}")
         assert r[3] <= 1.5e-10
