@@ -73,24 +73,26 @@ def trace(args):
 
 
 def counters(path, counter):
+    """Per (kernel, grid): dispatches and summed counter; and the counter of the calibration copies,
+    the run's last four device-copy dispatches (bench.py makes them after everything else)."""
     per = collections.defaultdict(lambda: [0, 0.0])
     copies = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         name, g, v = short_name(r["Kernel_Name"]), grid_of(r), float(r["Counter_Value"])
-        if "copyBuffer" in name or "copy_kernel" in name or "elementwise_kernel" in name:
-            copies.append(v)
+        if "copyBuffer" in name:
+            copies.append((int(r["Dispatch_Id"]), v))
         per[(name, g)][0] += 1
         per[(name, g)][1] += v
-    return per, copies
+    last = [v for _, v in sorted(copies)[-4:]]
+    return per, sum(last) / len(last)
 
 
 def hbm(args):
     fetch, fcopy = counters(args.fetch, "FETCH_SIZE")
     write, wcopy = counters(args.write, "WRITE_SIZE")
-    # the calibration copies are the largest copy dispatches of the run (KiB per dispatch)
-    fc, wc = max(fcopy), max(wcopy)
+    fc, wc = fcopy, wcopy   # KiB per calibration copy
     rs, ws = COPY_BYTES / (fc * 1024), COPY_BYTES / (wc * 1024)
     fine = max(g for (k, g) in fetch if k.startswith("k_apply_tiled"))
     rows, cls = [], collections.defaultdict(lambda: [0, 0.0, 0.0])
