@@ -157,7 +157,8 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
                                            const AT *__restrict__ x, AT s, AT sF,
                                            AT (&lds)[2][Rec<CST>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi,
-                                           WALL wall, const MgFuse<AT> &mf = MgFuse<AT>{})
+                                           WALL wall, const MgFuse<AT> &mf = MgFuse<AT>{},
+                                           const AT *__restrict__ cw = nullptr)
 {
     constexpr int CPT = TileShape<AT>::CPT;   // a thread's cells: rows CPT ly + c of the tile
     constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
@@ -241,6 +242,20 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                  (x0 + kTX >= g.nx && kind_of(0, 1) >= BC_OPEN ? 2u : 0u) |
                                  (y0 == 0 && kind_of(1, 0) >= BC_OPEN ? 4u : 0u) |
                                  (y0 + kTY >= g.ny && kind_of(1, 1) >= BC_OPEN ? 8u : 0u);
+    // A high wall's speed is the cell's own, which the stored low-face speeds do not hold.  FP32 Krylov
+    // sweeps of tiles on a high x wall (a quarter of the tiles at 256^3) read it from cw (per step: x walls
+    // [nz][ny], then y walls [nz][nx], then z walls [ny][nx]), staged into LDS for the tile's z-range (1 KB,
+    // so that two workgroups still share a CU); the rarer high y and z walls, and z-ranges over kWz planes,
+    // form it.
+    constexpr int kWz = 32;
+    constexpr bool WST = WL && CST && !CALL && sizeof(AT) == 4;
+    __shared__ std::conditional_t<WST, AT[kWz * kTY], AT[1]> wsp;
+    const bool wlds = WST && cw != nullptr && tg.kz <= kWz && (twall & 2u);
+    if constexpr (WST) {
+        if (wlds)
+            for (int t = threadIdx.x; t < (z1 - z0) * kTY; t += blockDim.x)
+                wsp[t] = cw[(long long)(z0 + t / kTY) * g.ny + min(y0 + t % kTY, g.ny - 1)];
+    }
 
     // one cell's record in registers (in flight from HBM)
     struct Full {
@@ -407,7 +422,17 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                     // its speed: a low face's stored speed is the cell's own, a high face's is formed
                     if (WL && (twall & (1u << (2 * d + side))) && !(d == 1 && side == 0 && c > 0)) {
                         const AT m = AT((wmask[c] >> (2 * d + side)) & 1u);
-                        const AT Cw = (CST && side) ? self_face_speed<AT>(fcr[d], S.sc, tk) : Cface;
+                        AT Cw = Cface;
+                        if (CST && side) {
+                            if constexpr (WST) {
+                                if (d == 0 && wlds)
+                                    Cw = wsp[(k - z0) * kTY + CPT * ly + c];
+                                else
+                                    Cw = self_face_speed<AT>(fcr[d], S.sc, tk);
+                            } else {
+                                Cw = self_face_speed<AT>(fcr[d], S.sc, tk);
+                            }
+                        }
                         wall_fix(kind_of(d, side), d, side, m, Cw, fcr, ex[c], S);
                     }
                 }
@@ -449,9 +474,11 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                         S.sumC_all += Cface;
                 }
                 face_flux_acc<AT>(2, 1, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
-                if (WL && selfz_hi && zwall_hi)   // uniform: the grid's top plane
-                    wall_fix(kind_of(2, 1), 2, 1, AT(1),
-                             CST ? self_face_speed<AT>(fcr[2], S.sc, tk) : Cface, fcr, ex[c], S);
+                if (WL && selfz_hi && zwall_hi) {   // uniform: the grid's top plane
+                    AT Cw = Cface;
+                    if constexpr (CST) Cw = self_face_speed<AT>(fcr[2], S.sc, tk);
+                    wall_fix(kind_of(2, 1), 2, 1, AT(1), Cw, fcr, ex[c], S);
+                }
             }
             epi(k, c, off[c], active[c], S, ex[c]);
             // this plane becomes the lower neighbour of the next one
@@ -590,7 +617,8 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
                   AT *__restrict__ y, AT xF, AT yF, AmrLv al = AmrLv{}, const AT *__restrict__ vb = nullptr,
                   const AT *__restrict__ vc = nullptr, AT pg = AT(0), AT xm = AT(1), const AT *__restrict__ qv = nullptr,
-                  AT qm = AT(0), AT qs = AT(1), AT *__restrict__ dout = nullptr, MgFuse<AT> mf = MgFuse<AT>{})
+                  AT qm = AT(0), AT qs = AT(1), AT *__restrict__ dout = nullptr, MgFuse<AT> mf = MgFuse<AT>{},
+                  const AT *__restrict__ cw = nullptr)
 {
     static_assert(MGM == 0 || (PRE && !AMR && !VEL && TileShape<AT>::CPT == 2), "multigrid fusion: FP32 Krylov apply");
     constexpr bool CS = PRE && LC;
@@ -711,7 +739,7 @@ __global__ void __launch_bounds__(tile_threads<AT>())
         wall_ghost<AT>(kind, d, side, Ec, Fc, fcr, AT(0), z3, AT(0), En, Fn, fnr);
     };
     tile_sweep<AT, ST, PRE, false, NEX, CS, WL, MGM == 2>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi,
-                                                         wall, mf);
+                                                         wall, mf, cw);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in
@@ -731,6 +759,33 @@ __global__ void __launch_bounds__(256) k_face_coef(Grid g, const CT *__restrict_
         const double sRn = g.cdt * (double)rho[nb] * (double)kR[nb];
         Cf[d * N + c] = (AT)face_speed<double>((double)f[d * N + nb], (double)f[d * N + c], sRn, sRc, g.tau_k);
     }
+}
+
+// The own corrected speed (divided by c) of every cell on a high open, Marshak or reflecting
+// wall, once per step, in FP64 from the stored coefficients, rounded to the apply precision:
+// x walls [nz][ny], then y walls [nz][nx], then z walls [ny][nx] (other faces' entries unused).
+// SR: sR is given (coarse levels), else formed from rho and kR.
+template <class CT, class AT, bool SR = false>
+__global__ void __launch_bounds__(256) k_wall_speed(Grid g, const CT *__restrict__ rho, const CT *__restrict__ kR,
+                                                    const AT *__restrict__ sR, const CT *__restrict__ f,
+                                                    AT *__restrict__ cw)
+{
+    const long long ax = (long long)g.ny * g.nz, ay = (long long)g.nx * g.nz, az = (long long)g.nx * g.ny;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ax + ay + az) return;
+    int d, i, j, k;
+    if (t < ax) {
+        d = 0, i = g.nx - 1, j = (int)(t % g.ny), k = (int)(t / g.ny);
+    } else if (t < ax + ay) {
+        d = 1, i = (int)((t - ax) % g.nx), j = g.ny - 1, k = (int)((t - ax) / g.nx);
+    } else {
+        d = 2, i = (int)((t - ax - ay) % g.nx), j = (int)((t - ax - ay) / g.nx), k = g.nz - 1;
+    }
+    if (wall_kind(g, d, 1) < BC_OPEN) return;
+    const long long c = i + (long long)g.nx * (j + (long long)g.ny * k);
+    const double s = SR ? (double)sR[c] : g.cdt * (double)rho[c] * (double)kR[c];
+    const double fdd = (double)f[d * g.N + c];
+    cw[t] = (AT)face_speed<double>(fdd, fdd, s, s, g.tau_k);
 }
 
 }  // namespace vr

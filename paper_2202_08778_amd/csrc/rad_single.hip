@@ -868,11 +868,13 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, Tfix, sR, dEA, fA, Cf, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG, part,
-        small, total;
+    size_t X, X0, Tc, Tfix, sR, dEA, fA, Cf, CW, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG,
+        part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
 };
+
+long long wall_area(int nx, int ny, int nz) { return (long long)nx * ny + (long long)ny * nz + (long long)nx * nz; }
 
 long long vec_blocks(long long n) { return std::min<long long>((n / 4 + kBlock - 1) / kBlock, 2048); }
 
@@ -910,8 +912,10 @@ int mg_levels(int nx, int ny, int nz, long long &coarse_cells)
 // mg_cells: cells of the multigrid levels below the grid (krylov_poly = 2): per coarse cell 25
 // values (sR, tensor, face speeds, E diagonal, Jacobi diagonal, right-hand side, residual,
 // correction), and per grid cell 6 more (Jacobi diagonal, the fine correction)
+// wall_area: cells on the three high faces of the grid (the high walls' own speeds of the grid and,
+// in as much room again, of its multigrid levels)
 Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr = false, bool vel = false,
-              long long mg_cells = 0)
+              long long mg_cells = 0, long long wall_area = 0)
 {
     Layout L;
     const bool mixed = p.prec == RAD_MIXED;
@@ -934,6 +938,7 @@ Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr 
     L.dEA = take(N * ksz);
     L.fA = (mixed && p.coef_dtype == RAD_F64) ? take(6 * N * ksz) : take(0);
     L.Cf = take(3 * N * ksz);
+    L.CW = take(2 * wall_area * ksz);
     // FP64 sR and face speeds of the FP64 residual (the FP64 path shares sR and Cf)
     L.sR64 = take(mixed ? N * 8 : 0);
     L.Cf64 = take(mixed ? 3 * N * 8 : 0);
@@ -1114,9 +1119,17 @@ int run_step(Solver &S)
                                    f + 6 * o, Cf64 + 3 * o);
             }
         });
+    // the high walls' own speeds (FP32 Krylov apply)
+    const bool walls = S.walls;
+    AT *CwA = walls ? S.at<AT>(S.L.CW) : nullptr;
+    if (walls && !S.amr)
+        S.timed(K_SETUP, 0.0, [&] {
+            const long long nw = wall_area(g.nx, g.ny, g.nz);
+            hipLaunchKernelGGL((k_wall_speed<CT, AT>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, S.st, g, rho,
+                               kR, (const AT *)nullptr, f, CwA);
+        });
     // moving medium: the O(v/c) coefficients, once per step
     const bool vel = S.beta != nullptr;
-    const bool walls = S.walls;
     const int vimp = vel && p.vel_implicit;
     double *VA = vel ? S.at<double>(S.L.VA) : nullptr, *VB = vel ? S.at<double>(S.L.VB) : nullptr;
     double *VC = vel ? S.at<double>(S.L.VC) : nullptr;
@@ -1174,13 +1187,15 @@ int run_step(Solver &S)
                                            S.st, S.gl[l], tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
                                            (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                            y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)),
-                                           (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf);
+                                           (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf,
+                                           (const AT *)CwA);
                     else
                         hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bt, 0,
                                            S.st, S.gl[l], tg[l], f + 6 * o, sR + o, (const CT *)nullptr,
                                            (const CT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                            y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)),
-                                           (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf);
+                                           (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf,
+                                           (const AT *)CwA);
                 }
             };
             // grids with open, Marshak or reflecting walls take the sweep with the wall code
@@ -1226,6 +1241,7 @@ int run_step(Solver &S)
     bool use_mg = mgL > 1;   // cleared for the rest of the step if a cycle stalls
     struct MgLev {
         AT *sR, *f, *Cf, *dE, *D, *q, *t, *e;
+        AT *Cw;   // the high walls' own speeds (grids with open, Marshak or reflecting faces)
         TileGeom tg;
     };
     MgLev ml[kMaxMg] = {};
@@ -1246,6 +1262,9 @@ int run_step(Solver &S)
                 *dst[u] = b;
                 b += planes[u] * Nl;
             }
+            // the level's high-wall speeds, after the grid's in the same area
+            ml[l].Cw = walls ? (l == 1 ? CwA + wall_area(g.nx, g.ny, g.nz) : ml[l - 1].Cw + wall_area(S.mg[l - 1].nx, S.mg[l - 1].ny, S.mg[l - 1].nz))
+                             : nullptr;
             // small levels: short z-ranges, so that their few columns still give a few hundred workgroups
             // (a sweep of one workgroup over 8 planes is latency-bound)
             ml[l].tg = tile_geom<AT>(S.mg[l]);
@@ -1272,6 +1291,12 @@ int run_step(Solver &S)
                 }
                 hipLaunchKernelGGL((k_mg_face<AT>), mg_cells(gc), bl, 0, S.st, gc, (const AT *)ml[l].sR,
                                    (const AT *)ml[l].f, ml[l].Cf);
+                if (walls) {
+                    const long long nw = wall_area(gc.nx, gc.ny, gc.nz);
+                    hipLaunchKernelGGL((k_wall_speed<AT, AT, true>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0,
+                                       S.st, gc, (const AT *)nullptr, (const AT *)nullptr, (const AT *)ml[l].sR,
+                                       (const AT *)ml[l].f, ml[l].Cw);
+                }
             }
         });
     }
@@ -1298,7 +1323,8 @@ int run_step(Solver &S)
         hipLaunchKernelGGL(kern, tiles(ml[l].tg), bt, 0, S.st, S.mg[l], ml[l].tg, (const AT *)ml[l].f,
                            (const AT *)ml[l].sR, (const AT *)nullptr, (const AT *)nullptr, (const AT *)ml[l].Cf,
                            (const AT *)ml[l].dE, x, (const double *)nullptr, y, AT(1), AT(1), AmrLv{},
-                           (const AT *)nullptr, (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout, mf);
+                           (const AT *)nullptr, (const AT *)nullptr, pg, xm, qv, qm, AT(1), dout, mf,
+                           (const AT *)ml[l].Cw);
         const double ybytes = mgm == 1 ? 0.5 * kb : 4 * kb, xbytes = mgm == 2 ? 4.5 * kb : 4 * kb;
         prof_end(tok, S.st,
                  (double)S.mg[l].N * (xbytes + ybytes + 6 * kb + 5 * kb + (qv ? 4 * kb : 0) + (dout ? 2 * kb : 0)));
@@ -1783,7 +1809,7 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
                        dim3(tile_threads<AT>()), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
                        (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
                        (AT)(1.0 / c), (AT)c, AmrLv{}, (const AT *)nullptr, (const AT *)nullptr, AT(0), AT(1),
-                       (const AT *)nullptr, AT(0), AT(1), (AT *)nullptr, MgFuse<AT>{});
+                       (const AT *)nullptr, AT(0), AT(1), (AT *)nullptr, MgFuse<AT>{}, (const AT *)nullptr);
 }
 
 }  // namespace
@@ -1806,7 +1832,7 @@ extern "C" size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t
     if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
     long long mgc = 0;
     if (mg_cells_for(nx, ny, nz, *p, mgc) != RAD_OK) return 0;
-    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc).total;
+    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc, wall_area(nx, ny, nz)).total;
 }
 
 namespace {
@@ -1865,7 +1891,7 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     S.p = *p;
     long long mgc = 0;
     RAD_TRY(mg_cells_for(nx, ny, nz, *p, mgc));
-    S.L = layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc);
+    S.L = layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, false, mgc, wall_area(nx, ny, nz));
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
     S.host = host ? host : pinned_staging();
     if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
@@ -1941,7 +1967,7 @@ extern "C" size_t rad_workspace_bytes_moving(int nx, int ny, int nz, const rad_p
 {
     if (!p || nx < 1 || ny < 1 || nz < 1 || check_params(p) != RAD_OK) return 0;
     if (p->krylov_poly == 2) return (void)fail(RAD_EINVAL, "the moving-medium step has no multigrid Krylov operator"), 0;
-    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, true).total;
+    return layout((long long)nx * ny * nz, *p, tile_bound(nx, ny, nz), false, true, 0, wall_area(nx, ny, nz)).total;
 }
 
 extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, double *T_gas, const void *rho,
@@ -1961,7 +1987,7 @@ extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, dou
     if (p->krylov_poly == 2) return fail(RAD_EINVAL, "the moving-medium step has no multigrid Krylov operator");
     RAD_TRY(init_solver(S, nx, ny, nz, E, F, T_gas, rho, kappa_P, kappa_R, f_ij, dt, dx, bc, p, workspace,
                         (size_t)-1, stream));
-    S.L = layout(S.Ntot, *p, tile_bound(nx, ny, nz), false, true);
+    S.L = layout(S.Ntot, *p, tile_bound(nx, ny, nz), false, true, 0, wall_area(nx, ny, nz));
     if (ws_bytes < S.L.total) return fail(RAD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, S.L.total);
     S.beta = beta;
     S.kz_apply = S.kz_res = 0;   // the velocity variants are not in the autotune cache
