@@ -242,13 +242,13 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                  (x0 + kTX >= g.nx && kind_of(0, 1) >= BC_OPEN ? 2u : 0u) |
                                  (y0 == 0 && kind_of(1, 0) >= BC_OPEN ? 4u : 0u) |
                                  (y0 + kTY >= g.ny && kind_of(1, 1) >= BC_OPEN ? 8u : 0u);
-    // A high wall's speed is the cell's own, which the stored low-face speeds do not hold.  FP32 Krylov
-    // sweeps of tiles on a high x wall (a quarter of the tiles at 256^3) read it from cw (per step: x walls
-    // [nz][ny], then y walls [nz][nx], then z walls [ny][nx]), staged into LDS for the tile's z-range (1 KB,
-    // so that two workgroups still share a CU); the rarer high y and z walls, and z-ranges over kWz planes,
-    // form it.
-    constexpr int kWz = 32;
-    constexpr bool WST = WL && CST && !CALL && sizeof(AT) == 4;
+    // A high wall's speed is the cell's own, which the stored low-face speeds do not hold.  Sweeps of
+    // tiles on a high x wall (a quarter of the tiles at 256^3) read it from cw (per step: x walls [nz][ny],
+    // then y walls [nz][nx], then z walls [ny][nx]), staged into LDS for the tile's z-range: FP32 Krylov
+    // sweeps (1 KB, so that two workgroups still share a CU) and the FP64 residual (8 KB beside its 145 KB,
+    // one workgroup per CU either way).  The rarer high y and z walls, and longer z-ranges, form it.
+    constexpr int kWz = CALL ? 128 : 32;
+    constexpr bool WST = WL && CST && (CALL || sizeof(AT) == 4);
     __shared__ std::conditional_t<WST, AT[kWz * kTY], AT[1]> wsp;
     const bool wlds = WST && cw != nullptr && tg.kz <= kWz && (twall & 2u);
     if constexpr (WST) {

@@ -166,7 +166,8 @@ __global__ void __launch_bounds__(tile_threads<double>())
                      const double *__restrict__ sR64, const double *__restrict__ Cf64, const double *__restrict__ X,
                      KT *__restrict__ out, DT *__restrict__ dEA, double *partials, AmrLv al = AmrLv{},
                      const double *__restrict__ VA = nullptr, const double *__restrict__ VB = nullptr,
-                     const double *__restrict__ VC = nullptr, DT *__restrict__ vbw = nullptr)
+                     const double *__restrict__ VC = nullptr, DT *__restrict__ vbw = nullptr,
+                     const double *__restrict__ cw = nullptr)
 {
     __shared__ double lds[2][Rec<true>::NL][TileShape<double>::LY][kLX];
     const long long N = g.N;
@@ -262,7 +263,7 @@ __global__ void __launch_bounds__(tile_threads<double>())
         wall_ghost<double>(kind, d, side, Ec, Fc, fcr, e[0], Fo, g.finc8[2 * d + side], En_, Fn_, fnr);
     };
     tile_sweep<double, CT, true, true, NEX, true, WL>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64,
-                                                      X, 1.0, 1.0, lds, lex, epi, wall);
+                                                      X, 1.0, 1.0, lds, lex, epi, wall, MgFuse<double>{}, cw);
     block_store<5, tile_threads<double>()>(acc, partials, blockIdx.x);
 }
 
@@ -868,7 +869,7 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
 }
 
 struct Layout {
-    size_t X, X0, Tc, Tfix, sR, dEA, fA, Cf, CW, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG,
+    size_t X, X0, Tc, Tfix, sR, dEA, fA, Cf, CW, CW64, sR64, Cf64, AAG, AAf, AMRC, AMRCA, VA, VB, VC, VBA, VCA, V, W, MG,
         part, small, total;
     long long nblk_cells, nblk_vec;
     size_t ksz;
@@ -939,6 +940,7 @@ Layout layout(long long N, const rad_params_t &p, long long part_rows, bool amr 
     L.fA = (mixed && p.coef_dtype == RAD_F64) ? take(6 * N * ksz) : take(0);
     L.Cf = take(3 * N * ksz);
     L.CW = take(2 * wall_area * ksz);
+    L.CW64 = take(mixed ? wall_area * 8 : 0);   // the grid's, in FP64 for the mixed path's residual
     // FP64 sR and face speeds of the FP64 residual (the FP64 path shares sR and Cf)
     L.sR64 = take(mixed ? N * 8 : 0);
     L.Cf64 = take(mixed ? 3 * N * 8 : 0);
@@ -1122,11 +1124,15 @@ int run_step(Solver &S)
     // the high walls' own speeds (FP32 Krylov apply)
     const bool walls = S.walls;
     AT *CwA = walls ? S.at<AT>(S.L.CW) : nullptr;
+    double *Cw64 = walls ? (mixed ? S.at<double>(S.L.CW64) : (double *)CwA) : nullptr;
     if (walls && !S.amr)
         S.timed(K_SETUP, 0.0, [&] {
             const long long nw = wall_area(g.nx, g.ny, g.nz);
             hipLaunchKernelGGL((k_wall_speed<CT, AT>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, S.st, g, rho,
                                kR, (const AT *)nullptr, f, CwA);
+            if (mixed)
+                hipLaunchKernelGGL((k_wall_speed<CT, double>), dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, S.st,
+                                   g, rho, kR, (const double *)nullptr, f, Cw64);
         });
     // moving medium: the O(v/c) coefficients, once per step
     const bool vel = S.beta != nullptr;
@@ -1439,7 +1445,7 @@ int run_step(Solver &S)
                                        S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o, f + 6 * o, sR64 + o,
                                        Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o, part + rrows * 5,
                                        level_view(l, corr, sizeof(double)), (const double *)VA, (const double *)VB,
-                                       (const double *)VC, VBA);
+                                       (const double *)VC, VBA, (const double *)Cw64);
                 };
                 if (S.amr)
                     go(std::true_type{}, std::integral_constant<int, 0>{});
