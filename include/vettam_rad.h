@@ -60,7 +60,7 @@ typedef enum {
 typedef enum {
     RAD_BC_PERIODIC = 0,
     RAD_BC_OUTFLOW = 1,    /* zero-gradient outflow (Sec. 3.3): the ghost is the boundary cell */
-    RAD_BC_DIRICHLET = 2,  /* fixed ghost data: the batched blocks */
+    RAD_BC_DIRICHLET = 2,  /* fixed ghost data: params->ghost on the single grid, the blocks' ghost layers */
     RAD_BC_OPEN = 3,       /* characteristic outflow: incoming characteristic held at its old value */
     RAD_BC_MARSHAK = 4,    /* c E + 2 F_in = 4 F_inc at the wall (Sec. 3.4), F_inc in params->F_inc */
     RAD_BC_REFLECT = 5     /* mirror */
@@ -115,6 +115,14 @@ typedef struct {
                              energy for any eps_P.  rad_step only, with anderson_m = 0 */
     int max_refine;       /* most FP64 residual evaluations (GMRES restarts) per linear solve; 0: no limit
                              beyond max_krylov */
+    const double *ghost[6]; /* each RAD_BC_DIRICHLET face (-x,+x,-y,+y,-z,+z) of a single grid: device
+                             pointer (caller-owned, read only, FP64) to the ghost cells' fixed state, four
+                             planes (E, F_x, F_y, F_z; F physical) over the face's cells in the order
+                             x faces [nz][ny], y faces [nz][nx], z faces [ny][nx] (last index fastest);
+                             one ghost layer, the one the first-order stencil reads.  NULL (default) for
+                             other faces.  rad_step, rad_step_noalloc, rad_step_moving, rad_autotune_step
+                             and rad_residual need it for every Dirichlet face (RAD_EINVAL otherwise);
+                             rad_apply and rad_face_speeds never read it */
 } rad_params_t;
 
 typedef struct {
@@ -152,6 +160,9 @@ size_t rad_workspace_bytes(int nx, int ny, int nz, const rad_params_t *p);
 /* One implicit radiation step on a uniform grid (Sec. 2.3.1 steps iv-vi).
  * bc[6]: faces -x,+x,-y,+y,-z,+z, each RAD_BC_PERIODIC (in pairs) or one of
  * the walls, whose ghost cell (coefficients: the boundary cell's) holds
+ *   RAD_BC_DIRICHLET the fixed state params->ghost[face] (the ghost data with which
+ *                   the HLLE flux of Sec. 2.3.3 is taken across the face; the data
+ *                   enter the right-hand side only);
  *   RAD_BC_OUTFLOW  the boundary cell's state (zero gradient, Sec. 3.3): uniform states
  *                   stay uniform, but where the corrected speed is below c sqrt(f_dd)
  *                   (optically thick boundary cells) the wall's block is indefinite, so

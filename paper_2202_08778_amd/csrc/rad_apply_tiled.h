@@ -12,11 +12,12 @@
 // through the boundary rule (periodic: wrap, any wall: the boundary cell
 // itself), so boundary faces and ragged tile edges need no special cases: a
 // zero-gradient wall's face carries the cell's physical flux and no
-// dissipation.  An open, Marshak or reflecting wall adds the difference to the
-// flux against its ghost, which is local to the cell (the HLLE flux is linear
-// in the neighbour's state): tiles holding wall cells compute it in uniform
-// branches on every lane and keep it on the wall's lanes, so the sweep carries
-// no per-lane branch and no ghost data.  The per-cell epilogue is a functor:
+// dissipation.  A Dirichlet, open, Marshak or reflecting face adds the
+// difference to the flux against its ghost, which is local to the cell (the
+// HLLE flux is linear in the neighbour's state): tiles holding such cells
+// compute it in uniform branches on every lane and keep it on the face's lanes,
+// so the sweep carries no per-lane branch, and the Krylov operator no ghost data
+// (the residual reads a Dirichlet face's data in those branches only).  The per-cell epilogue is a functor:
 // the Krylov operator apply and the FP64 residual of one Picard iteration
 // share the sweep.
 #pragma once
@@ -135,7 +136,7 @@ struct MgFuse {
 // factor nu), the face speeds of the faces between two cells (Jacobi diagonal)
 // and of all six faces (residual weights; a wall face takes the cell's own
 // speed), and the walls' own shares of the Jacobi diagonal per row (wE, wF;
-// zero away from open, Marshak and reflecting walls).
+// zero away from Dirichlet, open, Marshak and reflecting faces).
 template <class AT>
 struct CellSums {
     AT Ec, Fc[3], sc, dEs, dF[3], sumC_nb, sumC_all, wE, wF[3];
@@ -146,11 +147,13 @@ struct CellSums {
 // precomputed too; otherwise each face's speed is formed from f and sR.
 // lex(k, pb, o, e) loads the NE per-cell extras of the epilogue (plane k, its
 // base pb, in-plane offset o); epi(k, c, o, active, sums, e) consumes one cell;
-// wall(kind, d, side, Ec, Fc, fcr, e, Eg, Fg, fg) forms the ghost across an
-// open, Marshak or reflecting wall from the cell's values (and its extras e);
-// WL: the grid has such walls (the sweep without them has no wall code at all).
+// wall(kind, d, side, Ec, Fc, fcr, e, fi, Eg, Fg, fg) forms the ghost across a
+// Dirichlet, open, Marshak or reflecting face from the cell's values (its extras e
+// and its index fi on the face); WL: the grid has such faces (0: none, and no wall
+// code at all; 1: open, Marshak and reflecting walls; 2: Dirichlet faces too -- a
+// separate level, since a fourth specialised branch costs the other kinds registers).
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
-template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, bool WL = false, bool INJ = false,
+template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, int WL = 0, bool INJ = false,
           class LEX, class EPI, class WALL>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
@@ -225,23 +228,23 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     }
     auto mapz = [&](int q) { return map_axis(q, g.nz, g.bclo[2], g.bchi[2]); };
     // the six faces' kinds packed 4 bits each (face 2 d + side), and the faces of the thread's cells on
-    // open, Marshak or reflecting walls (bits: x lo, x hi, y lo, y hi)
+    // Dirichlet, open, Marshak or reflecting faces (bits: x lo, x hi, y lo, y hi)
     unsigned kinds = 0;
     for (int fi = 0; fi < 6; ++fi) kinds |= (unsigned)((fi & 1) ? g.bchi[fi >> 1] : g.bclo[fi >> 1]) << (4 * fi);
     auto kind_of = [&](int d, int side) { return (int)((kinds >> (4 * (2 * d + side))) & 15u); };
-    const bool zwall_lo = WL && kind_of(2, 0) >= BC_OPEN, zwall_hi = WL && kind_of(2, 1) >= BC_OPEN;
+    const bool zwall_lo = WL && ghost_face(kind_of(2, 0)), zwall_hi = WL && ghost_face(kind_of(2, 1));
     unsigned wmask[CPT];
     for (int c = 0; c < CPT; ++c)
         wmask[c] = !(WL && active[c]) ? 0u
-                   : (selfx_lo && kind_of(0, 0) >= BC_OPEN ? 1u : 0u) | (selfx_hi && kind_of(0, 1) >= BC_OPEN ? 2u : 0u) |
-                         (selfy_lo[c] && kind_of(1, 0) >= BC_OPEN ? 4u : 0u) |
-                         (selfy_hi[c] && kind_of(1, 1) >= BC_OPEN ? 8u : 0u);
+                   : (selfx_lo && ghost_face(kind_of(0, 0)) ? 1u : 0u) | (selfx_hi && ghost_face(kind_of(0, 1)) ? 2u : 0u) |
+                         (selfy_lo[c] && ghost_face(kind_of(1, 0)) ? 4u : 0u) |
+                         (selfy_hi[c] && ghost_face(kind_of(1, 1)) ? 8u : 0u);
     // tiles holding cells on such walls (uniform; bits as wmask)
     const unsigned twall = !WL ? 0u
-                           : (x0 == 0 && kind_of(0, 0) >= BC_OPEN ? 1u : 0u) |
-                                 (x0 + kTX >= g.nx && kind_of(0, 1) >= BC_OPEN ? 2u : 0u) |
-                                 (y0 == 0 && kind_of(1, 0) >= BC_OPEN ? 4u : 0u) |
-                                 (y0 + kTY >= g.ny && kind_of(1, 1) >= BC_OPEN ? 8u : 0u);
+                           : (x0 == 0 && ghost_face(kind_of(0, 0)) ? 1u : 0u) |
+                                 (x0 + kTX >= g.nx && ghost_face(kind_of(0, 1)) ? 2u : 0u) |
+                                 (y0 == 0 && ghost_face(kind_of(1, 0)) ? 4u : 0u) |
+                                 (y0 + kTY >= g.ny && ghost_face(kind_of(1, 1)) ? 8u : 0u);
     // A high wall's speed is the cell's own, which the stored low-face speeds do not hold.  Sweeps of
     // tiles on a high x wall (a quarter of the tiles at 256^3) read it from cw (per step: x walls [nz][ny],
     // then y walls [nz][nx], then z walls [ny][nx]), staged into LDS for the tile's z-range: FP32 Krylov
@@ -331,39 +334,53 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     };
 
     const AT tk = (AT)g.tau_k;
-    // The correction that turns the flux of wall face (d, side) of a cell from the self-mapped one
+    // The correction that turns the flux of ghost face (d, side) of a cell from the self-mapped one
     // the sweep computed (neighbour = the cell itself: the cell's physical flux, whatever the speed)
-    // into the flux against the wall's ghost, which the wall functor forms from the cell's state,
-    // tensor row and (the nonlinear residual) the walls' data; plus the wall's shares of the Jacobi
-    // diagonal.  Cw: the wall's speed (the cell's own).  m: 1 for a cell on the wall, else 0 -- the
-    // correction is computed by every lane of a tile holding such cells (uniform branches, no
-    // per-lane ones) and kept by those on the wall.
-    // (d is a constant once the face loops are unrolled)
+    // into the flux against the face's ghost, which the wall functor forms from the cell's state,
+    // tensor row and (the nonlinear residual) the face's data at the cell's index fi on the face
+    // (x faces [nz][ny], y faces [nz][nx], z faces [ny][nx], formed from the mapped coordinates:
+    // in range on every lane); plus the face's shares of the Jacobi diagonal.  Cw: the face's speed
+    // (the cell's own).  m: 1 for a cell on the face, else 0 -- the correction is computed by every
+    // lane of a tile holding such cells (uniform branches, no per-lane ones) and kept by those on
+    // the face.  (d is a constant once the face loops are unrolled)
     auto wall_fix_k = [&](auto K, int d, int side, AT m, AT Cw, const AT(&fr)[3], const AT(&e)[NE > 0 ? NE : 1],
-                          CellSums<AT> &S) __attribute__((always_inline)) {
+                          int k, int c, CellSums<AT> &S) __attribute__((always_inline)) {
         constexpr int kind = decltype(K)::value;
+        const unsigned my = (unsigned)map_axis(y0 + CPT * ly + c, g.ny, g.bclo[1], g.bchi[1]);
+        const unsigned fi = d == 0 ? (unsigned)k * (unsigned)g.ny + my
+                                   : (d == 1 ? (unsigned)k * (unsigned)g.nx + (unsigned)mx
+                                             : my * (unsigned)g.nx + (unsigned)mx);
         AT Eg, Fg[3], fg[3];
-        wall(kind, d, side, S.Ec, S.Fc, fr, e, Eg, Fg, fg);
+        wall(kind, d, side, S.Ec, S.Fc, fr, e, fi, Eg, Fg, fg);
         const AT sg = side ? AT(1) : AT(-1), ms = m * sg, hc = AT(-0.5) * sg * Cw;
         S.dEs += ms * (AT(0.5) * (Fg[d] - S.Fc[d]) + hc * (Eg - S.Ec));
 #pragma unroll
         for (int q = 0; q < 3; ++q) S.dF[q] += ms * (AT(0.5) * (fg[q] * Eg - fr[q] * S.Ec) + hc * (Fg[q] - S.Fc[q]));
         if constexpr (PRE) {
-            AT qE, qF;
-            wall_diag_q<AT>(kind, d, fr, Cw, qE, qF);
+            AT qE, qF, qX;
+            wall_diag_q<AT>(kind, d, fr, Cw, qE, qF, qX);
             S.wE += m * qE;
-            S.wF[d] += m * qF;
+            if constexpr (kind == BC_DIRICHLET) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) S.wF[q] += m * (q == d ? qF : qX);
+            } else {
+                S.wF[d] += m * qF;
+            }
         }
     };
     // the kind is uniform: a scalar branch to code specialised for it
     auto wall_fix = [&](int kind, int d, int side, AT m, AT Cw, const AT(&fr)[3], const AT(&e)[NE > 0 ? NE : 1],
-                        CellSums<AT> &S) __attribute__((always_inline)) {
+                        int k, int c, CellSums<AT> &S) __attribute__((always_inline)) {
         if (kind == BC_OPEN)
-            wall_fix_k(std::integral_constant<int, BC_OPEN>{}, d, side, m, Cw, fr, e, S);
+            wall_fix_k(std::integral_constant<int, BC_OPEN>{}, d, side, m, Cw, fr, e, k, c, S);
         else if (kind == BC_MARSHAK)
-            wall_fix_k(std::integral_constant<int, BC_MARSHAK>{}, d, side, m, Cw, fr, e, S);
-        else
-            wall_fix_k(std::integral_constant<int, BC_REFLECT>{}, d, side, m, Cw, fr, e, S);
+            wall_fix_k(std::integral_constant<int, BC_MARSHAK>{}, d, side, m, Cw, fr, e, k, c, S);
+        else if (WL == 2 && kind == BC_DIRICHLET) {
+            if constexpr (WL == 2)
+                wall_fix_k(std::integral_constant<int, BC_DIRICHLET>{}, d, side, m, Cw, fr, e, k, c, S);
+        } else {
+            wall_fix_k(std::integral_constant<int, BC_REFLECT>{}, d, side, m, Cw, fr, e, k, c, S);
+        }
     };
 
     ZRow prev[CPT];
@@ -418,7 +435,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                             S.sumC_all += Cface;
                     }
                     face_flux_acc<AT>(d, side, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
-                    // an open, Marshak or reflecting wall (y: the lowest row only holds the first cell);
+                    // a Dirichlet, open, Marshak or reflecting face (y: the lowest row only holds the first cell);
                     // its speed: a low face's stored speed is the cell's own, a high face's is formed
                     if (WL && (twall & (1u << (2 * d + side))) && !(d == 1 && side == 0 && c > 0)) {
                         const AT m = AT((wmask[c] >> (2 * d + side)) & 1u);
@@ -433,7 +450,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                                 Cw = self_face_speed<AT>(fcr[d], S.sc, tk);
                             }
                         }
-                        wall_fix(kind_of(d, side), d, side, m, Cw, fcr, ex[c], S);
+                        wall_fix(kind_of(d, side), d, side, m, Cw, fcr, ex[c], k, c, S);
                     }
                 }
             }
@@ -454,7 +471,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                 if constexpr (CALL) S.sumC_all += Cface;
                 face_flux_acc<AT>(2, 0, Cface, S.Ec, S.Fc, fcr, En, Fn, fnr, S.dEs, S.dF);
                 if (WL && selfz_lo && zwall_lo)   // uniform: the grid's bottom plane
-                    wall_fix(kind_of(2, 0), 2, 0, AT(1), Cface, fcr, ex[c], S);
+                    wall_fix(kind_of(2, 0), 2, 0, AT(1), Cface, fcr, ex[c], k, c, S);
             }
             {
                 AT En = lds[b][IX][sy][sxx];
@@ -477,7 +494,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
                 if (WL && selfz_hi && zwall_hi) {   // uniform: the grid's top plane
                     AT Cw = Cface;
                     if constexpr (CST) Cw = self_face_speed<AT>(fcr[2], S.sc, tk);
-                    wall_fix(kind_of(2, 1), 2, 1, AT(1), Cw, fcr, ex[c], S);
+                    wall_fix(kind_of(2, 1), 2, 1, AT(1), Cw, fcr, ex[c], k, c, S);
                 }
             }
             epi(k, c, off[c], active[c], S, ex[c]);
@@ -609,7 +626,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // MGM (multigrid, FP32 tiles, even z-ranges): 1 fuses the restriction of the
 // output into mf (y is not written), 2 the injection of mf's coarse correction
 // into the operand (see MgFuse).
-template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true, bool WL = false,
+template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true, int WL = 0,
           int MGM = 0>
 __global__ void __launch_bounds__(tile_threads<AT>())
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
@@ -732,9 +749,9 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             for (int q = 0; q < 3; ++q) st_off(y + (1 + q) * N + pb, o, yFq[q] * yF);
         }
     };
-    // the linear operator's walls: ghosts without their data
-    auto wall = [&](int kind, int d, int side, AT Ec, const AT(&Fc)[3], const AT(&fcr)[3], const AT(&)[NEX], AT &En,
-                    AT(&Fn)[3], AT(&fnr)[3]) __attribute__((always_inline)) {
+    // the linear operator's ghost faces: ghosts without their data
+    auto wall = [&](int kind, int d, int side, AT Ec, const AT(&Fc)[3], const AT(&fcr)[3], const AT(&)[NEX], unsigned,
+                    AT &En, AT(&Fn)[3], AT(&fnr)[3]) __attribute__((always_inline)) {
         const AT z3[3] = {AT(0), AT(0), AT(0)};
         wall_ghost<AT>(kind, d, side, Ec, Fc, fcr, AT(0), z3, AT(0), En, Fn, fnr);
     };
@@ -761,8 +778,8 @@ __global__ void __launch_bounds__(256) k_face_coef(Grid g, const CT *__restrict_
     }
 }
 
-// The own corrected speed (divided by c) of every cell on a high open, Marshak or reflecting
-// wall, once per step, in FP64 from the stored coefficients, rounded to the apply precision:
+// The own corrected speed (divided by c) of every cell on a high Dirichlet, open, Marshak or
+// reflecting face, once per step, in FP64 from the stored coefficients, rounded to the apply precision:
 // x walls [nz][ny], then y walls [nz][nx], then z walls [ny][nx] (other faces' entries unused).
 // SR: sR is given (coarse levels), else formed from rho and kR.
 template <class CT, class AT, bool SR = false>
@@ -781,7 +798,7 @@ __global__ void __launch_bounds__(256) k_wall_speed(Grid g, const CT *__restrict
     } else {
         d = 2, i = (int)((t - ax - ay) % g.nx), j = (int)((t - ax - ay) / g.nx), k = g.nz - 1;
     }
-    if (wall_kind(g, d, 1) < BC_OPEN) return;
+    if (!ghost_face(wall_kind(g, d, 1))) return;
     const long long c = i + (long long)g.nx * (j + (long long)g.ny * k);
     const double s = SR ? (double)sR[c] : g.cdt * (double)rho[c] * (double)kR[c];
     const double fdd = (double)f[d * g.N + c];

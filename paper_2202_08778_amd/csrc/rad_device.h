@@ -22,11 +22,15 @@ constexpr int kBlock = 256;   // threads per workgroup of the streaming kernels 
 constexpr int kMaxM = 64;     // largest GMRES restart length
 constexpr int kMaxAnderson = 5;  // most past iterates of the Anderson-accelerated Picard map
 
-// Face kinds (the values of rad_bc_kind).  Every kind but periodic and
-// Dirichlet maps the neighbour across the wall to the boundary cell itself;
-// outflow keeps it (zero gradient), open, Marshak and reflect then replace its
-// state by their ghost (wall_ghost).
+// Face kinds (the values of rad_bc_kind).  Every kind but periodic maps the
+// neighbour across the face to the boundary cell itself; outflow keeps it (zero
+// gradient), Dirichlet, open, Marshak and reflect then replace its state by
+// their ghost (wall_ghost).
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2, BC_OPEN = 3, BC_MARSHAK = 4, BC_REFLECT = 5 };
+
+// Faces whose ghost is not the boundary cell's own state: they correct the flux of the
+// self-mapped neighbour (Dirichlet data and the open, Marshak and reflecting walls).
+__host__ __device__ __forceinline__ constexpr bool ghost_face(int kind) { return kind >= BC_DIRICHLET; }
 
 // Geometry and constants of one uniform grid.
 struct Grid {
@@ -41,7 +45,22 @@ struct Grid {
     int cv_cubic;     // 0: E_int = alpha T; 1: C_v = alpha T^3, E_int = alpha T^4 / 4 (alpha = rho cv)
     double finc8[6];  // Marshak faces (-x,+x,-y,+y,-z,+z): 8 F_inc / c, the ghost's affine part
     double eps_N;     // relative tolerance of the per-cell Newton solve (0: to round-off)
+    // Dirichlet faces (-x,+x,-y,+y,-z,+z): the ghost cells' E and F (physical), 4 planes of the
+    // face's cells -- x faces [nz][ny], y faces [nz][nx], z faces [ny][nx]; null elsewhere
+    const double *ghost[6];
 };
+
+// Cells on face d of a grid, and the index on that face of the cell with in-plane offset o
+// (o = i + nx j) on plane k.
+__host__ __device__ __forceinline__ long long face_area(const Grid &g, int d)
+{
+    return d == 0 ? (long long)g.ny * g.nz : (d == 1 ? (long long)g.nx * g.nz : (long long)g.nx * g.ny);
+}
+__device__ __forceinline__ long long face_index(const Grid &g, int d, int k, unsigned o)
+{
+    const unsigned j = o / (unsigned)g.nx, i = o - j * (unsigned)g.nx;
+    return d == 0 ? (long long)k * g.ny + j : (d == 1 ? (long long)k * g.nx + i : (long long)j * g.nx + i);
+}
 
 // Kind of the wall on side `side` of axis d (periodic faces are no walls).
 __host__ __device__ __forceinline__ int wall_kind(const Grid &g, int d, int side)
@@ -50,7 +69,7 @@ __host__ __device__ __forceinline__ int wall_kind(const Grid &g, int d, int side
 }
 
 // row d of the symmetric tensor in the (xx,yy,zz,xy,xz,yz) plane order: f_d0, f_d1, f_d2
-__host__ __device__ constexpr int tens_row(int d, int j)
+__host__ __device__ __forceinline__ constexpr int tens_row(int d, int j)
 {
     return d == j ? d : ((d + j) == 1 ? 3 : ((d + j) == 2 ? 4 : 5));
 }
@@ -112,11 +131,12 @@ __device__ __forceinline__ long long neighbour(const Grid &g, int i, int j, int 
     return g.bclo[d] == BC_PERIODIC ? c + (long long)(n - 1) * stride : c;
 }
 
-// Ghost state across a wall face of kind open, Marshak or reflect, in the
-// scaled variables (E, Ft = F / c); (Eo, Fo, e8) are the affine data (the old
-// state at the cell and 8 F_inc / c), all zero for the linear operator.  With
-// s = +1 at a low face and -1 at a high one (the sign of the incoming
-// direction along d):
+// Ghost state across a face of kind Dirichlet, open, Marshak or reflect, in the
+// scaled variables (E, Ft = F / c); (Eo, Fo, e8) are the affine data (Dirichlet:
+// the ghost's given state; open: the old state at the cell; Marshak: 8 F_inc / c),
+// all zero for the linear operator.  With s = +1 at a low face and -1 at a high
+// one (the sign of the incoming direction along d):
+//   Dirichlet: (Eo, Fo) itself;
 //   open:    the cell's state with the amplitude of the incoming characteristic
 //            of the d-flux, (E + s Ft_d / sqrt(f_dd)) / 2 (speed c sqrt(f_dd)),
 //            replaced by its old value along the eigenvector
@@ -126,7 +146,8 @@ __device__ __forceinline__ long long neighbour(const Grid &g, int i, int j, int 
 //   reflect: E_g = E, Ft_g = Ft with Ft_d negated, tensor row with f_dj
 //            (j != d) negated.
 // The ghost's own tensor row is the cell's otherwise; its corrected speed is
-// the cell's own (both cells have the same f_dd and sR).
+// the cell's own (both cells have the same f_dd and sR): the ghost's
+// coefficients are the boundary cell's, Dirichlet faces included.
 template <class T>
 __device__ __forceinline__ void wall_ghost(int kind, int d, int side, T Ec, const T (&Fc)[3], const T (&fcr)[3],
                                            T Eo, const T (&Fo)[3], T e8, T &Eg, T (&Fg)[3], T (&fg)[3])
@@ -138,41 +159,36 @@ __device__ __forceinline__ void wall_ghost(int kind, int d, int side, T Ec, cons
     const T Fcd = d == 0 ? Fc[0] : (d == 1 ? Fc[1] : Fc[2]);
     const T Fod = d == 0 ? Fo[0] : (d == 1 ? Fo[1] : Fo[2]);
     const bool op = kind == BC_OPEN && fdd > T(0), ms = kind == BC_MARSHAK, rf = kind == BC_REFLECT;
+    const bool dr = kind == BC_DIRICHLET;
     const T ia = op ? T(1) / xsqrt(fdd) : T(0);
     const T delta = op ? T(0.5) * ((Eo + s * Fod * ia) - (Ec + s * Fcd * ia)) : T(0);
     const T Em = e8 - T(4) * s * Fcd - Ec;
-    Eg = ms ? Em : Ec + delta;
+    Eg = dr ? Eo : (ms ? Em : Ec + delta);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const T Fj = Fc[j] + delta * s * fcr[j] * ia;
-        Fg[j] = (rf && j == d) ? -Fc[j] : Fj;
+        Fg[j] = dr ? Fo[j] : ((rf && j == d) ? -Fc[j] : Fj);
         fg[j] = (rf && j != d) ? -fcr[j] : fcr[j];
     }
 }
 
-// The wall face's share of the Jacobi diagonal (the derivative of its flux
+// The ghost face's share of the Jacobi diagonal (the derivative of its flux
 // contribution with respect to the cell's own unknowns, to be multiplied by
 // nu): open: (sqrt(f_dd) + C)/4 in the E and F_d rows; Marshak: C in the E row,
-// 2 f_dd in the F_d row; reflect: C in the F_d row.  The other rows get nothing
-// from a wall (their ghost values follow the cell's one to one).  qE, qF: the
-// shares of the E row and of the F_d row.
+// 2 f_dd in the F_d row; reflect: C in the F_d row; Dirichlet (the ghost does not
+// follow the cell): C/2 in every row, as a face between two cells.  The other
+// rows get nothing from a wall (their ghost values follow the cell's one to
+// one).  qE, qF, qX: the shares of the E row, of the F_d row and of each F_j
+// row with j != d.
 template <class T>
-__device__ __forceinline__ void wall_diag_q(int kind, int d, const T (&fcr)[3], T C, T &qE, T &qF)
+__device__ __forceinline__ void wall_diag_q(int kind, int d, const T (&fcr)[3], T C, T &qE, T &qF, T &qX)
 {
     const T fdd = d == 0 ? fcr[0] : (d == 1 ? fcr[1] : fcr[2]);
-    const bool op = kind == BC_OPEN && fdd > T(0);
+    const bool op = kind == BC_OPEN && fdd > T(0), dr = kind == BC_DIRICHLET;
     const T qo = T(0.25) * (xsqrt(op ? fdd : T(0)) + C);
-    qE = op ? qo : (kind == BC_MARSHAK ? C : T(0));
-    qF = op ? qo : (kind == BC_MARSHAK ? T(2) * fdd : (kind == BC_REFLECT ? C : T(0)));
-}
-template <class T>
-__device__ __forceinline__ void wall_diag(int kind, int d, const T (&fcr)[3], T C, T &wE, T (&wF)[3])
-{
-    T qE, qF;
-    wall_diag_q<T>(kind, d, fcr, C, qE, qF);
-    wE += qE;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) wF[j] += j == d ? qF : T(0);
+    qE = dr ? T(0.5) * C : (op ? qo : (kind == BC_MARSHAK ? C : T(0)));
+    qF = dr ? T(0.5) * C : (op ? qo : (kind == BC_MARSHAK ? T(2) * fdd : (kind == BC_REFLECT ? C : T(0))));
+    qX = dr ? T(0.5) * C : T(0);
 }
 
 // face_speed of a face between a cell and itself (a wall's speed), without branches; the same
@@ -242,9 +258,18 @@ __device__ __forceinline__ void transport(const Grid &g, int i, int j, int k, lo
             T fnr[3] = {fl(tens_row(d, 0), nb), fl(tens_row(d, 1), nb), fl(tens_row(d, 2), nb)};
             const T C = face_speed<T>(fcr[d], fnr[d], sRc, sr(nb), tk);
             const int wk = nb == c ? wall_kind(g, d, side) : BC_PERIODIC;
-            if (wk >= BC_OPEN) {
-                const T zero3[3] = {T(0), T(0), T(0)};
-                wall_ghost<T>(wk, d, side, Ec, Fc, fcr, affine ? Eo : T(0), affine ? Fo : zero3,
+            if (ghost_face(wk)) {
+                T Ea = affine ? Eo : T(0), Fa[3] = {affine ? Fo[0] : T(0), affine ? Fo[1] : T(0),
+                                                    affine ? Fo[2] : T(0)};
+                if (affine && wk == BC_DIRICHLET) {   // the face's data at the cell's place on it
+                    const double *gd = g.ghost[2 * d + side];
+                    const long long fi = face_index(g, d, k, (unsigned)(i + (long long)g.nx * j)),
+                                    ar = face_area(g, d);
+                    Ea = (T)gd[fi];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) Fa[q] = (T)(gd[(1 + q) * ar + fi] / g.c);
+                }
+                wall_ghost<T>(wk, d, side, Ec, Fc, fcr, Ea, Fa,
                               affine && wk == BC_MARSHAK ? (T)g.finc8[2 * d + side] : T(0), En, Fn, fnr);
             }
             sumC_all += C;

@@ -229,6 +229,7 @@ extern "C" void rad_default_params(rad_params_t *p)
     p->eps_N = 0.0;
     p->energy_fix = 0;
     p->max_refine = 0;
+    for (int f = 0; f < 6; ++f) p->ghost[f] = nullptr;
 }
 
 // ------------------------------------------------------------------ autotune cache

@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kBlock)
 // emission keeps the fraction 1 - eta of the energy row's O(v/c) terms (the gas
 // energy eliminated, as for the emission) and writes that row's coupling to Ft
 // for the Krylov apply (vbw).
-template <class CT, class KT, class DT, bool AMR = false, int VEL = 0, bool WL = false>
+template <class CT, class KT, class DT, bool AMR = false, int VEL = 0, int WL = 0>
 __global__ void __launch_bounds__(tile_threads<double>())
     k_residual_tiled(Grid g, TileGeom tg, int picard_mode, const double *__restrict__ En,
                      const double *__restrict__ Fn, const double *__restrict__ Tn, const double *__restrict__ Ts,
@@ -256,11 +256,19 @@ __global__ void __launch_bounds__(tile_threads<double>())
             acc[4] += zz;
         }
     };
-    // the walls' ghosts with their data: the old state (E_n, F_n / c) and 8 F_inc / c
+    // the ghosts with their data: a Dirichlet face's given state at the cell's place on the face,
+    // the old state (E_n, F_n / c) of an open wall and 8 F_inc / c
     auto wall = [&](int kind, int d, int side, double Ec, const double(&Fc)[3], const double(&fcr)[3],
-                    const double(&e)[NEX], double &En_, double(&Fn_)[3], double(&fnr)[3]) __attribute__((always_inline)) {
-        const double Fo[3] = {e[1] * invc, e[2] * invc, e[3] * invc};
-        wall_ghost<double>(kind, d, side, Ec, Fc, fcr, e[0], Fo, g.finc8[2 * d + side], En_, Fn_, fnr);
+                    const double(&e)[NEX], unsigned fi, double &En_, double(&Fn_)[3], double(&fnr)[3])
+                    __attribute__((always_inline)) {
+        double Eo = e[0], Fo[3] = {e[1] * invc, e[2] * invc, e[3] * invc};
+        if (kind == BC_DIRICHLET) {   // (kind, d and side are constants here; 32 fi < 2^31 checked on the host)
+            const double *gd = g.ghost[2 * d + side];
+            const long long ar = face_area(g, d);
+            Eo = ld_off(gd, fi);
+            for (int q = 0; q < 3; ++q) Fo[q] = ld_off(gd + (1 + q) * ar, fi) * invc;
+        }
+        wall_ghost<double>(kind, d, side, Ec, Fc, fcr, Eo, Fo, g.finc8[2 * d + side], En_, Fn_, fnr);
     };
     tile_sweep<double, CT, true, true, NEX, true, WL>(g, tg, f, sR64, (const CT *)nullptr, (const CT *)nullptr, Cf64,
                                                       X, 1.0, 1.0, lds, lex, epi, wall, MgFuse<double>{}, cw);
@@ -841,12 +849,17 @@ Grid make_grid(int nx, int ny, int nz, const int bc[6], double dt, double dx, co
     g.cv_cubic = p.cv_cubic;
     for (int f = 0; f < 6; ++f) g.finc8[f] = 8.0 * p.F_inc[f] / p.c;
     g.eps_N = p.eps_N;
+    for (int f = 0; f < 6; ++f) g.ghost[f] = bc[f] == RAD_BC_DIRICHLET ? p.ghost[f] : nullptr;
     return g;
 }
 
+// Dirichlet faces on a uniform single grid: rejected, accepted (calls that never read the ghost
+// data: the linear operator, the face speeds) or accepted with params->ghost of each such face set.
+enum { DIR_NO = 0, DIR_ANY = 1, DIR_DATA = 2 };
+
 // allow_walls: the open, Marshak and reflecting faces (uniform single grids)
 int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6], const rad_params_t *p,
-                    bool allow_dirichlet, bool allow_walls = true)
+                    int dirichlet, bool allow_walls = true)
 {
     if (!p) return fail(RAD_EINVAL, "params is NULL");
     if (nx < 1 || ny < 1 || nz < 1) return fail(RAD_EINVAL, "grid extents must be >= 1");
@@ -858,9 +871,15 @@ int check_grid_args(int nx, int ny, int nz, double dt, double dx, const int bc[6
     if (!bc) return fail(RAD_EINVAL, "bc is NULL");
     for (int f = 0; f < 6; ++f) {
         const bool wall = bc[f] == RAD_BC_OPEN || bc[f] == RAD_BC_MARSHAK || bc[f] == RAD_BC_REFLECT;
-        if (bc[f] != RAD_BC_PERIODIC && bc[f] != RAD_BC_OUTFLOW && !(allow_dirichlet && bc[f] == RAD_BC_DIRICHLET) &&
+        if (bc[f] != RAD_BC_PERIODIC && bc[f] != RAD_BC_OUTFLOW && !(dirichlet && bc[f] == RAD_BC_DIRICHLET) &&
             !(allow_walls && wall))
             return fail(RAD_EINVAL, "unsupported boundary kind %d on face %d", bc[f], f);
+        if (dirichlet == DIR_DATA && bc[f] == RAD_BC_DIRICHLET && !p->ghost[f])
+            return fail(RAD_EINVAL, "Dirichlet face %d without ghost data (params->ghost[%d] is NULL)", f, f);
+        // the sweep addresses a face's data plane by a 32-bit byte offset
+        const long long n[3] = {nx, ny, nz}, area = n[(f / 2 + 1) % 3] * n[(f / 2 + 2) % 3];
+        if (bc[f] == RAD_BC_DIRICHLET && area > (1LL << 26))
+            return fail(RAD_EINVAL, "Dirichlet face %d larger than 2^26 cells", f);
     }
     for (int a = 0; a < 3; ++a)
         if ((bc[2 * a] == RAD_BC_PERIODIC) != (bc[2 * a + 1] == RAD_BC_PERIODIC))
@@ -986,7 +1005,8 @@ struct Solver {
     Grid mg[kMaxMg];      // their grids (mg[0] = g)
     long long c0[2] = {0, 0};
     bool amr = false;
-    bool walls = false;   // an open, Marshak or reflecting face (uniform single grids only)
+    bool walls = false;   // a Dirichlet, open, Marshak or reflecting face (uniform single grids only)
+    bool dirichlet = false;   // ... of which a Dirichlet face
     Amr A{};
     long long nshell = 0, ncoarse = 0;  // threads of the level-jump kernel
     long long Ntot = 0;                 // cells of all levels
@@ -1123,6 +1143,7 @@ int run_step(Solver &S)
         });
     // the high walls' own speeds (FP32 Krylov apply)
     const bool walls = S.walls;
+    const int wl = walls ? (S.dirichlet ? 2 : 1) : 0;   // the sweep's wall level
     AT *CwA = walls ? S.at<AT>(S.L.CW) : nullptr;
     double *Cw64 = walls ? (mixed ? S.at<double>(S.L.CW64) : (double *)CwA) : nullptr;
     if (walls && !S.amr)
@@ -1184,10 +1205,12 @@ int run_step(Solver &S)
             const long long o = S.c0[l];
             auto go = [&](auto amr_c, auto vel_c, auto lc_c, auto wl_c, auto mg_c) {
                 constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
-                constexpr bool WLc = decltype(wl_c)::value;
+                constexpr int WLc = decltype(wl_c)::value;
                 constexpr int MG = decltype(mg_c)::value;
-                // not built: walls on the two-level grid, fused transfers outside the plain FP32 apply
-                if constexpr (!(AM && WLc) && (MG == 0 || (!AM && !VL && std::is_same<AT, float>::value))) {
+                // not built: walls on the two-level grid, fused transfers outside the plain FP32 apply,
+                // Dirichlet faces with the face speeds formed per face
+                if constexpr (!(AM && WLc) && (MG == 0 || (!AM && !VL && std::is_same<AT, float>::value)) &&
+                              !(WLc == 2 && !LC)) {
                     if (fA)
                         hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bt, 0,
                                            S.st, S.gl[l], tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
@@ -1204,20 +1227,20 @@ int run_step(Solver &S)
                                            (const AT *)CwA);
                 }
             };
-            // grids with open, Marshak or reflecting walls take the sweep with the wall code
+            // grids with Dirichlet, open, Marshak or reflecting faces take the sweep with the wall code
+            // (Dirichlet faces: its own level, with the stored face speeds)
             auto go2 = [&](auto amr_c, auto vel_c, auto lc_c) {
                 using I0 = std::integral_constant<int, 0>;
                 using I1 = std::integral_constant<int, 1>;
                 using I2 = std::integral_constant<int, 2>;
-                if (walls) {
-                    if (mgm == 1) go(amr_c, vel_c, lc_c, std::true_type{}, I1{});
-                    else if (mgm == 2) go(amr_c, vel_c, lc_c, std::true_type{}, I2{});
-                    else go(amr_c, vel_c, lc_c, std::true_type{}, I0{});
-                } else {
-                    if (mgm == 1) go(amr_c, vel_c, lc_c, std::false_type{}, I1{});
-                    else if (mgm == 2) go(amr_c, vel_c, lc_c, std::false_type{}, I2{});
-                    else go(amr_c, vel_c, lc_c, std::false_type{}, I0{});
-                }
+                auto go3 = [&](auto wl_c, auto lc2) {
+                    if (mgm == 1) go(amr_c, vel_c, lc2, wl_c, I1{});
+                    else if (mgm == 2) go(amr_c, vel_c, lc2, wl_c, I2{});
+                    else go(amr_c, vel_c, lc2, wl_c, I0{});
+                };
+                if (wl == 2) go3(I2{}, std::true_type{});
+                else if (wl == 1) go3(I1{}, lc_c);
+                else go3(I0{}, lc_c);
             };
             if (S.amr)
                 go2(std::true_type{}, std::false_type{}, std::true_type{});
@@ -1247,7 +1270,7 @@ int run_step(Solver &S)
     bool use_mg = mgL > 1;   // cleared for the rest of the step if a cycle stalls
     struct MgLev {
         AT *sR, *f, *Cf, *dE, *D, *q, *t, *e;
-        AT *Cw;   // the high walls' own speeds (grids with open, Marshak or reflecting faces)
+        AT *Cw;   // the high walls' own speeds (grids with Dirichlet, open, Marshak or reflecting faces)
         TileGeom tg;
     };
     MgLev ml[kMaxMg] = {};
@@ -1312,7 +1335,7 @@ int run_step(Solver &S)
                         const MgFuse<AT> &mf = MgFuse<AT>{}) {
         const int tok = prof_begin(K_MG, S.st);
         auto pick = [&](auto wl_c, auto mg_c) {
-            constexpr bool WLc = decltype(wl_c)::value;
+            constexpr int WLc = decltype(wl_c)::value;
             constexpr int MG = decltype(mg_c)::value;
             if constexpr (MG == 0 || std::is_same<AT, float>::value)
                 return &k_apply_tiled<AT, AT, true, false, false, true, WLc, MG>;
@@ -1322,10 +1345,8 @@ int run_step(Solver &S)
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
-        auto kern = walls ? (mgm == 1 ? pick(std::true_type{}, I1{}) : mgm == 2 ? pick(std::true_type{}, I2{})
-                                                                               : pick(std::true_type{}, I0{}))
-                          : (mgm == 1 ? pick(std::false_type{}, I1{}) : mgm == 2 ? pick(std::false_type{}, I2{})
-                                                                                : pick(std::false_type{}, I0{}));
+        auto pick3 = [&](auto wl_c) { return mgm == 1 ? pick(wl_c, I1{}) : mgm == 2 ? pick(wl_c, I2{}) : pick(wl_c, I0{}); };
+        auto kern = wl == 2 ? pick3(I2{}) : wl == 1 ? pick3(I1{}) : pick3(I0{});
         hipLaunchKernelGGL(kern, tiles(ml[l].tg), bt, 0, S.st, S.mg[l], ml[l].tg, (const AT *)ml[l].f,
                            (const AT *)ml[l].sR, (const AT *)nullptr, (const AT *)nullptr, (const AT *)ml[l].Cf,
                            (const AT *)ml[l].dE, x, (const double *)nullptr, y, AT(1), AT(1), AmrLv{},
@@ -1439,8 +1460,9 @@ int run_step(Solver &S)
                 auto go = [&](auto amr_c, auto vel_c) {
                     constexpr bool AM = decltype(amr_c)::value;
                     constexpr int VL = decltype(vel_c)::value;
-                    auto kern = (walls && !AM) ? k_residual_tiled<CT, KT, AT, false, VL, true>
-                                               : k_residual_tiled<CT, KT, AT, AM, VL, false>;
+                    auto kern = (wl == 2 && !AM)   ? k_residual_tiled<CT, KT, AT, false, VL, 2>
+                                : (wl == 1 && !AM) ? k_residual_tiled<CT, KT, AT, false, VL, 1>
+                                                   : k_residual_tiled<CT, KT, AT, AM, VL, 0>;
                     hipLaunchKernelGGL(kern, tiles(tgr[l]), bt64, 0, S.st, S.gl[l], tgr[l], p.mode, S.En + o,
                                        S.Fn + 3 * o, S.Tn + o, Tc + o, rho + o, kP + o, f + 6 * o, sR64 + o,
                                        Cf64 + 3 * o, X + 4 * o, V + 4 * o, dEA + o, part + rrows * 5,
@@ -1808,9 +1830,14 @@ void launch_apply_phys(const Grid &g, const void *x, void *y, const void *dE, co
                        const void *f, double c, hipStream_t st)
 {
     const TileGeom tg = tile_geom<AT>(g);
-    bool walls = false;
-    for (int a = 0; a < 3; ++a) walls |= g.bclo[a] >= BC_OPEN || g.bchi[a] >= BC_OPEN;
-    auto kern = walls ? k_apply_tiled<AT, CT, false, false, false, true, true> : k_apply_tiled<AT, CT, false>;
+    int wl = 0;
+    for (int a = 0; a < 3; ++a) {
+        wl = std::max(wl, ghost_face(g.bclo[a]) || ghost_face(g.bchi[a]) ? 1 : 0);
+        wl = g.bclo[a] == BC_DIRICHLET || g.bchi[a] == BC_DIRICHLET ? 2 : wl;
+    }
+    auto kern = wl == 2   ? k_apply_tiled<AT, CT, false, false, false, true, 2>
+                : wl == 1 ? k_apply_tiled<AT, CT, false, false, false, true, 1>
+                          : k_apply_tiled<AT, CT, false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(tg.tiles_x * tg.tiles_y * tg.tiles_z)),
                        dim3(tile_threads<AT>()), 0, st, g, tg, (const CT *)f, (const AT *)nullptr, (const CT *)rho, (const CT *)kR,
                        (const AT *)nullptr, (const AT *)dE, (const AT *)x, (const double *)nullptr, (AT *)y,
@@ -1890,7 +1917,7 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
                 const void *kappa_P, const void *kappa_R, const void *f_ij, double dt, double dx, const int bc[6],
                 const rad_params_t *p, void *workspace, size_t ws_bytes, void *stream, double *host = nullptr)
 {
-    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, DIR_DATA));
     if (!E || !F || !T_gas || !rho || !kappa_P || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
     if (!workspace) return fail(RAD_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace) % 256) return fail(RAD_EINVAL, "workspace must be 256-byte aligned");
@@ -1902,7 +1929,10 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     S.host = host ? host : pinned_staging();
     if (!S.host) return fail(RAD_EHIP, "pinned host staging allocation failed");
     S.g = make_grid(nx, ny, nz, bc, dt, dx, *p);
-    for (int a = 0; a < 6; ++a) S.walls |= bc[a] >= BC_OPEN;
+    for (int a = 0; a < 6; ++a) {
+        S.walls |= ghost_face(bc[a]);
+        S.dirichlet |= bc[a] == RAD_BC_DIRICHLET;
+    }
     S.nlev = 1;
     S.gl[0] = S.g;
     S.mgL = 1;
@@ -1910,9 +1940,11 @@ int init_solver(Solver &S, int nx, int ny, int nz, double *E, double *F, double 
     if (p->krylov_poly == 2) {
         long long cells = 0;
         S.mgL = mg_levels(nx, ny, nz, cells);
-        for (int l = 1; l < S.mgL; ++l)
+        for (int l = 1; l < S.mgL; ++l) {
             S.mg[l] = make_grid(S.mg[l - 1].nx / 2, S.mg[l - 1].ny / 2, S.mg[l - 1].nz / 2, bc, dt,
                                 dx * (double)(1 << l), *p);
+            for (int f = 0; f < 6; ++f) S.mg[l].ghost[f] = nullptr;   // coarse operators take no data
+        }
     }
     S.Ntot = S.g.N;
     S.st = (hipStream_t)stream;
@@ -1985,7 +2017,7 @@ extern "C" int rad_step_moving(int nx, int ny, int nz, double *E, double *F, dou
     auto t0 = std::chrono::steady_clock::now();
     if (stats) std::memset(stats, 0, sizeof(*stats));
     Solver S;
-    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, DIR_DATA));
     if (!beta) return fail(RAD_EINVAL, "beta (velocity) is NULL");
     if (p->vel_implicit && p->anderson_m > 0)
         return fail(RAD_EINVAL, "anderson_m must be 0 with vel_implicit = 1");
@@ -2019,7 +2051,7 @@ int amr_setup(const rad_amr2_t *geom, const int bc[6], double dt, double dx, con
     if (p && p->cv_cubic) return fail(RAD_EINVAL, "the two-level grid requires cv_cubic = 0");
     if (p && p->krylov_poly == 2) return fail(RAD_EINVAL, "the two-level grid has no multigrid Krylov operator");
     const int nc[3] = {geom->nx, geom->ny, geom->nz};
-    RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, false, false));
+    RAD_TRY(check_grid_args(nc[0], nc[1], nc[2], dt, dx, bc, p, DIR_NO, false));
     if (p->energy_fix) return fail(RAD_EINVAL, "energy_fix: single-grid rad_step only");
     Amr &A = S.A;
     int fbc[6];
@@ -2228,7 +2260,7 @@ extern "C" int rad_residual(int nx, int ny, int nz, const double *E_n, const dou
                             const rad_params_t *p, double *R, void *stream)
 {
     clear_error();
-    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, DIR_DATA));
     if (!E_n || !F_n || !T_n || !E || !F || !T || !rho || !kappa_P || !kappa_R || !f_ij || !R)
         return fail(RAD_EINVAL, "NULL data pointer");
     Grid g = make_grid(nx, ny, nz, bc, dt, dx, *p);
@@ -2252,7 +2284,7 @@ extern "C" int rad_face_speeds(int nx, int ny, int nz, const void *rho, const vo
                                double dx, const int bc[6], const rad_params_t *p, double *C, void *stream)
 {
     clear_error();
-    RAD_TRY(check_grid_args(nx, ny, nz, 1.0, dx, bc, p, false));
+    RAD_TRY(check_grid_args(nx, ny, nz, 1.0, dx, bc, p, DIR_ANY));
     if (!rho || !kappa_R || !f_ij || !C) return fail(RAD_EINVAL, "NULL data pointer");
     // the wave speed does not depend on dt: evaluate with dt = dx / c (nu = 1)
     Grid g = make_grid(nx, ny, nz, bc, dx / p->c, dx, *p);
@@ -2273,7 +2305,7 @@ extern "C" int rad_apply(int nx, int ny, int nz, const void *x, void *y, const v
                          const rad_params_t *p, int dtype, void *stream)
 {
     clear_error();
-    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, false));
+    RAD_TRY(check_grid_args(nx, ny, nz, dt, dx, bc, p, DIR_ANY));
     if (!x || !y || !dE || !rho || !kappa_R || !f_ij) return fail(RAD_EINVAL, "NULL data pointer");
     if (dtype != RAD_F64 && dtype != RAD_F32) return fail(RAD_EINVAL, "dtype must be RAD_F64 or RAD_F32");
     Grid g = make_grid(nx, ny, nz, bc, dt, dx, *p);

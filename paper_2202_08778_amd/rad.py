@@ -27,7 +27,7 @@ class Params(ct.Structure):
                 ("max_krylov", ct.c_int), ("gmres_m", ct.c_int), ("prec", ct.c_int), ("mode", ct.c_int),
                 ("coef_dtype", ct.c_int), ("anderson_m", ct.c_int), ("vel_implicit", ct.c_int),
                 ("cv_cubic", ct.c_int), ("krylov_poly", ct.c_int), ("F_inc", ct.c_double * 6), ("eps_N", ct.c_double),
-                ("energy_fix", ct.c_int), ("max_refine", ct.c_int)]
+                ("energy_fix", ct.c_int), ("max_refine", ct.c_int), ("ghost", ct.c_void_p * 6)]
 
 
 class Stats(ct.Structure):
@@ -218,6 +218,22 @@ def _coef_dtype(t):
     raise TypeError("coefficients must be float64 or float32")
 
 
+def _set_ghost(p, ghost, shape):
+    """Point p.ghost at the Dirichlet faces' ghost data: a sequence of six entries (faces -x,+x,-y,+y,-z,+z),
+    each None or a contiguous float64 device tensor of (E, F_x, F_y, F_z) over the face's cells -- shape
+    (4, nz, ny) for x faces, (4, nz, nx) for y faces, (4, ny, nx) for z faces.  The tensors must outlive the
+    call."""
+    if ghost is None:
+        return
+    torch = _torch()
+    nz, ny, nx = shape
+    if len(ghost) != 6:
+        raise ValueError("ghost: one entry per face (-x,+x,-y,+y,-z,+z)")
+    area = (ny * nz, nx * nz, nx * ny)
+    for fi, t in enumerate(ghost):
+        p.ghost[fi] = None if t is None else _ptr(t, torch.float64, 4 * area[fi // 2], f"ghost[{fi}]")
+
+
 def workspace_bytes(shape, p: Params) -> int:
     nz, ny, nx = shape
     return int(lib.rad_workspace_bytes(nx, ny, nz, ct.byref(p)))
@@ -229,13 +245,15 @@ def alloc_workspace(nbytes, device=None):
 
 
 def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace=None, stream=None,
-             check=True):
+             check=True, ghost=None):
     """One implicit step in place on device tensors E (nz,ny,nx), F (3,...), T (...) (float64);
-    rho, kappa_P, kappa_R, f (6,...) of one float dtype.  Returns the stats dict."""
+    rho, kappa_P, kappa_R, f (6,...) of one float dtype; ghost: the Dirichlet faces' data (see _set_ghost).
+    Returns the stats dict."""
     torch = _torch()
     nz, ny, nx = E.shape
     N = nx * ny * nz
     p = Params.from_buffer_copy(p)
+    _set_ghost(p, ghost, E.shape)
     p.coef_dtype = _coef_dtype(rho)
     cd = rho.dtype
     args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
@@ -255,13 +273,14 @@ def rad_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, workspace
     return d
 
 
-def rad_step_noalloc(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, stream=None, check=True):
+def rad_step_noalloc(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, stream=None, check=True, ghost=None):
     """rad_step with the library's static device scratch as the workspace (no allocation in the call;
     grids whose workspace exceeds rad_noalloc_max_bytes() are refused with RAD_ENOMEM)."""
     torch = _torch()
     nz, ny, nx = E.shape
     N = nx * ny * nz
     p = Params.from_buffer_copy(p)
+    _set_ghost(p, ghost, E.shape)
     p.coef_dtype = _coef_dtype(rho)
     cd = rho.dtype
     args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
@@ -278,13 +297,14 @@ def rad_step_noalloc(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, s
 
 
 def rad_step_moving(E, F, T, rho, kappa_P, kappa_R, f, beta, dt, dx, bc, p: Params, workspace=None, stream=None,
-                    check=True):
+                    check=True, ghost=None):
     """rad_step in a moving medium: beta = v/c as a (3, nz, ny, nx) tensor of the coefficients' dtype
     (held fixed over the step); p.vel_implicit selects the implicit O(v/c) gas-energy term."""
     torch = _torch()
     nz, ny, nx = E.shape
     N = nx * ny * nz
     p = Params.from_buffer_copy(p)
+    _set_ghost(p, ghost, E.shape)
     p.coef_dtype = _coef_dtype(rho)
     cd = rho.dtype
     args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
@@ -364,7 +384,7 @@ def rad_step_amr2(geom: Amr2, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: 
 
 
 def autotune_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, tune_restart=True, workspace=None,
-                  stream=None):
+                  stream=None, ghost=None):
     """Autotune rad_step on this data (state left unchanged): returns {"kz_apply", "kz_residual", "gmres_m",
     "krylov_poly"}.  The z-ranges are cached and used by later rad_step calls; gmres_m and krylov_poly are
     recommendations."""
@@ -372,6 +392,7 @@ def autotune_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, tune
     nz, ny, nx = E.shape
     N = nx * ny * nz
     p = Params.from_buffer_copy(p)
+    _set_ghost(p, ghost, E.shape)
     p.coef_dtype = _coef_dtype(rho)
     cd = rho.dtype
     args = [_ptr(E, torch.float64, N, "E"), _ptr(F, torch.float64, 3 * N, "F"), _ptr(T, torch.float64, N, "T"),
@@ -387,12 +408,14 @@ def autotune_step(E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, tune
     return {"kz_apply": ka.value, "kz_residual": kr.value, "gmres_m": m.value, "krylov_poly": kp.value}
 
 
-def rad_residual(En, Fn, Tn, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, R=None, stream=None):
+def rad_residual(En, Fn, Tn, E, F, T, rho, kappa_P, kappa_R, f, dt, dx, bc, p: Params, R=None, stream=None,
+                 ghost=None):
     """Nonlinear residual (5, nz, ny, nx) float64 of a state; asynchronous on the stream."""
     torch = _torch()
     nz, ny, nx = E.shape
     N = nx * ny * nz
     p = Params.from_buffer_copy(p)
+    _set_ghost(p, ghost, E.shape)
     p.coef_dtype = _coef_dtype(rho)
     cd = rho.dtype
     if R is None:

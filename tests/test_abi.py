@@ -53,7 +53,7 @@ def _step(rad, p, nx=4, ny=4, nz=4, ptr=0x1000, bc="periodic", dt=1.0, dx=1.0, w
     (dict(dt=float("nan")), "dt"),
     (dict(dx=0.0), "dx"),
     (dict(bc=("periodic", "outflow", "periodic", "periodic", "periodic", "periodic")), "pairs"),
-    (dict(bc="dirichlet"), "boundary"),
+    (dict(bc="dirichlet"), "ghost data"),
     (dict(ptr=0), "NULL"),
     (dict(ws=0), "workspace"),
     (dict(ws=0x10001), "aligned"),
@@ -64,6 +64,38 @@ def test_rad_step_rejects_bad_arguments_on_host(rad, case, msg):
     rc = _step(rad, p, **case)
     assert rc in (rad.RAD_EINVAL, rad.RAD_ENOMEM)
     assert msg in rad.last_error()
+
+
+def test_dirichlet_faces_need_ghost_data_on_host(rad):
+    """A Dirichlet face of the single grid takes its data from params->ghost: without it the step,
+    the residual and the autotuner refuse it; with it the boundary check passes (here the call then
+    stops at the workspace check); the linear operator and the face speeds read no data; the
+    two-level grid and faces of more than 2^26 cells are refused."""
+    bc = ("dirichlet", "dirichlet", "periodic", "periodic", "periodic", "periodic")
+    p = rad.params()
+    assert _step(rad, p, bc=bc) == rad.RAD_EINVAL and "ghost[0]" in rad.last_error()
+    p.ghost[0] = 0x1000
+    assert _step(rad, p, bc=bc) == rad.RAD_EINVAL and "ghost[1]" in rad.last_error()
+    p.ghost[1] = 0x2000
+    assert _step(rad, p, bc=bc, ws=0) == rad.RAD_EINVAL and "workspace" in rad.last_error()
+    q = rad.params()
+    b = rad.bc_array(bc)
+    assert rad.lib.rad_residual(4, 4, 4, *([8] * 10), 1.0, 1.0, b, ct.byref(q), 8, None) == rad.RAD_EINVAL
+    assert "ghost" in rad.last_error()
+    assert rad.lib.rad_autotune_step(4, 4, 4, *([8] * 7), 1.0, 1.0, b, ct.byref(q), 0x1000, 1 << 30, None, 1,
+                                     None, None, None, None) == rad.RAD_EINVAL
+    assert "ghost" in rad.last_error()
+    # the linear operator and the face speeds pass the boundary check without data (then fail on dtype)
+    assert rad.lib.rad_apply(4, 4, 4, 8, 8, 8, 8, 8, 8, 1.0, 1.0, b, ct.byref(q), 5, None) == rad.RAD_EINVAL
+    assert "dtype" in rad.last_error()
+    g = rad.amr_geometry((4, 4, 4), (1, 1, 1), (3, 3, 3))
+    assert rad.lib.rad_step_amr2(ct.byref(g), *([8] * 7), 1.0, 1.0, b, ct.byref(p), 0x1000, 1 << 30, None,
+                                 None) == rad.RAD_EINVAL
+    assert "boundary" in rad.last_error()
+    big = rad.params()
+    big.ghost[0] = big.ghost[1] = 0x1000
+    assert _step(rad, big, nx=1, ny=9000, nz=9000, bc=bc) == rad.RAD_EINVAL
+    assert "2^26" in rad.last_error()
 
 
 @pytest.mark.parametrize("field,val", [("gmres_m", 0), ("gmres_m", 65), ("c", 0.0), ("tol", 0.0), ("prec", 7),

@@ -1,0 +1,329 @@
+"""Dirichlet faces on the single grid (the ghost data of params->ghost) on the GPU.
+
+Against the oracle on padded inputs whose Dirichlet ghosts hold the data and whose ghost
+coefficients are the boundary cells' own (the library's reading): face speeds, the linear operator
+(ghosts without data), the nonlinear residual (ghosts with data), and steps per field (<= 1e-10
+FP64, <= 1e-8 mixed), with ragged tiles along every axis and Dirichlet faces beside every other
+kind; the multigrid operator.  Also the steady anisotropic diffusion profile of a linear E with a
+constant flux, a closed form the scheme holds exactly for any dt, and the relaxation onto it."""
+import ctypes as ct
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_08778_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-8
+FINC = [0.7, 0.2, 0.0, 0.4, 0.3, 0.0]
+INNER = (slice(1, -1),) * 3
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def rad(torch):
+    from paper_2202_08778_amd import rad as r
+    return r
+
+
+def _dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _relerr(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def _pad(a, lead=0):
+    """One ghost layer per side holding the boundary cell's value."""
+    return np.pad(a, [(0, 0)] * lead + [(1, 1)] * 3, mode="edge")
+
+
+def _face_slab(fi):
+    """Index of face fi's ghost layer (its interior cells) in a padded (..., nz+2, ny+2, nx+2) array,
+    in the library's face order: x faces [k][j], y faces [k][i], z faces [j][i]."""
+    d, side = fi // 2, fi % 2
+    g = -1 if side else 0
+    i = slice(1, -1)
+    return (Ellipsis,) + ((i, i, g) if d == 0 else ((i, g, i) if d == 1 else (g, i, i)))
+
+
+def _ghost_data(Ep, Fp, bc):
+    """Per face: (4, ...) float64 of (E, F_x, F_y, F_z) on the face for Dirichlet faces, else None."""
+    out = []
+    for fi in range(6):
+        if bc[fi] != "dirichlet":
+            out.append(None)
+            continue
+        s = _face_slab(fi)
+        out.append(np.ascontiguousarray(np.concatenate([Ep[s][None], Fp[s]], axis=0)))
+    return out
+
+
+def _with_ghosts(rng, Ep, Fp, bc, c):
+    """Dirichlet ghost layers: the boundary cells' state scaled by U(0.5, 1.5) with a flux of up to
+    0.3 c E per component."""
+    for fi in range(6):
+        if bc[fi] != "dirichlet":
+            continue
+        s = _face_slab(fi)
+        Eg = Ep[s] * rng.uniform(0.5, 1.5, Ep[s].shape)
+        Ep[s] = Eg
+        for q in range(3):
+            Fp[q][s[1:]] = 0.3 * c * Eg * rng.uniform(-1.0, 1.0, Eg.shape)
+    return Ep, Fp
+
+
+CASES = [
+    ("dirichlet-x", (11, 13, 70), 2, ["dirichlet", "dirichlet", "periodic", "periodic", "periodic", "periodic"],
+     50.0),
+    ("dirichlet-1d", (1, 1, 90), 3, ["dirichlet", "dirichlet", "periodic", "periodic", "periodic", "periodic"],
+     20.0),
+    ("dirichlet-all", (9, 10, 12), 5, ["dirichlet"] * 6, 50.0),
+    ("dirichlet-mixed", (10, 9, 66), 6, ["dirichlet", "open", "outflow", "dirichlet", "marshak", "dirichlet"],
+     10.0),
+    ("dirichlet-yz", (12, 17, 8), 7, ["periodic", "periodic", "dirichlet", "reflect", "dirichlet", "dirichlet"],
+     30.0),
+]
+
+
+def _case(shape, seed, bc, dt_cross, f32=False):
+    d = W.mixed_depth(shape=shape, seed=seed, steps=1, dt_cross=dt_cross)
+    rng = np.random.default_rng(seed + 11)
+    d["F"] = 0.05 * rng.standard_normal((3,) + shape) * d["E"]
+    if f32:
+        for k in ("E", "F", "T", "rho", "kP", "kR", "f"):
+            d[k] = W._f32(d[k])
+    d["bc"] = bc
+    d["Ep"], d["Fp"] = _with_ghosts(rng, _pad(d["E"]), _pad(d["F"], 1), bc, d["c"])
+    d["Tp"] = _pad(d["T"])
+    d["ghost"] = _ghost_data(d["Ep"], d["Fp"], bc)
+    return d
+
+
+def _oracle_problem(d):
+    return oracle.Problem(_pad(d["rho"]), _pad(d["kP"]), _pad(d["kR"]), _pad(d["f"], 1), d["dt"], d["dx"], d["bc"],
+                          c=d["c"], aR=d["aR"], cv=d["cv"], finc=FINC, padded=True)
+
+
+def _params(rad, d, **kw):
+    return rad.params(c=d["c"], a_R=d["aR"], c_v=d["cv"], F_inc=FINC, **kw)
+
+
+def _ghost_dev(torch, d):
+    return [None if g is None else _dev(torch, g) for g in d["ghost"]]
+
+
+@pytest.mark.parametrize("name,shape,seed,bc,dtc", CASES)
+def test_dirichlet_face_speeds(torch, rad, name, shape, seed, bc, dtc):
+    _say("dirichlet face speeds", name, shape)
+    d = _case(shape, seed, bc, dtc)
+    Cx, Cy, Cz = _oracle_problem(d).face_speeds()
+    want = np.stack([Cx[INNER], Cy[INNER], Cz[INNER]])
+    got = rad.rad_face_speeds(_dev(torch, d["rho"]), _dev(torch, d["kR"]), _dev(torch, d["f"]), d["dx"], d["bc"],
+                              _params(rad, d)).cpu().numpy()
+    assert np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300)) <= 1e-13
+
+
+def _oracle_apply_linear(P, x, dE):
+    """The oracle's operator with every face's ghost filled as for the linear operator (Dirichlet: 0)."""
+    xp = np.ascontiguousarray(np.stack([_pad(x[q]) for q in range(4)]))
+    L = oracle.lib()
+    XG = (ct.c_void_p * 4)(*(xp[q].ctypes.data for q in range(4)))
+    L.or_fill_state_ghosts(ct.byref(P.g), ct.byref(P.cf), XG, None, 1)
+    return P.apply(xp, _pad(dE))[(slice(None),) + INNER]
+
+
+@pytest.mark.parametrize("name,shape,seed,bc,dtc", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dirichlet_operator_apply(torch, rad, name, shape, seed, bc, dtc, prec):
+    """The linear operator of a Picard iteration: Dirichlet ghosts without their data (zero)."""
+    _say("dirichlet apply", name, shape, prec)
+    d = _case(shape, seed, bc, dtc, f32=prec == "f32")
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((4,) + shape)
+    x[1:] *= d["c"]
+    dE = rng.uniform(1.0, 3.0, shape)
+    if prec == "f32":
+        x, dE = W._f32(x), W._f32(dE)
+    want = _oracle_apply_linear(_oracle_problem(d), x, dE)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    got = rad.rad_apply(_dev(torch, x, dt), _dev(torch, dE, dt), _dev(torch, d["rho"], dt), _dev(torch, d["kR"], dt),
+                        _dev(torch, d["f"], dt), d["dt"], d["dx"], d["bc"], _params(rad, d)).double().cpu().numpy()
+    tol = 1e-13 if prec == "f64" else 2e-6
+    scale = np.max(np.abs(want))
+    for q in range(4):
+        assert np.max(np.abs(got[q] - want[q])) <= tol * scale, (q, np.max(np.abs(got[q] - want[q])) / scale)
+
+
+@pytest.mark.parametrize("name,shape,seed,bc,dtc", CASES)
+def test_dirichlet_nonlinear_residual(torch, rad, name, shape, seed, bc, dtc):
+    """The nonlinear residual: Dirichlet ghosts with their data (and the walls' old state, F_inc)."""
+    _say("dirichlet residual", name, shape)
+    d = _case(shape, seed, bc, dtc)
+    rng = np.random.default_rng(seed + 1)
+    E = d["E"] * (1 + 0.1 * rng.standard_normal(shape))
+    F = d["F"] + 0.1 * rng.standard_normal((3,) + shape) * d["E"]
+    T = d["T"] * (1 + 0.1 * rng.standard_normal(shape))
+    Ep, Fp = d["Ep"].copy(), d["Fp"].copy()
+    Ep[INNER], Fp[(slice(None),) + INNER] = E, F
+    want = _oracle_problem(d).residual(d["Ep"], d["Fp"], d["Tp"], Ep, Fp, _pad(T))[(slice(None),) + INNER]
+    g = lambda a: _dev(torch, a)
+    got = rad.rad_residual(g(d["E"]), g(d["F"]), g(d["T"]), g(E), g(F), g(T), g(d["rho"]), g(d["kP"]), g(d["kR"]),
+                           g(d["f"]), d["dt"], d["dx"], d["bc"], _params(rad, d),
+                           ghost=_ghost_dev(torch, d)).cpu().numpy()
+    for q in range(5):
+        scale = max(np.max(np.abs(want[q])), 1e-300)
+        assert np.max(np.abs(got[q] - want[q])) <= 1e-12 * scale + 1e-13 * np.max(np.abs(want)), q
+
+
+def _oracle_step(d, **kw):
+    E, F, T, st = _oracle_problem(d).step(d["Ep"], d["Fp"], d["Tp"], **kw)
+    return E[INNER], F[(slice(None),) + INNER], T[INNER]
+
+
+@pytest.mark.parametrize("name,shape,seed,bc,dtc", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("poly", [1, 0], ids=["poly", "jacobi"])
+def test_dirichlet_step_matches_oracle(torch, rad, name, shape, seed, bc, dtc, prec, poly):
+    _say("dirichlet step", name, shape, prec, poly)
+    d = _case(shape, seed, bc, dtc, f32=prec == "mixed")
+    ref = _oracle_step(d, tol=1e-14)
+    cd = torch.float32 if prec == "mixed" else torch.float64
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    st = rad.rad_step(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd), d["dt"], d["dx"],
+                      d["bc"], _params(rad, d, prec=prec, tol=1e-13, krylov_poly=poly, gmres_m=30),
+                      ghost=_ghost_dev(torch, d))
+    _say("  stats", st)
+    errs = [_relerr(E.cpu().numpy(), ref[0]), _relerr(F.cpu().numpy(), ref[1]), _relerr(T.cpu().numpy(), ref[2])]
+    _say("  relerr E F T", ["%.2e" % e for e in errs])
+    assert max(errs) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dirichlet_multigrid_operator(torch, rad, prec):
+    """krylov_poly = 2 with Dirichlet x faces and open z faces (the coarse levels carry the same faces,
+    their ghosts without data) on the clumpy medium at 100 crossings."""
+    _say("dirichlet multigrid", prec)
+    bc = ["dirichlet", "dirichlet", "periodic", "periodic", "open", "open"]
+    c = W.periodic_clumpy(shape=(16, 8, 32), seed=6)
+    if prec == "mixed":
+        for k in ("E", "F", "T", "rho", "kP", "kR", "f"):
+            c[k] = W._f32(c[k])
+    rng = np.random.default_rng(9)
+    d = dict(c, bc=bc, aR=1.0, cv=1.0, c=1.0)
+    d["Ep"], d["Fp"] = _with_ghosts(rng, _pad(d["E"]), _pad(d["F"], 1), bc, 1.0)
+    d["Tp"] = _pad(d["T"])
+    d["ghost"] = _ghost_data(d["Ep"], d["Fp"], bc)
+    ref = _oracle_step(d, tol=1e-14)
+    cd = torch.float32 if prec == "mixed" else torch.float64
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    st = rad.rad_step(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd), d["dt"], d["dx"], bc,
+                      rad.params(prec=prec, tol=1e-13, krylov_poly=2, gmres_m=12), ghost=_ghost_dev(torch, d))
+    _say("  stats", st)
+    errs = [_relerr(E.cpu().numpy(), ref[0]), _relerr(F.cpu().numpy(), ref[1]), _relerr(T.cpu().numpy(), ref[2])]
+    _say("  relerr E F T", ["%.2e" % e for e in errs])
+    assert max(errs) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), errs
+
+
+# ------------------------------------------------- steady anisotropic diffusion (closed form)
+
+def _linear_profile(shape, sigR, f3, c, grad, E0):
+    """Padded E linear in x, y, z with the constant flux F = -(c / sigma_R) f grad E."""
+    nz, ny, nx = shape
+    h = 1.0 / nx
+    k = (np.arange(nz + 2) - 0.5) * h
+    j = (np.arange(ny + 2) - 0.5) * h
+    i = (np.arange(nx + 2) - 0.5) * h
+    E = E0 + grad[0] * i[None, None, :] + grad[1] * j[None, :, None] + grad[2] * k[:, None, None]
+    F = np.empty((3,) + E.shape)
+    for q, v in enumerate(-(c / sigR) * f3 @ np.asarray(grad)):
+        F[q] = v
+    return E, F, h
+
+
+F3 = np.array([[0.5, 0.1, -0.05], [0.1, 0.3, 0.02], [-0.05, 0.02, 0.2]])
+
+
+def _diffusion_inputs(torch, shape, sigR, c, E, F, cd):
+    f = np.empty((6,) + shape)
+    for n, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        f[n] = F3[a, b]
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    rho = np.full(shape, 2.0)
+    bc = ["dirichlet"] * 6
+    ghost = [_dev(torch, x) if x is not None else None for x in _ghost_data(E, F, bc)]
+    return (g(rho, cd), g(np.zeros(shape), cd), g(np.full(shape, sigR / 2.0), cd), g(f, cd)), bc, ghost
+
+
+@pytest.mark.parametrize("dt_cross", [0.3, 50.0, 1e4])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_steady_anisotropic_diffusion_holds_on_gpu(torch, rad, dt_cross, prec):
+    """sigma_P = 0, uniform sigma_R, a constant anisotropic f, E linear along every axis and the constant
+    diffusive flux: an exact discrete steady state (central differences of a linear field are exact,
+    the dissipation terms cancel).  With that profile as the data of six Dirichlet faces the step
+    returns its input for any dt; ragged tiles along x and y."""
+    _say("steady diffusion", dt_cross, prec)
+    shape, c, sigR = (6, 10, 70), 1.5, 3.0
+    Ep, Fp, h = _linear_profile(shape, sigR, F3, c, (0.7, -0.4, 0.25), 2.0)
+    cd = torch.float32 if prec == "mixed" else torch.float64
+    coef, bc, ghost = _diffusion_inputs(torch, shape, sigR, c, Ep, Fp, cd)
+    E, F, T = _dev(torch, Ep[INNER]), _dev(torch, Fp[(slice(None),) + INNER]), _dev(torch, np.full(shape, 0.5))
+    st = rad.rad_step(E, F, T, *coef, dt_cross * h / c, h, bc,
+                      rad.params(c=c, prec=prec, tol=1e-13, gmres_m=30), ghost=ghost)
+    _say("  stats", st)
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    assert np.max(np.abs(E.cpu().numpy() - Ep[INNER])) <= tol * np.max(np.abs(Ep))
+    assert np.max(np.abs(F.cpu().numpy() - Fp[(slice(None),) + INNER])) <= tol * np.max(np.abs(Fp))
+    assert np.all(T.cpu().numpy() == 0.5)
+
+
+def test_relaxation_onto_steady_diffusion_on_gpu(torch, rad):
+    """A perturbed start with dt = 1e4 light-crossing times relaxes onto the steady profile the six
+    Dirichlet faces impose (the perturbation decays by the slowest diffusion mode's factor)."""
+    shape, c, sigR = (8, 8, 16), 1.0, 4.0
+    Ep, Fp, h = _linear_profile(shape, sigR, F3, c, (1.0, 0.3, -0.2), 3.0)
+    coef, bc, ghost = _diffusion_inputs(torch, shape, sigR, c, Ep, Fp, torch.float64)
+    rng = np.random.default_rng(5)
+    E0 = Ep[INNER] + 0.3 * rng.standard_normal(shape)
+    F0 = Fp[(slice(None),) + INNER] + 0.3 * rng.standard_normal((3,) + shape)
+    E, F, T = _dev(torch, E0), _dev(torch, F0), _dev(torch, np.ones(shape))
+    st = rad.rad_step(E, F, T, *coef, 1e4 * h / c, h, bc, rad.params(c=c, tol=1e-13, gmres_m=40), ghost=ghost)
+    _say("  stats", st)
+    dE = np.max(np.abs(E.cpu().numpy() - Ep[INNER]))
+    dF = np.max(np.abs(F.cpu().numpy() - Fp[(slice(None),) + INNER]))
+    assert dE <= 1e-3 * np.max(np.abs(E0 - Ep[INNER])) and dF <= 1e-3 * np.max(np.abs(F0 - Fp[(slice(None),) + INNER]))
+
+
+def test_dirichlet_ghost_data_is_required(torch, rad):
+    d = _case((4, 4, 8), 1, ["dirichlet", "dirichlet", "periodic", "periodic", "periodic", "periodic"], 5.0)
+    g = lambda a: _dev(torch, a)
+    with pytest.raises(rad.RadError, match="ghost"):
+        rad.rad_step(g(d["E"]), g(d["F"]), g(d["T"]), g(d["rho"]), g(d["kP"]), g(d["kR"]), g(d["f"]), d["dt"], d["dx"],
+                     d["bc"], _params(rad, d))
+    gh = _ghost_dev(torch, d)
+    gh[0] = gh[0][:, :2].contiguous()
+    with pytest.raises(ValueError, match="ghost"):
+        rad.rad_step(g(d["E"]), g(d["F"]), g(d["T"]), g(d["rho"]), g(d["kP"]), g(d["kR"]), g(d["f"]), d["dt"], d["dx"],
+                     d["bc"], _params(rad, d), ghost=gh)
