@@ -33,21 +33,29 @@ constexpr int kTX = 64;  // tile width (x), one wave per row
 constexpr int kLX = kTX + 2;
 
 // thread rows of the tile, cells per thread along y and planes in flight
-// (prefetch depth), by arithmetic type: FP64 records take twice the registers
-template <class AT>
+// (prefetch depth), by arithmetic type; every shape covers the same 64 x 8 cell
+// tile.  One cell per thread and one plane in flight keep the FP32 sweep within
+// 128 VGPRs: two 512-thread workgroups per CU (their 75-81 KB of LDS each) give 4
+// waves per SIMD.  Measured at 256^3 against two cells per thread with two planes
+// in flight (PAIR: 256 threads, 231-245 VGPRs, 2 waves per SIMD): 295 against 317
+// us per Krylov apply, and 290 against 302 ms per multigrid step.  The two-level
+// grid's sweeps, whose jump terms would spill at 128 VGPRs, keep PAIR (1255
+// against 1305 ms per step).  FP64 records take twice the registers; its LDS
+// allows one workgroup per CU.
+template <class AT, bool PAIR = false>
 struct TileShape {
-    static constexpr int TYT = 4, CPT = 2, DEPTH = 2;
+    static constexpr int TYT = PAIR ? 4 : 8, CPT = PAIR ? 2 : 1, DEPTH = PAIR ? 2 : 1;
     static constexpr int TY = TYT * CPT, LY = TY + 2, HALO = 2 * kTX + 2 * TY;
 };
-template <>
-struct TileShape<double> {
+template <bool PAIR>
+struct TileShape<double, PAIR> {
     static constexpr int TYT = 8, CPT = 1, DEPTH = 1;
     static constexpr int TY = TYT * CPT, LY = TY + 2, HALO = 2 * kTX + 2 * TY;
 };
-template <class AT>
+template <class AT, bool PAIR = false>
 constexpr int tile_threads()
 {
-    return 64 * TileShape<AT>::TYT;
+    return 64 * TileShape<AT, PAIR>::TYT;
 }
 
 // Workgroup barrier that orders LDS only: global loads issued before it stay in
@@ -142,6 +150,19 @@ struct CellSums {
     AT Ec, Fc[3], sc, dEs, dF[3], sumC_nb, sumC_all, wE, wF[3];
 };
 
+// The workgroup's tile in XCD-aware order: consecutive workgroup ids go to different XCDs, so each
+// XCD gets a contiguous range of tiles (neighbours share halo rows in L2).
+__device__ __forceinline__ void tile_coords(const TileGeom &tg, int &bx, int &by, int &bz)
+{
+    const int ntiles = gridDim.x;
+    int tile = blockIdx.x;
+    if (ntiles % 8 == 0) tile = (blockIdx.x % 8) * (ntiles / 8) + blockIdx.x / 8;
+    bx = tile % tg.tiles_x;
+    const int rest = tile / tg.tiles_x;
+    by = rest % tg.tiles_y;
+    bz = rest / tg.tiles_y;
+}
+
 // The sweep.  PRE: sR is precomputed, otherwise derived from rho and kR.  CST
 // (PRE only): the low-face speeds Cf (divided by c, planes x|y|z) are
 // precomputed too; otherwise each face's speed is formed from f and sR.
@@ -153,35 +174,33 @@ struct CellSums {
 // code at all; 1: open, Marshak and reflecting walls; 2: Dirichlet faces too -- a
 // separate level, since a fourth specialised branch costs the other kinds registers).
 // Offsets inside one z plane are 32-bit: nx * ny * 8 < 2^31 is checked on the host.
+// beg(k) runs at the start of plane k's step, after the barrier that ended plane k - 1 and once the
+// prefetched record has gone to LDS (its registers free), before the next plane's loads are issued.
+struct NoPlaneHook {
+    __device__ void operator()(int) const {}
+};
 template <class AT, class ST, bool PRE, bool CALL, int NE, bool CST = PRE, int WL = 0, bool INJ = false,
-          class LEX, class EPI, class WALL>
+          bool PAIR = false, class LEX, class EPI, class WALL, class BEG = NoPlaneHook>
 __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, const ST *__restrict__ f,
                                            const AT *__restrict__ sR, const ST *__restrict__ rho,
                                            const ST *__restrict__ kR, const AT *__restrict__ Cf,
                                            const AT *__restrict__ x, AT s, AT sF,
-                                           AT (&lds)[2][Rec<CST>::NL][TileShape<AT>::LY][kLX], LEX lex, EPI epi,
+                                           AT (&lds)[2][Rec<CST>::NL][TileShape<AT, PAIR>::LY][kLX], LEX lex, EPI epi,
                                            WALL wall, const MgFuse<AT> &mf = MgFuse<AT>{},
-                                           const AT *__restrict__ cw = nullptr)
+                                           const AT *__restrict__ cw = nullptr, BEG beg = BEG{})
 {
-    constexpr int CPT = TileShape<AT>::CPT;   // a thread's cells: rows CPT ly + c of the tile
-    constexpr int kTY = TileShape<AT>::TY, kLY = TileShape<AT>::LY, kHalo = TileShape<AT>::HALO;
+    using TS = TileShape<AT, PAIR>;
+    constexpr int CPT = TS::CPT;   // a thread's cells: rows CPT ly + c of the tile
+    constexpr int kTY = TS::TY, kLY = TS::LY, kHalo = TS::HALO;
     static_assert(PRE || !CST, "stored face speeds come with stored sR");
     static_assert(!CALL || CST, "the nonlinear residual reads stored face speeds");
-    static_assert(!INJ || TileShape<AT>::CPT == 2, "the fused injection takes FP32 tiles");
     constexpr int NC = CST ? 3 : 0;
     constexpr int IX = Rec<CST>::IX, IF = Rec<CST>::IF, IS = Rec<CST>::IS, IC = Rec<CST>::IC, NL = Rec<CST>::NL;
 
     const long long N = g.N;
     const long long plane = (long long)g.nx * g.ny;
-    // XCD-aware tile order: consecutive workgroup ids go to different XCDs, so
-    // give each XCD a contiguous range of tiles (neighbours share halo rows in L2)
-    const int ntiles = gridDim.x;
-    int tile = blockIdx.x;
-    if (ntiles % 8 == 0) tile = (blockIdx.x % 8) * (ntiles / 8) + blockIdx.x / 8;
-    const int bx = tile % tg.tiles_x;
-    const int rest = tile / tg.tiles_x;
-    const int by = rest % tg.tiles_y;
-    const int bz = rest / tg.tiles_y;
+    int bx, by, bz;
+    tile_coords(tg, bx, by, bz);
     const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * tg.kz;
     const int z1 = min(z0 + tg.kz, g.nz);
     const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
@@ -196,11 +215,8 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         const int gy = y0 + CPT * ly + c;
         const int my = map_axis(gy, g.ny, g.bclo[1], g.bchi[1]);
         off[c] = (unsigned)mx + (unsigned)g.nx * (unsigned)my;
-        // (the thread's two cells, rows 2j and 2j+1, share their parents: one load serves both;
-        // a ragged row past the grid is not stored)
-        poff[c] = INJ ? (unsigned)(mx >> 1) + (unsigned)mf.ncx * (unsigned)(map_axis(y0 + CPT * ly, g.ny, g.bclo[1],
-                                                                                      g.bchi[1]) >> 1)
-                      : 0u;
+        // (a ragged row past the grid maps to the last row: its parent is in range, and it is not stored)
+        poff[c] = INJ ? (unsigned)(mx >> 1) + (unsigned)mf.ncx * (unsigned)(my >> 1) : 0u;
         active[c] = gx < g.nx && gy < g.ny;  // then off[c] is the cell's own offset
     }
     int hly = -1, hlx = -1;
@@ -514,7 +530,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
     // without a halo cell re-read their own cell, an L2 hit), so the compiler's
     // wait counts stay a full set deep.  The epilogue's per-cell extras of plane
     // k are issued ahead of the prefetch, so waiting for them leaves it in flight.
-    constexpr int DEPTH = TileShape<AT>::DEPTH;
+    constexpr int DEPTH = TS::DEPTH;
     const unsigned hsrc = hly >= 0 ? hoff : off[0], phsrc = hly >= 0 ? phoff : poff[0];
     using HT = std::conditional_t<SLIM, Halo, Full>;
     auto load_h = [&](int kp, HT &u) __attribute__((always_inline)) {
@@ -567,6 +583,7 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
         // plane k+1 (issued DEPTH planes ago) into the free slot
         for (int c = 0; c < CPT; ++c) put(b, CPT * ly + c + 1, lx + 1, S[c]);
         if (hly >= 0) put_h(b, H);
+        beg(k);
         if constexpr (NE > 0)
             for (int c = 0; c < CPT; ++c) lex(k, plane * k, off[c], ex[c]);
         if constexpr (decltype(LOAD)::value) {
@@ -626,9 +643,20 @@ __device__ __forceinline__ void tile_sweep(const Grid &g, const TileGeom &tg, co
 // MGM (multigrid, FP32 tiles, even z-ranges): 1 fuses the restriction of the
 // output into mf (y is not written), 2 the injection of mf's coarse correction
 // into the operand (see MgFuse).
+// Waves per SIMD the single-grid FP32 sweep is built for: 4, two workgroups per CU (<= 128 VGPRs).
+// The multigrid transfer and moving-medium forms spill a few registers at that size (the
+// injection form 18) and are still faster than at one workgroup per CU (measured at 256^3: 290
+// against 298 ms per multigrid step).  The two-level grid's sweep (two cells per thread) is left
+// to the compiler.
+template <class AT, bool AMR, bool VEL, int MGM>
+constexpr int apply_waves()
+{
+    return (sizeof(AT) == 4 && !AMR) ? 4 : 1;
+}
+
 template <class AT, class ST, bool PRE, bool AMR = false, bool VEL = false, bool LC = true, int WL = 0,
           int MGM = 0>
-__global__ void __launch_bounds__(tile_threads<AT>())
+__global__ void __launch_bounds__((tile_threads<AT, AMR>()), (apply_waves<AT, AMR, VEL, MGM>()))
     k_apply_tiled(Grid g, TileGeom tg, const ST *__restrict__ f, const AT *__restrict__ sR,
                   const ST *__restrict__ rho, const ST *__restrict__ kR, const AT *__restrict__ Cf,
                   const AT *__restrict__ dE, const AT *__restrict__ x, const double *__restrict__ xs,
@@ -637,9 +665,12 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                   AT qm = AT(0), AT qs = AT(1), AT *__restrict__ dout = nullptr, MgFuse<AT> mf = MgFuse<AT>{},
                   const AT *__restrict__ cw = nullptr)
 {
-    static_assert(MGM == 0 || (PRE && !AMR && !VEL && TileShape<AT>::CPT == 2), "multigrid fusion: FP32 Krylov apply");
+    static_assert(MGM == 0 || (PRE && !AMR && !VEL && sizeof(AT) == 4), "multigrid fusion: FP32 Krylov apply");
+    using TS = TileShape<AT, AMR>;   // the two-level grid keeps two cells per thread
+    constexpr int CPT = TS::CPT;
+    static_assert(CPT == 1 || CPT == 2, "a restriction y-pair is a thread's two cells or two rows");
     constexpr bool CS = PRE && LC;
-    __shared__ AT lds[2][Rec<CS>::NL][TileShape<AT>::LY][kLX];
+    __shared__ AT lds[2][Rec<CS>::NL][TS::LY][kLX];
     const long long N = g.N;
     const AT s = ((PRE && xs) ? (AT)(*xs) : AT(1)) * xm;
     const AT nu = (AT)g.nu, half = AT(0.5) * (AT)g.nu;
@@ -664,9 +695,45 @@ __global__ void __launch_bounds__(tile_threads<AT>())
             for (int q = 0; q < 3; ++q) e[4 + q] = ld_off(vc + q * N + pb, o);
         }
     };
-    // restriction: the children's D t summed per thread (its y-pair) over a z-pair, then over the
-    // x-pair of lanes; the parents' diagonal is loaded on the pair's first plane
+    // restriction: the children's D t summed over the x-pair of lanes (a shuffle), the y-pair of rows
+    // and a z-pair of planes.  Two cells per thread: the thread's own y-pair, summed in registers over
+    // the z-pair (the parents' diagonal loaded on the pair's first plane).  One cell per thread (each
+    // row a wave): no state in registers across planes -- every plane's x-pair sums go to LDS, and at
+    // the start of the next plane (after the barrier that ends every plane) or after the range, 128
+    // threads add each row pair, keep the z-pair's first half in LDS and store the parents on its
+    // second (6 KB of LDS: two workgroups still share a CU).
     AT racc[4] = {AT(0), AT(0), AT(0), AT(0)}, rDc[2] = {AT(1), AT(1)};
+    constexpr bool RL = MGM == 1 && CPT == 1;
+    constexpr int RY = TS::TYT / 2, RX = kTX / 2;
+    __shared__ std::conditional_t<RL, AT[2 * RY][RX][4], AT[1][1][1]> rsh;
+    __shared__ std::conditional_t<RL, AT[RY][RX][4], AT[1][1][1]> rz;
+    int rbx = 0, rby = 0, rbz = 0;
+    if constexpr (RL) tile_coords(tg, rbx, rby, rbz);
+    // plane kd's sums (in rsh): the first plane of a z-pair is kept, the second completes the parents
+    auto rfold = [&](int kd) __attribute__((always_inline)) {
+        if constexpr (RL) {
+            const int t = (int)threadIdx.x;
+            if (t < RY * RX) {
+                const int r = t / RX, xp = t % RX;
+                AT v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = rsh[2 * r][xp][q] + rsh[2 * r + 1][xp][q];
+                if (!(kd & 1)) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) rz[r][xp][q] = v[q];
+                } else {
+                    const int gx = rbx * kTX + 2 * xp, gy = rby * TS::TY + 2 * r;
+                    if (gx < g.nx && gy < g.ny) {
+                        const long long pc = (long long)(kd >> 1) * mf.ncx * mf.ncy + (gx >> 1) +
+                                             (long long)mf.ncx * (gy >> 1);
+                        mf.qc[pc] = (rz[r][xp][0] + v[0]) * (AT(0.125) / mf.Dc[pc]);
+                        const AT iF = AT(0.125) / mf.Dc[mf.Nc + pc];
+                        for (int q = 1; q < 4; ++q) mf.qc[q * mf.Nc + pc] = (rz[r][xp][q] + v[q]) * iF;
+                    }
+                }
+            }
+        }
+    };
     auto epi = [&](int k, int c, unsigned o, bool active, const CellSums<AT> &S, const AT(&e)[NEX])
                    __attribute__((always_inline)) {
         const long long pb = (long long)g.nx * g.ny * k;
@@ -726,9 +793,17 @@ __global__ void __launch_bounds__(tile_threads<AT>())
                 DEr += nu * S.wE;
                 DFr += nu * (S.wF[0] + S.wF[1] + S.wF[2]) * AT(1.0 / 3.0);
             }
-            racc[0] += DEr * yE;
-            for (int q = 0; q < 3; ++q) racc[1 + q] += DFr * yFq[q];
-            if (c == 1) {   // the thread's y-pair is in
+            if constexpr (RL) {   // this plane's x-pair sums into LDS, one row of the tile per wave
+                AT v[4] = {DEr * yE, DFr * yFq[0], DFr * yFq[1], DFr * yFq[2]};
+                for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], 1);
+                const int lx = (int)(threadIdx.x % kTX), ly = (int)(threadIdx.x / kTX);
+                if (!(lx & 1))
+                    for (int q = 0; q < 4; ++q) rsh[ly][lx >> 1][q] = v[q];
+            } else {
+                racc[0] += DEr * yE;
+                for (int q = 0; q < 3; ++q) racc[1 + q] += DFr * yFq[q];
+            }
+            if (!RL && c == 1) {   // two cells per thread: the thread's y-pair is in
                 const unsigned gxo = o % (unsigned)g.nx, gyo = o / (unsigned)g.nx;
                 const long long pc = (long long)(k >> 1) * mf.ncx * mf.ncy + (gxo >> 1) + (long long)mf.ncx * (gyo >> 1);
                 if (!(k & 1)) {   // first plane of the z-pair: the parents' diagonal
@@ -755,8 +830,15 @@ __global__ void __launch_bounds__(tile_threads<AT>())
         const AT z3[3] = {AT(0), AT(0), AT(0)};
         wall_ghost<AT>(kind, d, side, Ec, Fc, fcr, AT(0), z3, AT(0), En, Fn, fnr);
     };
-    tile_sweep<AT, ST, PRE, false, NEX, CS, WL, MGM == 2>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex, epi,
-                                                         wall, mf, cw);
+    // the previous plane's restriction sums: at the start of each plane but the range's first, and
+    // after the range (the sweep ends with a barrier)
+    auto beg = [&](int k) __attribute__((always_inline)) {
+        if constexpr (RL)
+            if (k > rbz * tg.kz) rfold(k - 1);
+    };
+    tile_sweep<AT, ST, PRE, false, NEX, CS, WL, MGM == 2, AMR>(g, tg, f, sR, rho, kR, Cf, x, s, s * xF, lds, lex,
+                                                              epi, wall, mf, cw, beg);
+    if constexpr (RL) rfold(min(rbz * tg.kz + tg.kz, g.nz) - 1);
 }
 
 // Low-face corrected speeds (divided by c) of every cell, once per step, in

@@ -1207,19 +1207,20 @@ int run_step(Solver &S)
                 constexpr bool AM = decltype(amr_c)::value, VL = decltype(vel_c)::value, LC = decltype(lc_c)::value;
                 constexpr int WLc = decltype(wl_c)::value;
                 constexpr int MG = decltype(mg_c)::value;
+                const dim3 bta(tile_threads<AT, AM>());   // the two-level grid's sweep shape
                 // not built: walls on the two-level grid, fused transfers outside the plain FP32 apply,
                 // Dirichlet faces with the face speeds formed per face
                 if constexpr (!(AM && WLc) && (MG == 0 || (!AM && !VL && std::is_same<AT, float>::value)) &&
                               !(WLc == 2 && !LC)) {
                     if (fA)
-                        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bt, 0,
+                        hipLaunchKernelGGL((k_apply_tiled<AT, AT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bta, 0,
                                            S.st, S.gl[l], tg[l], (const AT *)fA + 6 * o, sR + o, (const AT *)nullptr,
                                            (const AT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                            y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)),
                                            (const AT *)VBA, (const AT *)VCA, pg, xm, qv, qm, qs, dout, mf,
                                            (const AT *)CwA);
                     else
-                        hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bt, 0,
+                        hipLaunchKernelGGL((k_apply_tiled<AT, CT, true, AM, VL, LC, WLc, MG>), tiles(tg[l]), bta, 0,
                                            S.st, S.gl[l], tg[l], f + 6 * o, sR + o, (const CT *)nullptr,
                                            (const CT *)nullptr, (const AT *)Cf + 3 * o, dEA + o, x + 4 * o, xs,
                                            y + 4 * o, AT(1), AT(1), level_view(l, corrA, sizeof(AT)),
