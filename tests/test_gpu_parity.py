@@ -181,8 +181,12 @@ def test_step_matches_oracle(torch, rad, kind, shape, seed, prec, poly):
 
 
 # grids whose extents halve at least once (the multigrid operator's levels, x y z: 20 -> 10 -> 5,
-# 16x8x32 -> 8x4x16, 16^3 -> 8^3 -> 4^3)
-MG_CASES = [("periodic", (20, 20, 20), 4), ("outflow", (32, 8, 16), 6), ("clumpy", (16, 16, 16), 7)]
+# 16x8x32 -> 8x4x16, 16^3 -> 8^3 -> 4^3, 40x12x16 -> 20x6x8).  20^3 takes 5-plane z-ranges and the
+# separate transfer kernels; the others even z-ranges and the transfers fused into the sweeps, the last
+# with tiles ragged along x (40 of 64 columns) and y (the second tile's 4 of 8 rows), so that the
+# restriction's row pairs straddle the inactive rows.
+MG_CASES = [("periodic", (20, 20, 20), 4), ("outflow", (32, 8, 16), 6), ("clumpy", (16, 16, 16), 7),
+            ("open", (16, 12, 40), 8)]
 
 
 @pytest.mark.parametrize("kind,shape,seed", MG_CASES)
