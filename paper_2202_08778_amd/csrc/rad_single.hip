@@ -1120,7 +1120,7 @@ int run_step(Solver &S)
     TileGeom tg[2], tgr[2];
     for (int l = 0; l < NL; ++l) {
         tg[l] = tile_geom<AT>(S.gl[l], S.kz_apply);
-        tgr[l] = tile_geom<double>(S.gl[l], S.kz_res, 128, 256);
+        tgr[l] = tile_geom<double>(S.gl[l], S.kz_res, 32, 256);
     }
     auto tiles = [](const TileGeom &t) { return dim3((unsigned)(t.tiles_x * t.tiles_y * t.tiles_z)); };
     const dim3 bt(tile_threads<AT>()), bt64(tile_threads<double>());
