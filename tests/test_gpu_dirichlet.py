@@ -4,8 +4,9 @@ Against the oracle on padded inputs whose Dirichlet ghosts hold the data and who
 coefficients are the boundary cells' own (the library's reading): face speeds, the linear operator
 (ghosts without data), the nonlinear residual (ghosts with data), and steps per field (<= 1e-10
 FP64, <= 1e-8 mixed), with ragged tiles along every axis and Dirichlet faces beside every other
-kind; the multigrid operator.  Also the steady anisotropic diffusion profile of a linear E with a
-constant flux, a closed form the scheme holds exactly for any dt, and the relaxation onto it."""
+kind; the multigrid operator; the moving medium; the allocation-free entry point.  Also the steady
+anisotropic diffusion profile of a linear E with a constant flux, a closed form the scheme holds exactly
+for any dt, and the relaxation onto it."""
 import ctypes as ct
 import sys
 
@@ -327,3 +328,60 @@ def test_dirichlet_ghost_data_is_required(torch, rad):
     with pytest.raises(ValueError, match="ghost"):
         rad.rad_step(g(d["E"]), g(d["F"]), g(d["T"]), g(d["rho"]), g(d["kP"]), g(d["kR"]), g(d["f"]), d["dt"], d["dx"],
                      d["bc"], _params(rad, d), ghost=gh)
+
+
+@pytest.mark.parametrize("implicit", [False, True], ids=["explicit", "implicit"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dirichlet_moving_medium_matches_oracle(torch, rad, prec, implicit):
+    """rad_step_moving with Dirichlet faces beside an open one: the O(v/c) terms are local to the cell and the
+    ghosts enter as in rad_step.  The clumpy medium at 100 crossings with a smooth flow (|beta| <= 0.05): no
+    cell reaches the T >= 0 bound, where T is ill-conditioned in E; two x tiles with a ragged tail."""
+    shape, seed, bmax = (6, 9, 70), 1, 0.05
+    bc = ["dirichlet", "open", "periodic", "periodic", "dirichlet", "dirichlet"]
+    _say("dirichlet moving", prec, implicit)
+    d = W.periodic_clumpy(shape=shape, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    d["F"] = 0.1 * rng.standard_normal((3,) + shape) * d["E"]
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny, (np.arange(nx) + 0.5) / nx,
+                          indexing="ij")
+    u = rng.standard_normal(3)
+    u /= np.linalg.norm(u)
+    d["beta"] = np.stack([0.5 * bmax * (u[q] + np.sin(2 * np.pi * (x + y + z) + q)) for q in range(3)])
+    if prec == "mixed":
+        for k in ("E", "F", "T", "rho", "kP", "kR", "f", "beta"):
+            d[k] = W._f32(d[k])
+    d["bc"] = bc
+    Ep, Fp = _with_ghosts(rng, _pad(d["E"]), _pad(d["F"], 1), bc, d["c"])
+    d["ghost"] = _ghost_data(Ep, Fp, bc)
+    P = oracle.Problem(_pad(d["rho"]), _pad(d["kP"]), _pad(d["kR"]), _pad(d["f"], 1), d["dt"], d["dx"], bc,
+                       c=d["c"], aR=d["aR"], cv=d["cv"], finc=FINC, padded=True, beta=_pad(d["beta"], 1),
+                       vel_implicit=implicit)
+    E1, F1, T1, _ = P.step(Ep, Fp, _pad(d["T"]), tol=1e-14)
+    ref = (E1[INNER], F1[(slice(None),) + INNER], T1[INNER])
+    cd = torch.float32 if prec == "mixed" else torch.float64
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    st = rad.rad_step_moving(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd),
+                             g(d["beta"], cd), d["dt"], d["dx"], bc,
+                             _params(rad, d, prec=prec, tol=1e-13, vel_implicit=int(implicit)),
+                             ghost=_ghost_dev(torch, d))
+    _say("  stats", st)
+    errs = [_relerr(E.cpu().numpy(), ref[0]), _relerr(F.cpu().numpy(), ref[1]), _relerr(T.cpu().numpy(), ref[2])]
+    _say("  relerr E F T", ["%.2e" % e for e in errs])
+    assert max(errs) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), errs
+
+
+def test_dirichlet_noalloc_matches_rad_step(torch, rad):
+    """The allocation-free entry point takes the ghost data through the same parameters: its step equals
+    rad_step's on the same inputs (the same kernels and reductions)."""
+    d = _case((9, 10, 12), 5, ["dirichlet"] * 6, 50.0)
+    g = lambda a: _dev(torch, a)
+    outs = []
+    for call in (rad.rad_step, rad.rad_step_noalloc):
+        E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+        call(E, F, T, g(d["rho"]), g(d["kP"]), g(d["kR"]), g(d["f"]), d["dt"], d["dx"], d["bc"],
+             _params(rad, d, tol=1e-13), ghost=_ghost_dev(torch, d))
+        outs.append([t.cpu().numpy() for t in (E, F, T)])
+    for a, b in zip(*outs):
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
