@@ -283,7 +283,8 @@ int rad_autotune_step(int nx, int ny, int nz, double *E, double *F, double *T_ga
 
 /* Nonlinear residual of the backward-Euler system at a state (E, F, T) given
  * the old state (E_n, F_n, T_n): R holds 5 planes [R_E | R_Fx | R_Fy | R_Fz | R_T]
- * (FP64, device).  Stream-ordered, asynchronous. */
+ * (FP64, device).  Faces as in rad_step, Dirichlet faces with their data from
+ * params->ghost.  Stream-ordered, asynchronous. */
 int rad_residual(int nx, int ny, int nz, const double *E_n, const double *F_n, const double *T_n,
                  const double *E, const double *F, const double *T,
                  const void *rho, const void *kappa_P, const void *kappa_R, const void *f_ij,
@@ -291,15 +292,18 @@ int rad_residual(int nx, int ny, int nz, const double *E_n, const double *F_n, c
 
 /* Corrected HLLE wave speed of every low face (Sec. 2.3.3): Cd[i] is the speed
  * of the face between cell i - e_d and cell i (three FP64 planes Cx|Cy|Cz);
- * the neighbour across a domain face follows bc (outflow: the cell itself).
- * Stream-ordered, asynchronous. */
+ * the neighbour across a domain face follows bc (periodic: the opposite cell;
+ * every other kind: the cell itself, whose coefficients a wall's or Dirichlet
+ * ghost takes).  Stream-ordered, asynchronous. */
 int rad_face_speeds(int nx, int ny, int nz, const void *rho, const void *kappa_R, const void *f_ij,
                     double dx, const int bc[6], const rad_params_t *p, double *C, void *stream);
 
 /* Linear transport operator of one Picard iteration applied to x = (E, Fx, Fy, Fz):
  *   y_E = dE * E + (dt/h) div PhiE,  y_Fj = (1 + sR) F_j + (dt/h) div PhiF_j.
  * x, y: four planes; dE: one plane.  dtype RAD_F64 or RAD_F32 selects the
- * element type of x, y, dE and the arithmetic.  Stream-ordered, asynchronous. */
+ * element type of x, y, dE and the arithmetic.  Faces as in rad_step with
+ * their data dropped (a Dirichlet ghost is zero; params->ghost is not read).
+ * Stream-ordered, asynchronous. */
 int rad_apply(int nx, int ny, int nz, const void *x, void *y, const void *dE,
               const void *rho, const void *kappa_R, const void *f_ij,
               double dt, double dx, const int bc[6], const rad_params_t *p, int dtype, void *stream);
