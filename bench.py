@@ -143,7 +143,8 @@ def bench_batched(args, torch, np, rad, W, steps=None, warmup=None, emit=True):
     batch = W.batched_blocks(nblocks=1024, seed=4)
     descs, ar = rad.pack_blocks(batch["blocks"])
     cells = sum(b["n"] ** 3 for b in batch["blocks"])
-    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1, krylov_poly=1 if args.krylov_poly == 2 else args.krylov_poly)
+    p = rad.params(prec="mixed", tol=args.tol, coef_dtype=1, krylov_poly=1 if args.krylov_poly == 2 else args.krylov_poly,
+                   eps_R=args.eps_r)
     # GMRES(48): the stiff blocks that GMRES(12) leaves unconverged although the oracle solves them converge
     p.gmres_m = args.gmres_m if (args.gmres_m is not None and args.batched) else 48
     g = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt).cuda()
@@ -178,7 +179,7 @@ def bench_batched(args, torch, np, rad, W, steps=None, warmup=None, emit=True):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "1024 Dirichlet blocks, edges uniform on {8,12,16,24,32}, dt 1..1000 crossings, "
                                   "kappa 1e-2..1e3 per block, one persistent graph-replayed launch per step",
-                      "cells": cells, "gmres_m": p.gmres_m, "krylov_poly": p.krylov_poly,
+                      "cells": cells, "gmres_m": p.gmres_m, "krylov_poly": p.krylov_poly, "eps_R": p.eps_R,
                       "queue": ("longest measured solve first (warm-up step's block times)"
                                 if warmup > 0 and args.reorder else "largest block first"),
                       "launch": dict(zip(("threads", "per_cu", "largest_first"), plan.launch_shape()))},
@@ -346,8 +347,9 @@ def main():
                          "with --batched: the launch shape")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--eps-r", type=float, default=3e-2,
-                    help="relative tolerance of each linear solve of the single-grid legs (default 3e-2, the "
-                         "fastest of 0.005..0.1 on the 256^3 and 512^3 workloads; the library's default 1e-2)")
+                    help="relative tolerance of each linear solve, single-grid and batched legs (default 3e-2, "
+                         "the fastest of 0.005..0.1 on the 256^3, 512^3 and 1024-block workloads; the library's "
+                         "default 1e-2)")
     ap.add_argument("--krylov-poly", type=int, choices=(0, 1, 2), default=None,
                     help="Krylov operator: the Jacobi-scaled B times 1: the Neumann polynomial 2I - B (the library's "
                          "default), 0: nothing, 2: a multigrid V-cycle (default here on the uniform grids; the "

@@ -67,13 +67,15 @@ def _relerr(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1, poly=1, m=None):
+def _run(torch, rad, batch, prec, tol=1e-13, autotune=False, reps=1, poly=1, m=None, eps_R=None):
     descs, ar = rad.pack_blocks(batch["blocks"])
     c32 = prec == "mixed"
     p = rad.params(c=batch["c"], a_R=batch["aR"], c_v=batch["cv"], prec=prec, tol=tol,
                    coef_dtype=1 if c32 else 0, krylov_poly=poly)
     if m is not None:
         p.gmres_m = m
+    if eps_R is not None:
+        p.eps_R = eps_R
     dev = _upload(torch, ar, c32)
     plan = rad.Plan(descs, p)
     if autotune:
@@ -166,16 +168,18 @@ def test_reorder_by_measured_times_keeps_results(torch, rad):
         assert np.array_equal(s0[k], s1[k])
 
 
-def test_full_batch_1024_blocks(torch, rad):
-    """1024 blocks with edges 8..32, dt 1..1000 crossings, kappa 1e-2..1e3, mixed precision, GMRES(48):
+@pytest.mark.parametrize("eps_R", [1e-2, 3e-2], ids=["eps_R-1e-2", "eps_R-3e-2"])
+def test_full_batch_1024_blocks(torch, rad, eps_R):
+    """1024 blocks with edges 8..32, dt 1..1000 crossings, kappa 1e-2..1e3, mixed precision, GMRES(48), linear
+    solves to the library's default relative reduction and to the bench's (3e-2):
     every block converges except those on which the FP64 oracle fails too (the linearised Picard
     iteration cycles there, with cells of E < 0 held at the T >= 0 bound; recorded by
     tests/golden/make_batched_flagged.py, which ran the oracle with GMRES(64), tight inner solves and 50
     Picard iterations on every block GMRES(12) leaves unconverged); sampled blocks match the oracle
     (small ones exactly to 1e-8, the largest through the oracle's residual)."""
-    _say("batched full 1024")
+    _say("batched full 1024", eps_R)
     batch = W.batched_blocks(nblocks=1024, seed=4)
-    descs, outs, stats = _run(torch, rad, batch, "mixed", tol=1e-10, m=48)
+    descs, outs, stats = _run(torch, rad, batch, "mixed", tol=1e-10, m=48, eps_R=eps_R)
     st = stats[0]
     _say("  status counts", np.unique(st["status"], return_counts=True))
     _say("  krylov per block: mean %.1f max %d" % (st["krylov_iters"].mean(), st["krylov_iters"].max()))
