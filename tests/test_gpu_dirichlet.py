@@ -4,7 +4,8 @@ Against the oracle on padded inputs whose Dirichlet ghosts hold the data and who
 coefficients are the boundary cells' own (the library's reading): face speeds, the linear operator
 (ghosts without data), the nonlinear residual (ghosts with data), and steps per field (<= 1e-10
 FP64, <= 1e-8 mixed), with ragged tiles along every axis and Dirichlet faces beside every other
-kind; the multigrid operator; the moving medium; the allocation-free entry point.  Also the steady
+kind; the multigrid operator; the moving medium; both Picard forms with and without the energy
+correction; the cubic heat capacity; the allocation-free entry point.  Also the steady
 anisotropic diffusion profile of a linear E with a constant flux, a closed form the scheme holds exactly
 for any dt, and the relaxation onto it."""
 import ctypes as ct
@@ -385,3 +386,65 @@ def test_dirichlet_noalloc_matches_rad_step(torch, rad):
         outs.append([t.cpu().numpy() for t in (E, F, T)])
     for a, b in zip(*outs):
         assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+def _clumpy_dirichlet(shape, seed, f32=False, dt_scale=1.0):
+    """The clumpy medium (no cell reaches the T >= 0 bound) inside six Dirichlet faces."""
+    d = W.periodic_clumpy(shape=shape, seed=seed)
+    d["dt"] *= dt_scale
+    if f32:
+        for k in ("E", "F", "T", "rho", "kP", "kR", "f"):
+            d[k] = W._f32(d[k])
+    d["bc"] = ["dirichlet"] * 6
+    rng = np.random.default_rng(seed + 3)
+    d["Ep"], d["Fp"] = _with_ghosts(rng, _pad(d["E"]), _pad(d["F"], 1), d["bc"], d["c"])
+    d["Tp"] = _pad(d["T"])
+    d["ghost"] = _ghost_data(d["Ep"], d["Fp"], d["bc"])
+    return d
+
+
+@pytest.mark.parametrize("mode", ["lagged", "linearised"])
+@pytest.mark.parametrize("fix", [False, True], ids=["nofix", "energy_fix"])
+def test_dirichlet_three_picard_iterations_match_oracle(torch, rad, mode, fix):
+    """Exactly three Picard iterations with tight linear solves inside Dirichlet faces, both Picard forms, with
+    and without the energy correction of Sec. 2.3.4: the iterates and the energy mismatch follow the oracle's."""
+    _say("dirichlet three iterations", mode, fix)
+    d = _clumpy_dirichlet((8, 7, 9), 31, dt_scale=0.1)
+    P = oracle.Problem(_pad(d["rho"]), _pad(d["kP"]), _pad(d["kR"]), _pad(d["f"], 1), d["dt"], d["dx"], d["bc"],
+                       c=d["c"], aR=d["aR"], cv=d["cv"], padded=True)
+    E1, F1, T1, ref_st = P.step(d["Ep"], d["Fp"], d["Tp"], mode=mode, max_picard=3, lin_rtol=1e-14, energy_fix=fix,
+                                allow_unconverged=True)
+    g = lambda a: _dev(torch, a)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    st = rad.rad_step(E, F, T, g(d["rho"]), g(d["kP"]), g(d["kR"]), g(d["f"]), d["dt"], d["dx"], d["bc"],
+                      _params(rad, d, mode=mode, max_picard=3, eps_R=1e-13, tol=1e-30, energy_fix=int(fix),
+                              gmres_m=30), check=False, ghost=_ghost_dev(torch, d))
+    _say("  gpu", st, "oracle", ref_st)
+    assert st["picard_iters"] == 3 and ref_st["picard_iters"] == 3
+    errs = [_relerr(E.cpu().numpy(), E1[INNER]), _relerr(F.cpu().numpy(), F1[(slice(None),) + INNER]),
+            _relerr(T.cpu().numpy(), T1[INNER])]
+    _say("  relerr E F T", ["%.2e" % e for e in errs])
+    assert max(errs) <= FP64_TOL
+    assert abs(st["energy_defect"] - ref_st["energy_defect"]) <= 1e-6 * abs(ref_st["energy_defect"]) + 1e-14
+    assert abs(st["dE_max"] - ref_st["dE_max"]) <= 1e-6 * ref_st["dE_max"] + 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dirichlet_cubic_gas_matches_oracle(torch, rad, prec):
+    """The C_v = alpha T^3 gas of the Marshak-wave test inside Dirichlet faces, converged steps."""
+    _say("dirichlet cubic gas", prec)
+    d = _clumpy_dirichlet((6, 9, 12), 21, f32=prec == "mixed")
+    P = oracle.Problem(_pad(d["rho"]), _pad(d["kP"]), _pad(d["kR"]), _pad(d["f"], 1), d["dt"], d["dx"], d["bc"],
+                       c=d["c"], aR=d["aR"], cv=d["cv"], padded=True, cv_cubic=True)
+    E1, F1, T1, _ = P.step(d["Ep"], d["Fp"], d["Tp"], tol=1e-14)
+    cd = torch.float32 if prec == "mixed" else torch.float64
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    st = rad.rad_step(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd), d["dt"], d["dx"],
+                      d["bc"], _params(rad, d, prec=prec, tol=1e-13, cv_cubic=1, max_picard=5000),
+                      ghost=_ghost_dev(torch, d))
+    _say("  stats", st)
+    errs = [_relerr(E.cpu().numpy(), E1[INNER]), _relerr(F.cpu().numpy(), F1[(slice(None),) + INNER]),
+            _relerr(T.cpu().numpy(), T1[INNER])]
+    _say("  relerr E F T", ["%.2e" % e for e in errs])
+    assert max(errs) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), errs
