@@ -5,7 +5,7 @@ coefficients are the boundary cells' own (the library's reading): face speeds, t
 (ghosts without data), the nonlinear residual (ghosts with data), and steps per field (<= 1e-10
 FP64, <= 1e-8 mixed), with ragged tiles along every axis and Dirichlet faces beside every other
 kind; the multigrid operator; the moving medium; both Picard forms with and without the energy
-correction; the cubic heat capacity; the allocation-free entry point.  Also the steady
+correction; the cubic heat capacity; the allocation-free entry point; the autotuner.  Also the steady
 anisotropic diffusion profile of a linear E with a constant flux, a closed form the scheme holds exactly
 for any dt, and the relaxation onto it."""
 import ctypes as ct
@@ -448,3 +448,31 @@ def test_dirichlet_cubic_gas_matches_oracle(torch, rad, prec):
             _relerr(T.cpu().numpy(), T1[INNER])]
     _say("  relerr E F T", ["%.2e" % e for e in errs])
     assert max(errs) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), errs
+
+
+def test_dirichlet_autotune_then_step(torch, rad, tmp_path, monkeypatch):
+    """rad_autotune_step with Dirichlet faces (its trial steps run every z-range on the Dirichlet sweep, with
+    and without the high wall's speeds staged in LDS) leaves the state unchanged; the step with the tuned
+    tiles matches the oracle."""
+    monkeypatch.setenv("VETTAM_RAD_CACHE_DIR", str(tmp_path))
+    bc = ["open", "dirichlet", "periodic", "periodic", "dirichlet", "dirichlet"]
+    d = _case((40, 20, 24), 17, bc, 50.0)
+    g = lambda a: _dev(torch, a)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    coef = [g(d[k]) for k in ("rho", "kP", "kR", "f")]
+    gh = _ghost_dev(torch, d)
+    p = _params(rad, d, gmres_m=16, tol=1e-12)
+    out = rad.autotune_step(E, F, T, *coef, d["dt"], d["dx"], bc, p, tune_restart=True, ghost=gh)
+    _say("autotune", out)
+    for t, a in zip((E, F, T), (d["E"], d["F"], d["T"])):
+        assert np.array_equal(t.cpu().numpy(), a)
+    p.gmres_m = out["gmres_m"]
+    p.krylov_poly = out["krylov_poly"]
+    p.tol = 1e-13
+    st = rad.rad_step(E, F, T, *coef, d["dt"], d["dx"], bc, p, ghost=gh)
+    _say("  stats", st)
+    E1, F1, T1, _ = _oracle_problem(d).step(d["Ep"], d["Fp"], d["Tp"], tol=1e-14)
+    errs = [_relerr(E.cpu().numpy(), E1[INNER]), _relerr(F.cpu().numpy(), F1[(slice(None),) + INNER]),
+            _relerr(T.cpu().numpy(), T1[INNER])]
+    _say("  relerr E F T", ["%.2e" % e for e in errs])
+    assert max(errs) <= FP64_TOL, errs
