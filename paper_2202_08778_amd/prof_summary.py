@@ -5,13 +5,16 @@
           (counter_collection CSVs), each scaled by what the same counter reads for the run's plain
           device copies of 256 MiB (bench.py --copy-calibration), grouped into the library's kernel
           classes; also a JSON record that bench.py reads for its roofline's traffic, tied to the
-          kernel sources by their hash.
+          kernel sources by their hash;
+  insts:  instruction counts per dispatch and per cell of the fine-grid stencil kernels from one SQ counter
+          pass (counter_collection CSV), with the VALU issue floor at one wave-instruction per clock per CU.
 
 Kernels are told apart by name and grid size; an apply sweep whose grid is smaller than the largest
 one is a multigrid coarse level.
 
   python -m paper_2202_08778_amd.prof_summary trace TRACE_CSV OUT_MD --cmd CMD --title TITLE
   python -m paper_2202_08778_amd.prof_summary hbm FETCH_CSV WRITE_CSV OUT_MD OUT_JSON --n N --cmds CMD...
+  python -m paper_2202_08778_amd.prof_summary insts PMC_CSV OUT_MD --cells CELLS --cmd CMD --title TITLE
 """
 import argparse
 import collections
@@ -130,6 +133,39 @@ def hbm(args):
     json.dump(rec, open(args.out_json, "w"), indent=1)
 
 
+def insts(args):
+    """Per fine-grid stencil kernel (the largest grid of k_apply_tiled, and k_residual_tiled at that grid):
+    the mean over dispatches of each device-wide SQ counter, and per cell: the count x 64 / cells, i.e. the
+    instructions of the wave that holds the cell (one cell per lane)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    ids = collections.defaultdict(set)
+    rows = list(csv.DictReader(open(args.csv)))
+    fine = max(grid_of(r) for r in rows if short_name(r["Kernel_Name"]).startswith("k_apply_tiled"))
+    for r in rows:
+        k, g = short_name(r["Kernel_Name"]), grid_of(r)
+        if g != fine or not k.startswith(("k_apply_tiled", "k_residual_tiled")):
+            continue
+        per[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        ids[k].add(r["Dispatch_Id"])
+    names = ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")
+    lines = [f"# {args.title}: instruction counters", "", "Command (repository root):", "", f"    {args.cmd}", "",
+             f"Per dispatch: the mean over the run's dispatches of each fine-grid kernel ({fine} threads) of the "
+             "counter summed over the device.  Per cell: that count x 64 / "
+             f"{args.cells} cells (the instructions of the wave that holds the cell, one cell per lane).  VALU "
+             f"floor: the VALU count / ({args.cus} CUs x 1 wave-instruction per clock x {args.ghz} GHz), four "
+             "16-lane SIMDs per CU taking 4 clocks per wave64 instruction.", "",
+             "| kernel | dispatches | waves | VALU / dispatch | VALU / cell | LDS / cell | SALU / cell | VMEM rd / cell | "
+             "VMEM wr / cell | VALU floor us |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(per, key=lambda k: -per[k]["SQ_INSTS_VALU"] / len(ids[k])):
+        n = len(ids[k])
+        m = {c: per[k][c] / n for c in per[k]}
+        pc = [f"{m.get(c, 0.0) * 64 / args.cells:.1f}" for c in names]
+        floor = m.get("SQ_INSTS_VALU", 0.0) / (args.cus * args.ghz * 1e9) * 1e6
+        lines.append(f"| {k} | {n} | {m.get('SQ_WAVES', 0):.0f} | {m.get('SQ_INSTS_VALU', 0):.4g} | " + " | ".join(pc) +
+                     f" | {floor:.1f} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -147,8 +183,16 @@ def main():
     h.add_argument("--n", type=int, required=True)
     h.add_argument("--title", required=True)
     h.add_argument("--cmds", nargs="+", required=True)
+    i = sub.add_parser("insts")
+    i.add_argument("csv")
+    i.add_argument("out")
+    i.add_argument("--cells", type=int, required=True)
+    i.add_argument("--cmd", required=True)
+    i.add_argument("--title", required=True)
+    i.add_argument("--cus", type=int, default=256)
+    i.add_argument("--ghz", type=float, default=2.4)
     args = ap.parse_args()
-    trace(args) if args.mode == "trace" else hbm(args)
+    {"trace": trace, "hbm": hbm, "insts": insts}[args.mode](args)
 
 
 if __name__ == "__main__":
