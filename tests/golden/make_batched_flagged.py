@@ -1,4 +1,4 @@
-"""Writes batched_1024_flagged.json: the FP64 oracle's own verdict on the blocks of the 1024-block
+"""Writes batched_1024_flagged.json: the FP64 oracle's own outcome on the blocks of the 1024-block
 batched workload (seed 4) that the batched GPU path leaves unconverged at GMRES(12).
 
 Each block is solved alone by the oracle with its Dirichlet ghost data, in the linearised Picard
