@@ -248,14 +248,15 @@ def test_multi_step_mixed_depth_128_properties(torch, rad):
         assert res[3] <= 1.5e-10
 
 
-@pytest.mark.parametrize("poly", [1, 2], ids=["neumann", "multigrid"])
-def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad, poly):
-    """The 256^3 precision workload (FP32-exact inputs, m = 8) with either Krylov operator, the multigrid
-    one being the bench's configuration: one mixed step and one FP64 step from the same state agree within
-    1e-8 per field, and the mixed output meets the oracle's residual definition at the requested tolerance
-    (an implicit step has no per-cell output the oracle could compute alone; its residual is the per-cell
-    check)."""
-    _say(f"full size 256^3, krylov_poly {poly}")
+@pytest.mark.parametrize("poly, eps_R", [(1, 1e-2), (2, 1e-2), (2, 3e-2)],
+                         ids=["neumann", "multigrid", "multigrid-eps3e-2"])
+def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad, poly, eps_R):
+    """The 256^3 precision workload (FP32-exact inputs, m = 8) with either Krylov operator; the multigrid
+    one with linear solves to 3e-2 is the bench's configuration: one mixed step and one FP64 step from the
+    same state agree within 1e-8 per field, and the mixed output meets the oracle's residual definition at
+    the requested tolerance (an implicit step has no per-cell output the oracle could compute alone; its
+    residual is the per-cell check)."""
+    _say(f"full size 256^3, krylov_poly {poly}, eps_R {eps_R}")
     d = W.mixed_depth_256(n=256, steps=1)
     P = _oracle_problem(d)
     g = lambda a, dt=None: _dev(torch, a, dt)
@@ -264,7 +265,7 @@ def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad, poly):
         cd = torch.float32 if prec == "mixed" else torch.float64
         E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
         p = _params(rad, d, prec=prec, tol=1e-10, gmres_m=8, coef_dtype=1 if prec == "mixed" else 0,
-                    krylov_poly=poly)
+                    krylov_poly=poly, eps_R=eps_R)
         st = rad.rad_step(E, F, T, g(d["rho"], cd), g(d["kP"], cd), g(d["kR"], cd), g(d["f"], cd), d["dt"],
                           d["dx"], d["bc"], p)
         _say(f"  {prec}: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, res {st['scaled_residual']:.2e}")
