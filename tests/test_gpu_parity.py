@@ -277,3 +277,25 @@ def test_full_size_256_mixed_against_fp64_and_oracle_residual(torch, rad, poly, 
     res = P.scaled_residual(d["E"], d["F"], d["T"], *outs["mixed"])
     _say("  oracle scaled residual of the mixed step", res)
     assert res[3] <= 1.5e-10
+
+
+def test_full_size_512_scale_step_meets_oracle_residual(torch, rad):
+    """The 512^3 scale workload (lognormal sigma 2, optical depth 1e-4..1e4, dt = 200 crossings, FP32-exact
+    inputs) in the bench's configuration: mixed precision, GMRES(8) on the multigrid operator, linear solves
+    to 3e-2, tol 1e-10.  One step converges, and its output meets the oracle's residual definition at the
+    requested tolerance."""
+    _say("full size 512^3 scale workload, mixed, multigrid, eps_R 3e-2")
+    d = W.mixed_depth_512(n=512, steps=1)
+    g = lambda a, dt=None: _dev(torch, a, dt)
+    E, F, T = g(d["E"]), g(d["F"]), g(d["T"])
+    p = _params(rad, d, prec="mixed", tol=1e-10, gmres_m=8, coef_dtype=1, krylov_poly=2, eps_R=3e-2)
+    coefs = [g(d[k], torch.float32) for k in ("rho", "kP", "kR", "f")]
+    st = rad.rad_step(E, F, T, *coefs, d["dt"], d["dx"], d["bc"], p)
+    _say(f"  mixed: {st['picard_iters']} Picard, {st['krylov_iters']} Krylov, res {st['scaled_residual']:.2e}")
+    assert st["rc"] == 0
+    out = (E.cpu().numpy(), F.cpu().numpy(), T.cpu().numpy())
+    del E, F, T, coefs
+    torch.cuda.empty_cache()
+    res = _oracle_problem(d).scaled_residual(d["E"], d["F"], d["T"], *out)
+    _say("  oracle scaled residual of the mixed step", res)
+    assert res[3] <= 1.5e-10
